@@ -1,0 +1,195 @@
+/*
+ * simdx.h — C ABI of libsimdx.so, an MI355X (gfx950) implementation of the
+ * Active-Compute-Combine (ACC) graph-processing method of
+ * "SIMD-X: Programming and Processing of Graph Algorithms on GPUs"
+ * (Liu and Huang, arXiv 1812.04070).
+ *
+ * The problem statement the calls follow (Section 2.1): a graph G = (V, E, w)
+ * with vertex metadata ("the distance array") is computed on iteratively,
+ * from a source until no vertex is updated.  An algorithm is the triple
+ * Active / Compute / Combine of Section 3.2; this library ships four of them
+ * (BFS, SSSP, k-core, PageRank, Section 6) and a program selects one.
+ *
+ * Conventions shared by every call
+ *  - Every call returns sx_status; SX_OK is 0, errors are negative.  Output
+ *    parameters are written only on SX_OK.  Nothing aborts and no C++
+ *    exception crosses the ABI.  sx_last_error() returns a thread-local text
+ *    describing the last failure on the calling thread.
+ *  - Opaque objects (sx_ctx, sx_graph, sx_program) are created and freed by
+ *    the library.  Destroy graphs and programs before their context.
+ *  - A hip_stream argument is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls that read results back synchronise that stream.
+ *  - Integer layouts: vertex ids int32, CSR offsets int32 (so m < 2^31),
+ *    edge weights uint32.  Vertex arrays have n elements.
+ *  - One context serves one HIP device; calls on one context from several
+ *    host threads at once are not supported.
+ */
+#ifndef SIMDX_H
+#define SIMDX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SX_OK = 0,
+  SX_EINVAL = -1,        /* bad argument: see sx_last_error()                  */
+  SX_ENOMEM = -2,        /* device or host allocation failed                   */
+  SX_EHIP = -3,          /* a HIP runtime call failed (text in sx_last_error) */
+  SX_EUNSUPPORTED = -4,  /* combination not supported (e.g. device lacks it)   */
+  SX_EDEADLOCK = -5,     /* grid-barrier watchdog fired: workgroups were not
+                            all resident (Section 5, deadlock of the software
+                            global barrier); engine state undefined, the graph
+                            stays valid                                        */
+  SX_EOVERFLOW = -6,     /* an SSSP distance reached 0xFFFFFFFF              */
+  SX_ESTATE = -7         /* call made in the wrong state                       */
+} sx_status;
+
+typedef struct sx_ctx sx_ctx;
+typedef struct sx_graph sx_graph;
+typedef struct sx_program sx_program;
+
+/* Create a context on HIP device `hip_device` (its ordinal).  Queries the
+ * device (compute units, cooperative-launch support) once. */
+sx_status sx_ctx_create(int hip_device, sx_ctx **out);
+void sx_ctx_destroy(sx_ctx *ctx);
+const char *sx_status_str(sx_status s);
+const char *sx_last_error(void);
+
+/* ------------------------------------------------------------- graphs --- */
+/* Storage format (Section 6, "Storage Format"): CSR of out-neighbours; an
+ * undirected graph stores both arcs of every edge (symmetric CSR) and needs
+ * no in-neighbour structure; a directed graph adds the CSR of in-neighbours
+ * (CSC) for pull processing. */
+enum {
+  SX_UNDIRECTED = 1u,    /* CSR is symmetric; in_* must be NULL               */
+  SX_DEVICE_PTRS = 2u,   /* pointers are device memory: borrowed, not copied;
+                            the caller keeps them alive until destroy          */
+  SX_VALIDATE = 4u       /* check offsets monotone and ids in range (host)    */
+};
+
+typedef struct {
+  int32_t n;                 /* vertices                                       */
+  int64_t m;                 /* arcs (entries of indices); must be < 2^31      */
+  const int32_t *offsets;    /* [n+1], offsets[0] = 0, offsets[n] = m          */
+  const int32_t *indices;    /* [m] out-neighbours, rows sorted ascending      */
+  const uint32_t *weights;   /* [m] arc weights, > 0; NULL if unweighted       */
+  const int32_t *in_offsets; /* [n+1] CSC; NULL for undirected graphs          */
+  const int32_t *in_indices; /* [m] in-neighbours                              */
+  const uint32_t *in_weights;/* [m] or NULL                                    */
+  uint32_t flags;            /* SX_UNDIRECTED | SX_DEVICE_PTRS | SX_VALIDATE   */
+} sx_graph_desc;
+
+/* Make the graph resident on the device (host arrays are copied; the caller
+ * may free them on return) and allocate the per-graph engine workspace
+ * (frontier queues, bitmaps, control block: about 40 bytes per vertex).
+ * Errors: SX_EINVAL (n < 0, m out of range, missing arrays, a directed graph
+ * without CSC, validation failure), SX_ENOMEM, SX_EHIP. */
+sx_status sx_graph_load(sx_ctx *ctx, const sx_graph_desc *desc, void *hip_stream, sx_graph **out);
+void sx_graph_destroy(sx_graph *g);
+sx_status sx_graph_info(const sx_graph *g, int32_t *n, int64_t *m, int32_t *directed, int32_t *weighted);
+
+/* ----------------------------------------------------------- programs --- */
+/* The four ACC programs (Section 3.2 for the Active/Compute/Combine triple,
+ * Section 6 for the algorithms):
+ *  SX_BFS      active = newly visited; compute = level + 1; combine = vote
+ *              (any one update suffices).  Output int32 depth, -1 unreached.
+ *  SX_SSSP     active = distance lowered in the last iteration; compute =
+ *              dist(v) + w(v,u); combine = minimum (aggregation).  Output
+ *              uint32 distance, 0xFFFFFFFF unreached.
+ *  SX_KCORE    active = alive with degree <= level; compute = remove v and
+ *              lower the neighbour's degree; combine = sum.  Extended from
+ *              the paper's fixed-k membership to the full decomposition:
+ *              output int32 core number (v is in the k-core iff core >= k).
+ *              Degree counts in- plus out-arcs for a directed graph.
+ *  SX_PAGERANK all vertices active; compute = rank(u)/outdeg(u); combine =
+ *              sum; pr_iters synchronous iterations with damping pr_damping,
+ *              uniform start 1/n, rank of vertices without out-arcs spread
+ *              uniformly.  Output float rank (FP32 arithmetic). */
+typedef enum { SX_BFS = 0, SX_SSSP = 1, SX_KCORE = 2, SX_PAGERANK = 3 } sx_algo;
+
+typedef struct {
+  sx_algo algo;
+  float pr_damping;      /* PageRank damping d (0.85)                          */
+  int32_t pr_iters;      /* PageRank iterations (20)                           */
+} sx_algo_params;
+
+sx_status sx_program_register(sx_ctx *ctx, const sx_algo_params *params, sx_program **out);
+void sx_program_destroy(sx_program *p);
+
+/* Per-iteration choices (Sections 4 and 5).  Each field 0 = automatic.
+ *  direction  SX_DIR_AUTO | SX_DIR_PUSH | SX_DIR_PULL
+ *  filter     SX_FILTER_JIT (online filter, ballot filter on overflow) |
+ *             SX_FILTER_ONLINE (never overflow: capacity = n) |
+ *             SX_FILTER_BALLOT (always rebuild the worklist by ballot scan)
+ *  bin_small  degree below which one lane takes a vertex (default 64)
+ *  bin_large  degree from which a workgroup takes chunks of a vertex (256)
+ *  online_cap online-filter capacity in entries per wavefront of the grid
+ *             (default 64, the paper's overflow threshold)
+ *  fused      SX_FUSED (persistent kernels + global barrier, Section 5) |
+ *             SX_UNFUSED (one launch per phase and iteration) | 0 = auto
+ *  policy     SX_POLICY_HEURISTIC | SX_POLICY_LEARNED (MLP; needs
+ *             sx_policy_load_mlp first)                                       */
+enum { SX_DIR_AUTO = 0, SX_DIR_PUSH = 1, SX_DIR_PULL = 2 };
+enum { SX_FILTER_JIT = 0, SX_FILTER_ONLINE = 1, SX_FILTER_BALLOT = 2 };
+enum { SX_FUSE_AUTO = 0, SX_FUSED = 1, SX_UNFUSED = 2 };
+enum { SX_POLICY_HEURISTIC = 0, SX_POLICY_LEARNED = 1 };
+
+typedef struct {
+  int32_t direction;
+  int32_t filter;
+  int32_t bin_small;
+  int32_t bin_large;
+  int32_t online_cap;
+  int32_t fused;
+  int32_t policy;
+  int32_t grid_wgs;      /* persistent grid size; 0 = occupancy x CUs (Eq. 1) */
+} sx_policy;
+
+sx_status sx_program_set_policy(sx_program *p, const sx_policy *pol);
+
+/* ---------------------------------------------------------------- run --- */
+typedef struct {
+  int32_t iterations;        /* BSP iterations (levels / rounds / sweeps)     */
+  int32_t launches;          /* kernel launches issued for the run            */
+  int32_t pull_iters;        /* iterations processed in pull direction        */
+  int32_t ballot_iters;      /* iterations whose worklist came from the ballot
+                                filter                                         */
+  int64_t edges_inspected;   /* arcs read by compute                          */
+  int64_t vertex_expansions; /* worklist entries processed                    */
+  double device_ms;          /* stream time of the run (HIP events)           */
+} sx_run_stats;
+
+/* Run program p on graph g.  source: start vertex (BFS, SSSP), ignored (pass
+ * -1) for k-core and PageRank.  d_out: caller-owned device array of n
+ * elements (int32 depth | uint32 dist | int32 core | float rank).  Blocks the
+ * host until the run is complete.  stats may be NULL.
+ * Errors: SX_EINVAL (source out of range, SSSP on an unweighted graph, wrong
+ * d_out), SX_EDEADLOCK, SX_EOVERFLOW, SX_EHIP. */
+sx_status sx_run(sx_program *p, const sx_graph *g, int32_t source, void *d_out,
+                 void *hip_stream, sx_run_stats *stats);
+
+/* Copy a vertex array (n elements of the algorithm's output type) from the
+ * device to host memory; synchronises the stream. */
+sx_status sx_read_vertices(const sx_graph *g, sx_algo algo, const void *d_out, void *host_out,
+                           void *hip_stream);
+
+/* Library/build facts for the measurement harness: kernel register use and
+ * persistent-grid sizing (the Eq. 1 analogue).  name: "bfs_push", ... */
+typedef struct {
+  int32_t vgprs, sgprs, lds_bytes, block, wgs_per_cu, grid_wgs, cus;
+} sx_kernel_info;
+sx_status sx_kernel_info_get(sx_ctx *ctx, const char *name, sx_kernel_info *out);
+
+/* Eq. 1 of Section 5: number of co-resident workgroups from a per-SM register
+ * budget, registers per thread and threads per workgroup:
+ *   floor(regs_per_sm / (regs_per_thread * threads_per_wg)) * sms.
+ * Pure host arithmetic; returns -1 on non-positive input. */
+int32_t sx_eq1_ctas(int32_t regs_per_sm, int32_t regs_per_thread, int32_t threads_per_wg, int32_t sms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIMDX_H */

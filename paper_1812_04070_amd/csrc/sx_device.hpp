@@ -1,0 +1,180 @@
+// Device primitives of the ACC engine for CDNA4 (gfx950, wave64).
+//
+//  - wavefront ballot / popcount / lane-prefix (mbcnt) helpers, used by both
+//    task-management filters of Section 4: the online filter appends active
+//    vertices with one atomic per wavefront, the ballot filter turns a
+//    coalesced scan of vertex metadata into 64-bit ballot words;
+//  - workgroup reductions through LDS;
+//  - the software global barrier that holds the persistent fused kernels of
+//    Section 5 together, with a watchdog so that a grid that is not fully
+//    resident reports an error instead of hanging.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sx_types.hpp"
+
+#define SX_AG __HIP_MEMORY_SCOPE_AGENT
+#define SX_DEV __device__ __forceinline__
+
+namespace sx {
+
+// ------------------------------------------------------------ wavefront ---
+SX_DEV int lane_id() { return __lane_id(); }
+SX_DEV int wave_in_wg() { return threadIdx.x >> 6; }
+
+SX_DEV uint64_t ballot(bool p) { return __ballot(p); }
+
+// number of set bits of `mask` in lanes below this lane
+SX_DEV unsigned lane_prefix(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+SX_DEV int wave_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+SX_DEV long long wave_sum_ll(long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+SX_DEV unsigned wave_min_u(unsigned v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) { unsigned t = __shfl_xor(v, o); v = t < v ? t : v; }
+  return v;
+}
+// inclusive prefix sum over the wavefront
+SX_DEV int wave_incl_scan(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------- atomics -------
+SX_DEV unsigned atomic_add_u32(unsigned *p, unsigned v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, SX_AG);
+}
+SX_DEV unsigned long long atomic_add_u64(unsigned long long *p, unsigned long long v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, SX_AG);
+}
+SX_DEV unsigned atomic_min_u32(unsigned *p, unsigned v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, SX_AG);
+}
+SX_DEV int atomic_sub_i32(int *p, int v) {
+  return __hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, SX_AG);
+}
+SX_DEV bool atomic_cas_i32(int *p, int expected, int desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, SX_AG);
+}
+SX_DEV int atomic_exch_i32(int *p, int v) {
+  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, SX_AG);
+}
+SX_DEV unsigned long long atomic_or_u64(unsigned long long *p, unsigned long long v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, SX_AG);
+}
+template <class T>
+SX_DEV T load_relaxed(const T *p) {
+  return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, SX_AG);
+}
+template <class T>
+SX_DEV void store_relaxed(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, SX_AG);
+}
+
+// ------------------------------------------------------- workgroup -------
+// Sum of one int per thread over the workgroup; every thread gets the total.
+// `red` must hold kBlock/64 ints of LDS.
+template <int kBlock>
+SX_DEV long long wg_sum_ll(long long v, long long *red) {
+  v = wave_sum_ll(v);
+  if (lane_id() == 0) red[wave_in_wg()] = v;
+  __syncthreads();
+  long long t = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+// ---------------------------------------------------- global barrier ------
+// Lock-array barrier (Section 5: every workgroup writes its own status word;
+// one monitor workgroup waits for all of them and then releases everybody).
+// Deadlock freedom comes from launching no more workgroups than can be
+// resident at once (the Eq. 1 analogue, computed from the occupancy API on
+// the host).  Each wait loop has a watchdog: when the spin budget runs out
+// it raises ctrl->error = SX_ERR_DEADLOCK and every workgroup leaves the
+// kernel at its next check.
+//
+// Arrival is a plain release store to a private 128-byte line, so arrivals
+// never serialise on one address; the monitor's threads poll the flags in
+// parallel.  gen is the barrier generation, kept per workgroup in a register
+// and identical in all workgroups.
+struct GridBarrier {
+  Ctrl *c;
+  unsigned nblk;
+  unsigned gen;
+
+  SX_DEV GridBarrier(Ctrl *ctrl, unsigned start_gen)
+      : c(ctrl), nblk(gridDim.x), gen(start_gen) {}
+
+  SX_DEV bool failed() const { return load_relaxed(&c->error.v[0]) != 0u; }
+
+  // returns false when the watchdog fired (this or another workgroup)
+  SX_DEV bool sync() {
+    const unsigned target = gen + 1;
+    __syncthreads();
+    bool ok = true;
+    if (blockIdx.x == 0) {
+      for (unsigned b = 1 + threadIdx.x; b < nblk; b += blockDim.x) {
+        unsigned spins = 0;
+        while (load_relaxed(&c->flags[b].v[0]) != target) {
+          __builtin_amdgcn_s_sleep(2);
+          if (failed()) { ok = false; break; }
+          if (++spins > kSpinLimit) {
+            store_relaxed(&c->error.v[0], (unsigned)SX_ERR_DEADLOCK);
+            ok = false;
+            break;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __syncthreads();
+      if (threadIdx.x == 0)
+        __hip_atomic_store(&c->bar_gen.v[0], target, __ATOMIC_RELEASE, SX_AG);
+    } else if (threadIdx.x == 0) {
+      __hip_atomic_store(&c->flags[blockIdx.x].v[0], target, __ATOMIC_RELEASE, SX_AG);
+      unsigned spins = 0;
+      while (load_relaxed(&c->bar_gen.v[0]) != target) {
+        __builtin_amdgcn_s_sleep(2);
+        if (failed()) break;
+        if (++spins > kSpinLimit) {
+          store_relaxed(&c->error.v[0], (unsigned)SX_ERR_DEADLOCK);
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    gen = target;
+    __syncthreads();
+    return ok && !failed();
+  }
+};
+
+// Start every run from barrier generation 0 (called by one workgroup of the
+// run's initialisation kernel, which completes before the persistent kernel
+// starts on the same stream).
+SX_DEV void reset_barrier(Ctrl *c) {
+  for (int b = threadIdx.x; b < kMaxGrid; b += blockDim.x) c->flags[b].v[0] = 0u;
+  if (threadIdx.x == 0) c->bar_gen.v[0] = 0u;
+}
+
+}  // namespace sx

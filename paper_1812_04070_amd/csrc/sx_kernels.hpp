@@ -1,0 +1,24 @@
+// Host-side entry points of the HIP kernels (launch helpers).
+#pragma once
+
+#include "sx_types.hpp"
+
+namespace sx {
+
+enum TravKernel {
+  TK_PUSH_FUSED, TK_PULL_FUSED, TK_PUSH_STEP, TK_BALLOT1, TK_BALLOT2,
+  TK_PULL_SCAN, TK_PULL_LISTS, TK_PULL_STEP, TK_COUNT
+};
+
+const void *trav_kernel(int kind, int sssp);
+hipError_t trav_launch(int kind, int sssp, const TravArgs &a, int it, int grid, hipStream_t s);
+hipError_t trav_init(const TravArgs &a, int sssp, unsigned long long mu0, hipStream_t s);
+hipError_t reset_slot(Ctrl *c, int slot, hipStream_t s);
+
+hipError_t kcore_launch(const KArgs &a, int grid, hipStream_t s, bool init);
+const void *kcore_kernel();
+
+hipError_t pagerank_launch(const PrArgs &a, int grid, hipStream_t s);
+const void *pagerank_kernel();
+
+}  // namespace sx

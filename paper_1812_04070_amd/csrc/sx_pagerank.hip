@@ -1,0 +1,214 @@
+// PageRank as an ACC program (Section 6, "PageRank": pull from the in-
+// neighbours with a sum as the merge operation), in FP32 for a fixed number
+// of synchronous iterations:
+//   x_0(v)     = 1/n
+//   x_{t+1}(v) = (1-d)/n + d * ( sum_{u->v} x_t(u)/outdeg(u) + D_t/n ),
+//   D_t        = sum of x_t over vertices without out-arcs.
+//
+//   Active   every vertex, every iteration.
+//   Compute  contribution x_t(u) / outdeg(u), stored per vertex once per
+//            iteration so that each arc costs one gather.
+//   Combine  sum over the in-arcs (aggregation), single writer per vertex.
+//
+// Task management: all vertices are active, so the binned lists are built by
+// one ballot-filter pass before the first iteration (the paper observes
+// PageRank needs the ballot filter exactly once) and reused.  Every sum --
+// per vertex over its in-arcs, and the dangling mass over vertices -- is a
+// compensated (TwoSum) FP32 summation in a fixed order, so the result is
+// reproducible bit for bit and its error stays near the rounding of the
+// stored FP32 values.  One persistent launch runs all iterations with one
+// global barrier each.
+#include "sx_frontier.hpp"
+#include "sx_kernels.hpp"
+
+namespace sx {
+
+
+struct CSum {
+  float s, c;
+};
+// Knuth's TwoSum: s + x = t + e exactly
+SX_DEV void cadd(CSum &a, float x) {
+  const float t = a.s + x;
+  const float z = t - a.s;
+  const float e = (a.s - (t - z)) + (x - z);
+  a.s = t;
+  a.c += e;
+}
+SX_DEV CSum cmerge(CSum a, CSum b) {
+  CSum r{a.s, a.c + b.c};
+  cadd(r, b.s);
+  return r;
+}
+SX_DEV CSum wave_merge(CSum a) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    CSum b{__shfl_xor(a.s, o), __shfl_xor(a.c, o)};
+    a = cmerge(a, b);
+  }
+  return a;
+}
+// fixed-order workgroup merge; result valid in every thread
+SX_DEV CSum wg_merge(CSum a, float *lds /* 2*kWaves */) {
+  a = wave_merge(a);
+  __syncthreads();
+  if (lane_id() == 0) {
+    lds[2 * wave_in_wg()] = a.s;
+    lds[2 * wave_in_wg() + 1] = a.c;
+  }
+  __syncthreads();
+  CSum r{lds[0], lds[1]};
+  for (int w = 1; w < kWaves; ++w) r = cmerge(r, CSum{lds[2 * w], lds[2 * w + 1]});
+  __syncthreads();
+  return r;
+}
+
+struct LdsPr {
+  unsigned cnt[kWaves * 8];
+  long long red[kWaves];
+  float f[2 * kWaves];
+};
+
+// Dangling mass D_t from the per-workgroup partials of iteration t.
+SX_DEV float dangling_total(const float *part, int nparts, float *lds) {
+  CSum a{0.f, 0.f};
+  for (int i = threadIdx.x; i < nparts; i += kBlock) a = cmerge(a, CSum{part[2 * i], part[2 * i + 1]});
+  a = wg_merge(a, lds);
+  return a.s + a.c;
+}
+
+// Binned vertex lists (by in-degree), built once.
+SX_DEV void pr_lists_pass1(const PrArgs &a, LdsPr &lds) {
+  Tiling T(a.g.n, gridDim.x * kWaves);
+  const int *io = a.g.in_off;
+  auto pred = [&](int v) { (void)v; return true; };
+  auto deg = [&](int v) { return io[v + 1] - io[v]; };
+  ballot_count(a.g.n, T, pred, deg, a.P, 0x7fffffff, a.w.bits, a.w.wavecnt, a.w.wgc, lds.cnt);
+}
+SX_DEV void pr_lists_pass2(const PrArgs &a, LdsPr &lds, unsigned tot_out[3]) {
+  Tiling T(a.g.n, gridDim.x * kWaves);
+  const int *io = a.g.in_off;
+  auto deg = [&](int v) { return io[v + 1] - io[v]; };
+  auto ident = [](int i) { return i; };
+  WgCount tot;
+  ballot_write(a.g.n, T, deg, ident, 0x7fffffff, a.w.bits, a.w.wavecnt, a.w.wgc, a.w.q[0][0],
+               a.w.q[0][1], a.w.ql[0], tot, lds.cnt, lds.red);
+  tot_out[0] = tot.cnt[0];
+  tot_out[1] = tot.cnt[1];
+  tot_out[2] = tot.cnt[2];
+}
+
+// One vertex's new value from its in-arc sum; returns the dangling share.
+SX_DEV void pr_finish_vertex(const PrArgs &a, int v, CSum s, float D, bool last, float *dst,
+                             CSum &dang) {
+  const float d = a.P.pr_d;
+  const float r = a.base_teleport + d * ((s.s + s.c) + D * a.inv_n);
+  const int od = a.g.off[v + 1] - a.g.off[v];
+  if (last) a.rank[v] = r;
+  else if (od > 0) dst[v] = r / (float)od;
+  if (od == 0) cadd(dang, r);
+}
+
+SX_DEV void pr_iteration(const PrArgs &a, int t, const unsigned cnt[3], LdsPr &lds) {
+  const Work &w = a.w;
+  const float *src = w.contrib[t & 1];
+  float *dst = w.contrib[(t + 1) & 1];
+  const float D = dangling_total(w.dang + (size_t)(t & 1) * 2 * kMaxGrid, gridDim.x, lds.f);
+  const bool last = t == a.iters - 1;
+  const int *io = a.g.in_off, *ii = a.g.in_idx;
+  const int lane = lane_id();
+  CSum dang{0.f, 0.f};
+  long long edges = 0;
+  // one workgroup per large vertex
+  for (unsigned i = blockIdx.x; i < cnt[2]; i += gridDim.x) {
+    const int v = (int)(w.ql[0][i] & 0xffffffffu);
+    const int beg = io[v], end = io[v + 1];
+    CSum s{0.f, 0.f};
+    for (int e = beg + (int)threadIdx.x; e < end; e += kBlock) { cadd(s, src[ii[e]]); ++edges; }
+    s = wg_merge(s, lds.f);
+    if (threadIdx.x == 0) pr_finish_vertex(a, v, s, D, last, dst, dang);
+  }
+  const unsigned gw = blockIdx.x * kWaves + wave_in_wg();
+  const unsigned nw = gridDim.x * kWaves;
+  // one wavefront per medium vertex
+  for (unsigned i = gw; i < cnt[1]; i += nw) {
+    const int v = w.q[0][1][i];
+    const int beg = io[v], end = io[v + 1];
+    CSum s{0.f, 0.f};
+    for (int e = beg + lane; e < end; e += 64) { cadd(s, src[ii[e]]); ++edges; }
+    s = wave_merge(s);
+    if (lane == 0) pr_finish_vertex(a, v, s, D, last, dst, dang);
+  }
+  // one lane per small vertex
+  for (unsigned i = gw * 64u + lane; i < cnt[0] + 0u; i += nw * 64u) {
+    const int v = w.q[0][0][i];
+    const int beg = io[v], end = io[v + 1];
+    CSum s{0.f, 0.f};
+    for (int e = beg; e < end; ++e) cadd(s, src[ii[e]]);
+    edges += end - beg;
+    pr_finish_vertex(a, v, s, D, last, dst, dang);
+  }
+  dang = wg_merge(dang, lds.f);
+  if (threadIdx.x == 0) {
+    float *part = w.dang + (size_t)((t + 1) & 1) * 2 * kMaxGrid;
+    part[2 * blockIdx.x] = dang.s;
+    part[2 * blockIdx.x + 1] = dang.c;
+  }
+  const long long e = wave_sum_ll(edges);
+  if (lane == 0 && e) atomic_add_u64((unsigned long long *)&w.ctrl->stats.v[0], (unsigned long long)e);
+}
+
+__global__ void __launch_bounds__(kBlock) k_pr_fused(PrArgs a) {
+  __shared__ LdsPr lds;
+  Ctrl *C = a.w.ctrl;
+  GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]));
+  pr_lists_pass1(a, lds);
+  if (!bar.sync()) return;
+  unsigned cnt[3];
+  pr_lists_pass2(a, lds, cnt);
+  if (!bar.sync()) return;
+  for (int t = 0; t < a.iters; ++t) {
+    pr_iteration(a, t, cnt, lds);
+    if (!bar.sync()) return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    store_relaxed(&C->state.v[0], (unsigned)EXIT_DONE);
+    store_relaxed(&C->stats.v[6], (unsigned)a.iters);
+    store_relaxed(&C->stats.v[4], 1u);
+  }
+}
+
+// x_0 = 1/n: contributions and the dangling partials of iteration 0 (same
+// grid as the persistent kernel, so partial i belongs to workgroup i).
+__global__ void __launch_bounds__(kBlock) k_pr_init(PrArgs a) {
+  __shared__ float lf[2 * kWaves];
+  const int n = a.g.n;
+  CSum dang{0.f, 0.f};
+  for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n;
+       v += (long long)gridDim.x * kBlock) {
+    const int od = a.g.off[v + 1] - a.g.off[v];
+    if (od > 0) a.w.contrib[0][v] = a.inv_n / (float)od;
+    else cadd(dang, a.inv_n);
+  }
+  dang = wg_merge(dang, lf);
+  if (threadIdx.x == 0) {
+    a.w.dang[2 * blockIdx.x] = dang.s;
+    a.w.dang[2 * blockIdx.x + 1] = dang.c;
+  }
+  if (blockIdx.x == 0) reset_barrier(a.w.ctrl);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctrl *C = a.w.ctrl;
+    for (int i = 0; i < 32; ++i) { C->state.v[i] = 0; C->stats.v[i] = 0; }
+    C->error.v[0] = 0;
+  }
+}
+
+hipError_t pagerank_launch(const PrArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_pr_init, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_pr_fused, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+const void *pagerank_kernel() { return (const void *)k_pr_fused; }
+
+}  // namespace sx

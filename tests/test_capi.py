@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every symbol include/simdx.h declares;
+host-only arithmetic (no GPU needed)."""
+from __future__ import annotations
+
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "simdx.h")
+LIB = os.path.join(ROOT, "paper_1812_04070_amd", "libsimdx.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sx_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for must in ["sx_ctx_create", "sx_graph_load", "sx_program_register", "sx_run",
+                 "sx_read_vertices", "sx_program_set_policy"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.skip("libsimdx.so not built")
+    out = subprocess.check_output(["nm", "-D", "--defined-only", LIB]).decode()
+    exported = set(re.findall(r" T (sx_[a-z0-9_]+)$", out, flags=re.M))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    import paper_1812_04070_amd as sx
+    assert sorted(sx.EXPORTED) == declared_functions()
+    for name in sx.EXPORTED:
+        assert hasattr(sx, name)
+
+
+def test_eq1_worked_example():
+    """Section 5, Eq. 1: 110 registers per thread, 128 threads per CTA, 65,536
+    registers per SMX and 15 SMX give 60 CTAs (4 per SMX; the text writes ceil
+    but its result is the floor)."""
+    if not os.path.exists(LIB):
+        pytest.skip("libsimdx.so not built")
+    import paper_1812_04070_amd as sx
+    assert sx.sx_eq1_ctas(65536, 110, 128, 15) == 60
+    assert sx.sx_eq1_ctas(65536, 48, 128, 15) == 150
+    assert sx.sx_eq1_ctas(0, 1, 1, 1) == -1
+
+
+def test_errors_without_device():
+    """With no HIP device the context call fails cleanly with SX_EHIP or SX_EINVAL."""
+    if not os.path.exists(LIB):
+        pytest.skip("libsimdx.so not built")
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("device present")
+    except Exception:
+        pass
+    import ctypes
+    import paper_1812_04070_amd as sx
+    h = ctypes.c_void_p()
+    rc = sx.lib().sx_ctx_create(0, ctypes.byref(h))
+    assert rc in (sx.SX_EHIP, sx.SX_EINVAL)
+    assert sx.lib().sx_last_error()
+    assert sx.lib().sx_status_str(sx.SX_EDEADLOCK)

@@ -1,0 +1,170 @@
+"""Parity of the HIP engine (through the C ABI) with the CPU oracle.
+
+BFS, SSSP and k-core are compared element by element and must be identical;
+PageRank (FP32) must be within 1e-6 relative L1 of the FP64 oracle.  Every
+policy arm (direction, filter, bins, fusion, grid size) must give the same
+integer output: the method's choices change the schedule, never the result.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1812_04070_amd as sx
+from paper_1812_04070_amd import gen
+from tests.gpu_util import ARMS, announce, rel_l1, run
+
+pytestmark = pytest.mark.gpu
+
+PR_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def engine():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    e = sx.Engine(0)
+    yield e
+    e.close()
+
+
+def _example():
+    edges = [(0, 1), (0, 3), (3, 2), (3, 4), (2, 1), (2, 5), (4, 5), (4, 6), (4, 7), (4, 8)]
+    w = [5, 1, 1, 2, 2, 3, 1, 2, 3, 4]
+    return gen.from_edges(9, edges, w, name="worked-example")
+
+
+SMALL_GRAPHS = [
+    ("worked-example", _example),
+    ("er-70", lambda: gen.random_graph(70, 0.08, seed=1, weights=(1, 64))),
+    ("er-130-dense", lambda: gen.random_graph(130, 0.3, seed=2, weights=(1, 9))),
+    ("rmat10", lambda: gen.rmat(10, seed=5, weights=(1, 64))),
+    ("rmat12", lambda: gen.rmat(12, seed=6, weights=(1, 64))),
+    ("grid-37", lambda: gen.grid(37, 0.1, seed=7, weights=(1, 1000))),
+    ("path-1000", lambda: gen.from_edges(1000, [(i, i + 1) for i in range(999)], [3] * 999)),
+    ("star-3000", lambda: gen.from_edges(3001, [(0, i) for i in range(1, 3001)], list(range(1, 3001)))),
+]
+
+
+@pytest.mark.parametrize("name,make", SMALL_GRAPHS, ids=[s[0] for s in SMALL_GRAPHS])
+@pytest.mark.parametrize("arm", ARMS, ids=[a[0] for a in ARMS])
+def test_bfs_sssp_small(engine, name, make, arm):
+    g = make()
+    src = gen.max_degree_vertex(g)
+    dg = engine.load(g)
+    announce(f"bfs {name} {arm[0]} src={src}")
+    d, st = run(engine, g, sx.SX_BFS, src, arm[1], dg=dg)
+    np.testing.assert_array_equal(d, oracle.bfs_g(g, src))
+    announce(f"sssp {name} {arm[0]} src={src}")
+    x, st = run(engine, g, sx.SX_SSSP, src, arm[1], dg=dg)
+    np.testing.assert_array_equal(x, oracle.sssp_g(g, src))
+    dg.close()
+
+
+@pytest.mark.parametrize("name,make", SMALL_GRAPHS, ids=[s[0] for s in SMALL_GRAPHS])
+def test_kcore_small(engine, name, make):
+    g = make()
+    for arm in ARMS[:3] + ARMS[7:]:
+        announce(f"kcore {name} {arm[0]}")
+        c, _ = run(engine, g, sx.SX_KCORE, -1, arm[1])
+        np.testing.assert_array_equal(c, oracle.kcore_g(g))
+
+
+def test_sources_and_isolated(engine):
+    g = gen.rmat(11, seed=3, weights=(1, 64))
+    dg = engine.load(g)
+    deg = g.out_degree()
+    iso = int(np.nonzero(deg == 0)[0][0])
+    for s in [0, iso, g.n - 1, int(np.argmin(np.where(deg > 0, deg, 10**9)))]:
+        announce(f"bfs/sssp rmat11 src={s}")
+        d, _ = run(engine, g, sx.SX_BFS, s, dg=dg)
+        np.testing.assert_array_equal(d, oracle.bfs_g(g, s))
+        x, _ = run(engine, g, sx.SX_SSSP, s, dg=dg)
+        np.testing.assert_array_equal(x, oracle.sssp_g(g, s))
+    dg.close()
+
+
+def test_degenerate_graphs(engine):
+    one = gen.from_edges(1, [], [])
+    one.weights = np.zeros(0, dtype=np.uint32)
+    announce("single vertex")
+    d, _ = run(engine, one, sx.SX_BFS, 0)
+    assert d.tolist() == [0]
+    x, _ = run(engine, one, sx.SX_SSSP, 0)
+    assert x.tolist() == [0]
+    c, _ = run(engine, one, sx.SX_KCORE)
+    assert c.tolist() == [0]
+    edgeless = gen.from_edges(100, [], directed=True)
+    announce("edgeless pagerank")
+    r, _ = run(engine, edgeless, sx.SX_PAGERANK)
+    np.testing.assert_allclose(r, np.full(100, 0.01), rtol=1e-6)
+
+
+def test_invalid_arguments(engine):
+    g = gen.rmat(8, seed=1, weights=(1, 4))
+    dg = engine.load(g)
+    with pytest.raises(sx.SxError) as e:
+        engine.run(dg, sx.SX_BFS, g.n)
+    assert e.value.status == sx.SX_EINVAL
+    with pytest.raises(sx.SxError) as e:
+        engine.run(dg, sx.SX_BFS, -1)
+    assert e.value.status == sx.SX_EINVAL
+    gu = gen.rmat(8, seed=1)
+    dgu = engine.load(gu)
+    with pytest.raises(sx.SxError) as e:
+        engine.run(dgu, sx.SX_SSSP, 0)
+    assert e.value.status == sx.SX_EINVAL
+    with pytest.raises(sx.SxError):
+        engine.run(dg, sx.SX_BFS, 0, sx.Policy(direction=7))
+    dg.close()
+    dgu.close()
+
+
+@pytest.mark.parametrize("scale", [10, 14])
+def test_pagerank_directed(engine, scale):
+    g = gen.rmat(scale, seed=4, directed=True)
+    announce(f"pagerank rmat{scale}d")
+    r, st = run(engine, g, sx.SX_PAGERANK)
+    ref = oracle.pagerank_g(g)
+    err = rel_l1(r, ref)
+    assert err <= PR_TOL, err
+    # deterministic: bitwise identical on a second run
+    r2, _ = run(engine, g, sx.SX_PAGERANK)
+    assert np.array_equal(r.view(np.uint32), r2.view(np.uint32))
+
+
+def test_pagerank_undirected_and_iters(engine):
+    g = gen.rmat(12, seed=8)
+    for iters in [1, 3, 20]:
+        announce(f"pagerank rmat12u iters={iters}")
+        r, _ = run(engine, g, sx.SX_PAGERANK, pr_iters=iters)
+        assert rel_l1(r, oracle.pagerank_g(g, 0.85, iters)) <= PR_TOL
+
+
+def test_kcore_directed(engine):
+    g = gen.rmat(13, seed=4, directed=True)
+    announce("kcore rmat13d")
+    c, _ = run(engine, g, sx.SX_KCORE)
+    np.testing.assert_array_equal(c, oracle.kcore_g(g))
+
+
+def test_rmat16_workload(engine):
+    """The s16 workload: BFS over every arm, SSSP and k-core."""
+    g = gen.workload_graph("rmat16")
+    src = gen.max_degree_vertex(g)
+    dg = engine.load(g)
+    ref_d = oracle.bfs_g(g, src)
+    ref_x = oracle.sssp_g(g, src)
+    for name, pol in ARMS:
+        announce(f"rmat16 bfs {name}")
+        d, st = run(engine, g, sx.SX_BFS, src, pol, dg=dg)
+        np.testing.assert_array_equal(d, ref_d)
+        announce(f"rmat16 sssp {name}")
+        x, st = run(engine, g, sx.SX_SSSP, src, pol, dg=dg)
+        np.testing.assert_array_equal(x, ref_x)
+    announce("rmat16 kcore")
+    c, _ = run(engine, g, sx.SX_KCORE, dg=dg)
+    np.testing.assert_array_equal(c, oracle.kcore_g(g))
+    dg.close()
