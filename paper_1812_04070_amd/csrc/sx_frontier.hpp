@@ -33,7 +33,9 @@ struct Lists {
 SX_DEV int bin_of(int deg, const Params &P) {
   return deg < P.t1 ? BIN_SMALL : (deg < P.t2 ? BIN_MED : BIN_LARGE);
 }
-SX_DEV int chunks_of(int deg, int chunk) { return (deg + chunk - 1) / chunk; }
+SX_DEV int chunks_of(int deg, int chunk) {
+  return (int)(((long long)deg + chunk - 1) / chunk);
+}
 
 // Per-wavefront statistics accumulated in registers and flushed once.
 struct WaveStats {

@@ -179,7 +179,7 @@ extern "C" sx_status sx_graph_load(sx_ctx *ctx, const sx_graph_desc *d, void *hi
   hipStream_t st = (hipStream_t)hip_stream;
   sx_graph *G = new sx_graph();
   G->ctx = ctx;
-  G->weighted = d->weights != nullptr;
+  G->weighted = d->weights != nullptr || d->m == 0;  // no arcs: trivially weighted
   G->directed = !undirected;
   const int n = d->n;
   const long long m = d->m;

@@ -130,8 +130,10 @@ SX_DEV void kpeel(const KArgs &a, int k, int qp, int slot, LdsK &lds) {
   const Work &w = a.w;
   Ctrl *C = w.ctrl;
   Counters *cur = &C->q[slot], *nxt = &C->q[(slot + 1) % 3];
-  const unsigned cs = load_relaxed(&cur->cnt[0]), cm = load_relaxed(&cur->cnt[1]),
-                 cl = load_relaxed(&cur->cnt[2]);
+  // counts are clamped to the list capacities: reads never leave the lists
+  const unsigned cs = min(load_relaxed(&cur->cnt[0]), w.qcap_small),
+                 cm = min(load_relaxed(&cur->cnt[1]), w.qcap_med),
+                 cl = min(load_relaxed(&cur->cnt[2]), w.qcap_large);
   const DevGraph &g = a.g;
   // mark the frontier deleted with core number k
   {

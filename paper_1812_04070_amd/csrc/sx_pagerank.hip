@@ -93,9 +93,9 @@ SX_DEV void pr_lists_pass2(const PrArgs &a, LdsPr &lds, unsigned tot_out[3]) {
   WgCount tot;
   ballot_write(a.g.n, T, deg, ident, 0x7fffffff, a.w.bits, a.w.wavecnt, a.w.wgc, a.w.q[0][0],
                a.w.q[0][1], a.w.ql[0], tot, lds.cnt, lds.red);
-  tot_out[0] = tot.cnt[0];
-  tot_out[1] = tot.cnt[1];
-  tot_out[2] = tot.cnt[2];
+  tot_out[0] = min(tot.cnt[0], a.w.qcap_small);
+  tot_out[1] = min(tot.cnt[1], a.w.qcap_med);
+  tot_out[2] = min(tot.cnt[2], a.w.qcap_large);
 }
 
 // One vertex's new value from its in-arc sum; returns the dangling share.

@@ -98,8 +98,10 @@ template <class Ops>
 SX_PHASE void push_phase(const TravArgs &a, const Ops &ops, int it, LdsTrav &lds) {
   Ctrl *C = a.w.ctrl;
   Counters *cur = &C->q[it % 3], *nxt = &C->q[(it + 1) % 3];
-  const unsigned cs = load_relaxed(&cur->cnt[0]), cm = load_relaxed(&cur->cnt[1]),
-                 cl = load_relaxed(&cur->cnt[2]);
+  // counts are clamped to the list capacities: reads never leave the lists
+  const unsigned cs = min(load_relaxed(&cur->cnt[0]), a.w.qcap_small),
+                 cm = min(load_relaxed(&cur->cnt[1]), a.w.qcap_med),
+                 cl = min(load_relaxed(&cur->cnt[2]), a.w.qcap_large);
   const int p = it & 1;
   Lists NL = lists_for(a.w, p ^ 1, nxt);
   NL.cap_s = online_cap(a.w, a.P, 0);
@@ -222,8 +224,10 @@ template <class Ops>
 SX_PHASE void pull_phase(const TravArgs &a, const Ops &ops, int it, LdsTrav &lds) {
   Ctrl *C = a.w.ctrl;
   Counters *cur = &C->q[it % 3], *nxt = &C->q[(it + 1) % 3];
-  const unsigned cs = load_relaxed(&cur->cnt[0]), cm = load_relaxed(&cur->cnt[1]),
-                 cl = load_relaxed(&cur->cnt[2]);
+  // counts are clamped to the list capacities: reads never leave the lists
+  const unsigned cs = min(load_relaxed(&cur->cnt[0]), a.w.qcap_small),
+                 cm = min(load_relaxed(&cur->cnt[1]), a.w.qcap_med),
+                 cl = min(load_relaxed(&cur->cnt[2]), a.w.qcap_large);
   const int p = it & 1;
   Lists NL = lists_for(a.w, p ^ 1, nxt);
   NL.cap_s = online_cap(a.w, a.P, 0);
