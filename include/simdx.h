@@ -176,12 +176,107 @@ sx_status sx_run(sx_program *p, const sx_graph *g, int32_t source, void *d_out,
 sx_status sx_read_vertices(const sx_graph *g, sx_algo algo, const void *d_out, void *host_out,
                            void *hip_stream);
 
+/* ------------------------------------------------------------ batches --- */
+/* Many BFS / SSSP queries over several graphs in one persistent launch (a
+ * project extension).  The grid is split into teams of team_wgs workgroups;
+ * each team takes queries from a shared queue (largest first) and runs each
+ * to completion with the same push/pull phases, filters and policy as sx_run,
+ * synchronised by a barrier over the team alone.  Results are identical to
+ * one sx_run per query.  Queries may share a graph; each needs its own d_out
+ * (device, n elements of the algorithm's output type). */
+typedef struct {
+  const sx_graph *g;
+  sx_algo algo;          /* SX_BFS or SX_SSSP                                */
+  int32_t source;
+  void *d_out;
+} sx_query;
+
+typedef struct {
+  int32_t team_wgs;      /* workgroups per team (1..64)                      */
+  int32_t bin_small;     /* bin thresholds (0 = policy / defaults)           */
+  int32_t bin_large;
+} sx_batch_config;
+
+/* Run the batch.  pol: direction/filter/policy as for sx_run (NULL =
+ * defaults); cfg NULL = the configuration last chosen by sx_batch_autotune
+ * for this context, else team_wgs 4.  per_query (nullable, nq entries)
+ * receives each query's counters; *batch_ms (nullable) the stream time.
+ * The team workspaces (about 30 bytes per vertex of the largest graph, per
+ * team) are kept in the context for reuse.
+ * Errors: SX_EINVAL (bad query, graph of another context), SX_ENOMEM,
+ * SX_EDEADLOCK, SX_EHIP. */
+sx_status sx_run_batch(sx_ctx *ctx, const sx_query *queries, int32_t nq, const sx_policy *pol,
+                       const sx_batch_config *cfg, void *hip_stream, sx_run_stats *per_query,
+                       double *batch_ms);
+
+/* Autotuner: times the batch under each candidate configuration (team sizes
+ * 1, 2, 4, 8, 16, 32 x bin thresholds (64,256), (32,1024)), keeps the fastest
+ * in the context for later sx_run_batch calls and returns it (and its time).
+ * The queries' outputs hold the result of the last candidate run. */
+sx_status sx_batch_autotune(sx_ctx *ctx, const sx_query *queries, int32_t nq, const sx_policy *pol,
+                            void *hip_stream, sx_batch_config *best, double *best_ms);
+
 /* Library/build facts for the measurement harness: kernel register use and
  * persistent-grid sizing (the Eq. 1 analogue).  name: "bfs_push", ... */
 typedef struct {
   int32_t vgprs, sgprs, lds_bytes, block, wgs_per_cu, grid_wgs, cus;
 } sx_kernel_info;
 sx_status sx_kernel_info_get(sx_ctx *ctx, const char *name, sx_kernel_info *out);
+
+/* ------------------------------------------------------ learned policy --- */
+/* A project extension, not in the paper: a small FP32 MLP, 8 frontier
+ * features -> 32 -> 32 -> 4 (ReLU), chooses each iteration's direction
+ * (output 0 > 0: pull), worklist filter (output 1 > 0: ballot) and bin
+ * thresholds (outputs 2, 3: log2 of the small/medium and medium/large degree
+ * thresholds).  Parameters are SX_MLP_NPARAMS floats: W1[32][8] row-major,
+ * b1[32], W2[32][32], b2[32], W3[4][32], b3[4].  The outputs never change a
+ * result, only the schedule.
+ * Features (float[8]) of the decision after an iteration: log2(1+nf)/24,
+ * log2(1+mf)/32, log2(1+mu)/32, nf/n, min(reached/n, 4)/4,
+ * (log2(1+nf) - log2(1+nf_prev))/8, log2(1+mf/nf)/16, pulling?1:0, where nf
+ * and mf are the next frontier's vertices and arcs, mu the unexplored arcs
+ * (BFS) or m (SSSP) and reached the vertices activated so far. */
+#define SX_MLP_NPARAMS 1476
+#define SX_MLP_FEATURES 8
+#define SX_MLP_OUTPUTS 4
+
+/* Copy host parameters into the context; programs with policy
+ * SX_POLICY_LEARNED use them from then on.  SX_EINVAL unless nparams ==
+ * SX_MLP_NPARAMS. */
+sx_status sx_policy_load_mlp(sx_ctx *ctx, const float *params, int64_t nparams);
+
+/* Batch inference: d_x device [n][8] -> d_y device [n][4]. */
+sx_status sx_mlp_forward(sx_ctx *ctx, const float *d_params, const float *d_x, int32_t n, float *d_y,
+                         void *hip_stream);
+
+/* Mean loss over n samples and its gradient (device pointers).  d_target and
+ * d_mask are [n][4]: outputs 0 and 1 take a binary cross-entropy on logits
+ * against 0/1 targets, outputs 2 and 3 half the squared error; mask entries
+ * (0 or 1) select the terms.  d_loss: device float[1]; d_grad: device
+ * float[SX_MLP_NPARAMS].  Sums run in sample order (deterministic). */
+sx_status sx_mlp_loss_grad(sx_ctx *ctx, const float *d_params, const float *d_x, const float *d_target,
+                           const float *d_mask, int32_t n, float *d_loss, float *d_grad,
+                           void *hip_stream);
+
+/* One Adam step (bias-corrected; step counts from 1) on device arrays of
+ * SX_MLP_NPARAMS floats. */
+sx_status sx_mlp_adam(sx_ctx *ctx, float *d_params, const float *d_grad, float *d_m, float *d_v,
+                      int32_t step, float lr, float beta1, float beta2, float eps, void *hip_stream);
+
+/* Timing records for training the policy.  Runs program p (BFS or SSSP) from
+ * `source` in one-phase mode under the heuristic policy and, before every
+ * `stride`-th iteration, times each of SX_POLICY_ARMS ways of running that
+ * iteration from the same saved state (the state is restored after each arm,
+ * so the run's result is unchanged).  Arms: 0 push on the online-filter lists
+ * (NaN when they overflowed), 1-4 push after a ballot-filter rebuild with bin
+ * thresholds (16,256) (64,256) (64,1024) (256,2048), 5 pull.  Writes up to
+ * max_records rows: features [8] (as for the learned policy, at the decision
+ * before the iteration) and arm_ms [6] (stream time of the arm).  *nrecords
+ * receives the row count.  Host arrays; the run's output lands in d_out. */
+#define SX_POLICY_ARMS 6
+sx_status sx_policy_collect(sx_program *p, const sx_graph *g, int32_t source, void *d_out,
+                            void *hip_stream, int32_t stride, float *features, float *arm_ms,
+                            int32_t max_records, int32_t *nrecords);
 
 /* Eq. 1 of Section 5: number of co-resident workgroups from a per-SM register
  * budget, registers per thread and threads per workgroup:

@@ -43,7 +43,12 @@ EXPORTED = [
     "sx_graph_load", "sx_graph_destroy", "sx_graph_info",
     "sx_program_register", "sx_program_destroy", "sx_program_set_policy",
     "sx_run", "sx_read_vertices", "sx_kernel_info_get", "sx_eq1_ctas",
+    "sx_policy_load_mlp", "sx_mlp_forward", "sx_mlp_loss_grad", "sx_mlp_adam",
+    "sx_policy_collect", "sx_run_batch", "sx_batch_autotune",
 ]
+SX_POLICY_ARMS = 6
+ARM_THRESHOLDS = [None, (16, 256), (64, 256), (64, 1024), (256, 2048), None]
+SX_MLP_NPARAMS = 1476
 
 
 class sx_graph_desc(ctypes.Structure):
@@ -73,6 +78,15 @@ class sx_run_stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class sx_query(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("algo", ctypes.c_int), ("source", ctypes.c_int32),
+                ("d_out", ctypes.c_void_p)]
+
+
+class sx_batch_config(ctypes.Structure):
+    _fields_ = [("team_wgs", ctypes.c_int32), ("bin_small", ctypes.c_int32), ("bin_large", ctypes.c_int32)]
 
 
 class sx_kernel_info(ctypes.Structure):
@@ -109,6 +123,17 @@ def lib() -> ctypes.CDLL:
         "sx_read_vertices": ([vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "sx_kernel_info_get": ([vp, ctypes.c_char_p, P(sx_kernel_info)], ctypes.c_int),
         "sx_eq1_ctas": ([ctypes.c_int32] * 4, ctypes.c_int32),
+        "sx_policy_load_mlp": ([vp, vp, ctypes.c_int64], ctypes.c_int),
+        "sx_mlp_forward": ([vp, vp, vp, ctypes.c_int32, vp, vp], ctypes.c_int),
+        "sx_mlp_loss_grad": ([vp, vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp], ctypes.c_int),
+        "sx_mlp_adam": ([vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                         ctypes.c_float, ctypes.c_float, vp], ctypes.c_int),
+        "sx_policy_collect": ([vp, vp, ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp, ctypes.c_int32,
+                               P(ctypes.c_int32)], ctypes.c_int),
+        "sx_run_batch": ([vp, P(sx_query), ctypes.c_int32, P(sx_policy), P(sx_batch_config), vp,
+                          P(sx_run_stats), P(ctypes.c_double)], ctypes.c_int),
+        "sx_batch_autotune": ([vp, P(sx_query), ctypes.c_int32, P(sx_policy), vp, P(sx_batch_config),
+                               P(ctypes.c_double)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -207,6 +232,65 @@ def sx_kernel_info_get(ctx, name: str) -> dict:
 
 def sx_eq1_ctas(regs_per_sm: int, regs_per_thread: int, threads_per_wg: int, sms: int) -> int:
     return int(lib().sx_eq1_ctas(regs_per_sm, regs_per_thread, threads_per_wg, sms))
+
+
+def sx_policy_load_mlp(ctx, params: np.ndarray) -> None:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    check(lib().sx_policy_load_mlp(ctx, p.ctypes.data_as(ctypes.c_void_p), p.size), "sx_policy_load_mlp")
+
+
+def sx_mlp_forward(ctx, d_params: int, d_x: int, n: int, d_y: int, stream: int = 0) -> None:
+    check(lib().sx_mlp_forward(ctx, ctypes.c_void_p(d_params), ctypes.c_void_p(d_x), n,
+                               ctypes.c_void_p(d_y), ctypes.c_void_p(stream)), "sx_mlp_forward")
+
+
+def sx_mlp_loss_grad(ctx, d_params: int, d_x: int, d_t: int, d_mask: int, n: int, d_loss: int,
+                     d_grad: int, stream: int = 0) -> None:
+    check(lib().sx_mlp_loss_grad(ctx, *[ctypes.c_void_p(v) for v in (d_params, d_x, d_t, d_mask)], n,
+                                 ctypes.c_void_p(d_loss), ctypes.c_void_p(d_grad), ctypes.c_void_p(stream)),
+          "sx_mlp_loss_grad")
+
+
+def sx_mlp_adam(ctx, d_params: int, d_grad: int, d_m: int, d_v: int, step: int, lr: float = 1e-3,
+                beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream: int = 0) -> None:
+    check(lib().sx_mlp_adam(ctx, *[ctypes.c_void_p(v) for v in (d_params, d_grad, d_m, d_v)], step, lr,
+                            beta1, beta2, eps, ctypes.c_void_p(stream)), "sx_mlp_adam")
+
+
+def sx_policy_collect(p, g, source: int, d_out_ptr: int, stream: int = 0, stride: int = 1,
+                      max_records: int = 4096):
+    """Per-iteration arm timings for policy training: returns (features [r, 8], arm_ms [r, 6])."""
+    feats = np.zeros((max_records, 8), dtype=np.float32)
+    arms = np.zeros((max_records, SX_POLICY_ARMS), dtype=np.float32)
+    nrec = ctypes.c_int32(0)
+    check(lib().sx_policy_collect(p, g, source, ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream), stride,
+                                  feats.ctypes.data_as(ctypes.c_void_p), arms.ctypes.data_as(ctypes.c_void_p),
+                                  max_records, ctypes.byref(nrec)), "sx_policy_collect")
+    return feats[:nrec.value].copy(), arms[:nrec.value].copy()
+
+
+def sx_run_batch(ctx, queries, pol=None, cfg=None, stream: int = 0):
+    """queries: list of (graph handle, algo, source, d_out pointer).  Returns
+    (batch_ms, [per-query stats dicts])."""
+    nq = len(queries)
+    arr = (sx_query * max(nq, 1))(*[sx_query(g, a, s, o) for g, a, s, o in queries])
+    stats = (sx_run_stats * max(nq, 1))()
+    ms = ctypes.c_double(0.0)
+    check(lib().sx_run_batch(ctx, arr, nq, ctypes.byref(pol) if pol is not None else None,
+                             ctypes.byref(cfg) if cfg is not None else None, ctypes.c_void_p(stream),
+                             stats, ctypes.byref(ms)), "sx_run_batch")
+    return ms.value, [stats[i].as_dict() for i in range(nq)]
+
+
+def sx_batch_autotune(ctx, queries, pol=None, stream: int = 0):
+    nq = len(queries)
+    arr = (sx_query * max(nq, 1))(*[sx_query(g, a, s, o) for g, a, s, o in queries])
+    best = sx_batch_config()
+    ms = ctypes.c_double(0.0)
+    check(lib().sx_batch_autotune(ctx, arr, nq, ctypes.byref(pol) if pol is not None else None,
+                                  ctypes.c_void_p(stream), ctypes.byref(best), ctypes.byref(ms)),
+          "sx_batch_autotune")
+    return {"team_wgs": best.team_wgs, "bin_small": best.bin_small, "bin_large": best.bin_large}, ms.value
 
 
 # ---------------------------------------------------------------------------

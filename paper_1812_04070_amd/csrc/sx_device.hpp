@@ -105,6 +105,14 @@ SX_DEV long long wg_sum_ll(long long v, long long *red) {
   return t;
 }
 
+// A (virtual) grid: workgroup `bid` of `nb` cooperating workgroups.  The
+// single-query kernels use the hardware grid; the batched kernel splits the
+// hardware grid into teams and gives each team its own virtual grid.
+struct VGrid {
+  unsigned bid, nb;
+};
+SX_DEV VGrid hw_grid() { return VGrid{blockIdx.x, gridDim.x}; }
+
 // ---------------------------------------------------- global barrier ------
 // Lock-array barrier (Section 5: every workgroup writes its own status word;
 // one monitor workgroup waits for all of them and then releases everybody).
@@ -120,11 +128,13 @@ SX_DEV long long wg_sum_ll(long long v, long long *red) {
 // and identical in all workgroups.
 struct GridBarrier {
   Ctrl *c;
-  unsigned nblk;
+  unsigned nblk, rank;
   unsigned gen;
 
   SX_DEV GridBarrier(Ctrl *ctrl, unsigned start_gen)
-      : c(ctrl), nblk(gridDim.x), gen(start_gen) {}
+      : c(ctrl), nblk(gridDim.x), rank(blockIdx.x), gen(start_gen) {}
+  SX_DEV GridBarrier(Ctrl *ctrl, unsigned start_gen, const VGrid &vg)
+      : c(ctrl), nblk(vg.nb), rank(vg.bid), gen(start_gen) {}
 
   SX_DEV bool failed() const { return load_relaxed(&c->error.v[0]) != 0u; }
 
@@ -133,7 +143,7 @@ struct GridBarrier {
     const unsigned target = gen + 1;
     __syncthreads();
     bool ok = true;
-    if (blockIdx.x == 0) {
+    if (rank == 0) {
       for (unsigned b = 1 + threadIdx.x; b < nblk; b += blockDim.x) {
         unsigned spins = 0;
         while (load_relaxed(&c->flags[b].v[0]) != target) {
@@ -151,7 +161,7 @@ struct GridBarrier {
       if (threadIdx.x == 0)
         __hip_atomic_store(&c->bar_gen.v[0], target, __ATOMIC_RELEASE, SX_AG);
     } else if (threadIdx.x == 0) {
-      __hip_atomic_store(&c->flags[blockIdx.x].v[0], target, __ATOMIC_RELEASE, SX_AG);
+      __hip_atomic_store(&c->flags[rank].v[0], target, __ATOMIC_RELEASE, SX_AG);
       unsigned spins = 0;
       while (load_relaxed(&c->bar_gen.v[0]) != target) {
         __builtin_amdgcn_s_sleep(2);

@@ -114,10 +114,10 @@ struct Tiling {
 // per-workgroup counts.  `wavecnt` (global) receives [gw][NBINS] counts;
 // `wgc` (global) the workgroup totals.  Every thread of the workgroup calls.
 template <class Pred, class Deg>
-SX_DEV void ballot_count(int n, const Tiling &T, Pred pred, Deg degree, const Params &P, int chunk,
+SX_DEV void ballot_count(const VGrid &vg, int n, const Tiling &T, Pred pred, Deg degree, const Params &P, int chunk,
                          unsigned long long *const bits[NBINS], unsigned *wavecnt, WgCount *wgc,
                          unsigned *lds /* kWaves * 6 */) {
-  const unsigned gw = blockIdx.x * kWaves + wave_in_wg();
+  const unsigned gw = vg.bid * kWaves + wave_in_wg();
   const int lane = lane_id();
   const long long start = (long long)gw * T.tile;
   unsigned c[NBINS] = {0, 0, 0};
@@ -160,7 +160,7 @@ SX_DEV void ballot_count(int n, const Tiling &T, Pred pred, Deg degree, const Pa
       t.mf += (unsigned long long)lds[w * 6 + 3] | ((unsigned long long)lds[w * 6 + 4] << 32);
     }
     // vertices = small + medium + (large vertices, counted from the words in pass 2)
-    wgc[blockIdx.x] = t;
+    wgc[vg.bid] = t;
   }
   __syncthreads();
 }
@@ -169,7 +169,7 @@ SX_DEV void ballot_count(int n, const Tiling &T, Pred pred, Deg degree, const Pa
 // holds vertex vertex_of(i)).  Grid totals are returned in `tot`, identical
 // in every workgroup.
 template <class Deg, class VertexOf>
-SX_DEV void ballot_write(int n, const Tiling &T, Deg degree, VertexOf vertex_of, int chunk,
+SX_DEV void ballot_write(const VGrid &vg, int n, const Tiling &T, Deg degree, VertexOf vertex_of, int chunk,
                          unsigned long long *const bits[NBINS], const unsigned *wavecnt,
                          const WgCount *wgc, int *out_s, int *out_m, unsigned long long *out_l,
                          WgCount &tot, unsigned *lds /* kWaves * 8 */, long long *red /* kWaves */) {
@@ -180,9 +180,9 @@ SX_DEV void ballot_write(int n, const Tiling &T, Deg degree, VertexOf vertex_of,
   for (int i = 0; i < 2 * NBINS; ++i) acc[i] = 0;
   unsigned long long mf = 0;
 #pragma unroll 1
-  for (unsigned b = threadIdx.x; b < gridDim.x; b += kBlock) {
+  for (unsigned b = threadIdx.x; b < vg.nb; b += kBlock) {
     const WgCount w = wgc[b];
-    const bool lower = b < blockIdx.x;
+    const bool lower = b < vg.bid;
 #pragma unroll
     for (int bin = 0; bin < NBINS; ++bin) {
       acc[NBINS + bin] += w.cnt[bin];
@@ -214,13 +214,13 @@ SX_DEV void ballot_write(int n, const Tiling &T, Deg degree, VertexOf vertex_of,
   for (int w = 0; w < kWaves; ++w) mft += (unsigned long long)red[w];
   __syncthreads();
   const unsigned wv = wave_in_wg();
-  const unsigned gw = blockIdx.x * kWaves + wv;
+  const unsigned gw = vg.bid * kWaves + wv;
   unsigned pos[NBINS];
 #pragma unroll
   for (int bin = 0; bin < NBINS; ++bin) {
     unsigned p = r[bin];
 #pragma unroll 1
-    for (unsigned w = blockIdx.x * kWaves; w < gw; ++w) p += wavecnt[w * NBINS + bin];
+    for (unsigned w = vg.bid * kWaves; w < gw; ++w) p += wavecnt[w * NBINS + bin];
     pos[bin] = p;
   }
   const int lane = lane_id();
@@ -322,9 +322,9 @@ SX_DEV void visit_med(const int *list, unsigned cnt, const int *off, const int *
 
 // Large bin: one workgroup per item (a chunk of `chunk` arcs of one vertex).
 template <class Op>
-SX_DEV void visit_large(const unsigned long long *list, unsigned cnt, const int *off,
+SX_DEV void visit_large(const VGrid &vg, const unsigned long long *list, unsigned cnt, const int *off,
                         const int *idx, int chunk, Op &op) {
-  for (unsigned i = blockIdx.x; i < cnt; i += gridDim.x) {
+  for (unsigned i = vg.bid; i < cnt; i += vg.nb) {
     const unsigned long long it = list[i];
     const int v = (int)(it & 0xffffffffu);
     const int c = (int)(it >> 32);

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -19,6 +20,7 @@
 
 #include "simdx.h"
 #include "sx_kernels.hpp"
+#include "sx_policy.hpp"
 
 using namespace sx;
 
@@ -47,7 +49,16 @@ struct sx_ctx {
   int cus;
   int cooperative;
   std::vector<float> mlp;  // learned-policy parameters (host copy)
-  float *d_mlp = nullptr;
+  float *d_mlp = nullptr;  // and on the device
+  // training scratch, grown on demand: per sample y[4], h[64], delta[68], loss
+  float *d_scratch = nullptr;
+  size_t scratch_samples = 0;
+  // batched mode: team workspaces sized for (team_n, team_m), kept for reuse
+  std::vector<void *> team_allocs;
+  std::vector<Work> team_work;
+  int team_n = 0;
+  long long team_m = 0;
+  sx_batch_config tuned{0, 0, 0};
 };
 
 struct sx_graph {
@@ -112,7 +123,67 @@ sx_status sx_ctx_create(int hip_device, sx_ctx **out) {
 void sx_ctx_destroy(sx_ctx *c) {
   if (!c) return;
   if (c->d_mlp) (void)hipFree(c->d_mlp);
+  if (c->d_scratch) (void)hipFree(c->d_scratch);
+  for (void *p : c->team_allocs) (void)hipFree(p);
   delete c;
+}
+
+sx_status sx_policy_load_mlp(sx_ctx *ctx, const float *params, int64_t nparams) {
+  if (!ctx || !params) return fail(SX_EINVAL, "NULL argument");
+  if (nparams != SX_MLP_NPARAMS) return fail(SX_EINVAL, "nparams %lld != %d", (long long)nparams, SX_MLP_NPARAMS);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (!ctx->d_mlp) HIP_TRY(hipMalloc(&ctx->d_mlp, sizeof(float) * SX_MLP_NPARAMS));
+  HIP_TRY(hipMemcpy(ctx->d_mlp, params, sizeof(float) * SX_MLP_NPARAMS, hipMemcpyHostToDevice));
+  ctx->mlp.assign(params, params + SX_MLP_NPARAMS);
+  return SX_OK;
+}
+
+static sx_status mlp_scratch(sx_ctx *ctx, int n, float **Y, float **H, float **D, float **L) {
+  const size_t per = 4 + 64 + 68 + 1;
+  if ((size_t)n > ctx->scratch_samples) {
+    if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+    ctx->d_scratch = nullptr;
+    ctx->scratch_samples = 0;
+    hipError_t e = hipMalloc(&ctx->d_scratch, sizeof(float) * per * (size_t)n);
+    if (e != hipSuccess) return fail(SX_ENOMEM, "MLP scratch: %s", hipGetErrorString(e));
+    ctx->scratch_samples = (size_t)n;
+  }
+  float *b = ctx->d_scratch;
+  *Y = b;
+  *H = b + 4 * (size_t)n;
+  *D = b + 68 * (size_t)n;
+  *L = b + 136 * (size_t)n;
+  return SX_OK;
+}
+
+sx_status sx_mlp_forward(sx_ctx *ctx, const float *P, const float *X, int32_t n, float *Y,
+                         void *hip_stream) {
+  if (!ctx || !P || (n > 0 && (!X || !Y))) return fail(SX_EINVAL, "NULL argument");
+  if (n < 0) return fail(SX_EINVAL, "n < 0");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(mlp_forward(P, X, n, Y, nullptr, (hipStream_t)hip_stream));
+  return SX_OK;
+}
+
+sx_status sx_mlp_loss_grad(sx_ctx *ctx, const float *P, const float *X, const float *T,
+                           const float *M, int32_t n, float *loss, float *G, void *hip_stream) {
+  if (!ctx || !P || !X || !T || !M || !loss || !G) return fail(SX_EINVAL, "NULL argument");
+  if (n <= 0) return fail(SX_EINVAL, "n must be positive");
+  HIP_TRY(hipSetDevice(ctx->device));
+  float *Y, *H, *D, *L;
+  sx_status s = mlp_scratch(ctx, n, &Y, &H, &D, &L);
+  if (s != SX_OK) return s;
+  HIP_TRY(mlp_loss_grad(P, X, T, M, n, Y, H, D, L, loss, G, (hipStream_t)hip_stream));
+  return SX_OK;
+}
+
+sx_status sx_mlp_adam(sx_ctx *ctx, float *P, const float *G, float *Mo, float *Vo, int32_t step,
+                      float lr, float b1, float b2, float eps, void *hip_stream) {
+  if (!ctx || !P || !G || !Mo || !Vo) return fail(SX_EINVAL, "NULL argument");
+  if (step < 1) return fail(SX_EINVAL, "step counts from 1");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(mlp_adam(P, G, Mo, Vo, step, lr, b1, b2, eps, (hipStream_t)hip_stream));
+  return SX_OK;
 }
 
 }  // extern "C"
@@ -346,9 +417,11 @@ static Params make_params(const sx_program *p, const sx_graph *G, int grid) {
   P.beta = 24.0f;
   // a BFS level or a Bellman-Ford round adds at least one vertex to the set
   // of settled ones, so n + 2 iterations bound every correct run
-  P.max_iters = G->g.n + 2;
+  P.max_iters = G ? G->g.n + 2 : INT_MAX / 2;
   P.pr_d = p->ap.pr_damping;
   P.pr_iters = p->ap.pr_iters;
+  P.learned = pol.policy == SX_POLICY_LEARNED ? 1 : 0;
+  P.bins_fixed = (pol.bin_small > 0 || pol.bin_large > 0) ? 1 : 0;
   (void)G;
   return P;
 }
@@ -400,6 +473,8 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   a.P = make_params(p, G, grid);
   a.state_i = (int *)d_out;
   a.src = src;
+  a.mlp = ctx->d_mlp;
+  if (a.P.learned && !ctx->d_mlp) return fail(SX_ESTATE, "learned policy without loaded MLP");
   // unexplored arcs (BFS direction rule)
   int h_off[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(h_off, G->g.off + src, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -427,6 +502,7 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
     }
   } else {
     bool pulling = p->pol.direction == SX_DIR_PULL;
+    PolicyState ps{0u, 0ull};
     for (int it = 0;; ++it) {
       if (!pulling) {
         HIP_TRY(reset_slot(G->w.ctrl, (it + 2) % 3, st));
@@ -454,6 +530,25 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
       in.n = G->g.n;
       in.m = G->g.m;
       Decision d = decide_core(in, a.P, mu);
+      if (!d.done && a.P.learned) {
+        float x[kMlpIn], y[kMlpOut];
+        policy_features(in.nf, in.mf, sssp ? (unsigned long long)G->g.m : mu, G->g.n, G->g.m, ps,
+                        pulling, x);
+        mlp_eval_host(ctx->mlp.data(), x, y);
+        if (p->pol.direction == SX_DIR_AUTO) {
+          if (!pulling) d.to_pull = y[0] > 0.f;
+          else d.to_push = !(y[0] > 0.f);
+        }
+        if (!pulling && !d.to_pull)
+          d.ballot = in.ovf || (a.P.filter == 0 ? y[1] > 0.f : a.P.filter == 2);
+        if (!a.P.bins_fixed) {
+          a.P.t1 = 1 << clamp_log2(y[2], 2, 8);
+          const int t2 = 1 << clamp_log2(y[3], 6, 12);
+          a.P.t2 = std::max(t2, a.P.t1);
+        }
+      }
+      ps.nf_prev = in.nf;
+      ps.reached += in.nf;
       if (d.done) break;
       bool rebuild = d.ballot;
       if (pulling && d.to_push) { pulling = false; rebuild = q.overflow != 0; }
@@ -547,6 +642,359 @@ static sx_status run_pagerank(sx_program *p, sx_graph *G, void *d_out, hipStream
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
   fill_stats(G->h_ctrl, 2, ms, stats);
+  return SX_OK;
+}
+
+// ------------------------------------------------ policy data collection ---
+namespace {
+struct Snapshot {
+  std::vector<std::pair<void *, size_t>> items;  // (device source, bytes)
+  std::vector<void *> copies;
+  sx_status save(hipStream_t st) {
+    for (size_t i = 0; i < items.size(); ++i)
+      HIP_TRY(hipMemcpyAsync(copies[i], items[i].first, items[i].second, hipMemcpyDeviceToDevice, st));
+    return SX_OK;
+  }
+  sx_status restore(hipStream_t st) {
+    for (size_t i = 0; i < items.size(); ++i)
+      HIP_TRY(hipMemcpyAsync(items[i].first, copies[i], items[i].second, hipMemcpyDeviceToDevice, st));
+    return SX_OK;
+  }
+  ~Snapshot() {
+    for (void *c : copies) (void)hipFree(c);
+  }
+};
+}  // namespace
+
+extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_t src, void *d_out,
+                                       void *hip_stream, int32_t stride, float *features,
+                                       float *arm_ms, int32_t max_records, int32_t *nrecords) {
+  if (!p || !gc || !d_out || !features || !arm_ms || !nrecords) return fail(SX_EINVAL, "NULL argument");
+  if (p->ap.algo != SX_BFS && p->ap.algo != SX_SSSP) return fail(SX_EINVAL, "BFS or SSSP only");
+  sx_graph *G = const_cast<sx_graph *>(gc);
+  if (src < 0 || src >= G->g.n) return fail(SX_EINVAL, "source out of range");
+  if (p->ap.algo == SX_SSSP && !G->weighted) return fail(SX_EINVAL, "SSSP needs edge weights");
+  if (stride < 1) stride = 1;
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int sssp = p->ap.algo == SX_SSSP;
+  const int n = G->g.n;
+  const int grid = plain_grid(p->ctx, trav_kernel(TK_PUSH_STEP, sssp));
+  TravArgs a;
+  memset(&a, 0, sizeof a);
+  a.g = G->g;
+  a.w = G->w;
+  sx_program hp = *p;
+  hp.pol.policy = SX_POLICY_HEURISTIC;
+  hp.pol.fused = SX_UNFUSED;
+  a.P = make_params(&hp, G, grid);
+  a.state_i = (int *)d_out;
+  a.src = src;
+  const Params P0 = a.P;
+  Snapshot snap;
+  for (int par = 0; par < 2; ++par) {
+    snap.items.push_back({G->w.q[par][0], sizeof(int) * (size_t)n});
+    snap.items.push_back({G->w.q[par][1], sizeof(int) * (size_t)n});
+    snap.items.push_back({G->w.ql[par], sizeof(unsigned long long) * G->w.qcap_large});
+  }
+  snap.items.push_back({d_out, sizeof(int) * (size_t)n});
+  snap.items.push_back({G->w.stamp, sizeof(int) * (size_t)n});
+  snap.items.push_back({G->w.ctrl, sizeof(Ctrl)});
+  for (auto &it : snap.items) {
+    void *c = nullptr;
+    hipError_t e = hipMalloc(&c, it.second);
+    if (e != hipSuccess) return fail(SX_ENOMEM, "snapshot: %s", hipGetErrorString(e));
+    snap.copies.push_back(c);
+  }
+  int h_off[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(h_off, G->g.off + src, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  unsigned long long mu = (unsigned long long)(G->g.m - (h_off[1] - h_off[0]));
+  HIP_TRY(trav_init(a, sssp, mu, st));
+  const int arm_t[4][2] = {{16, 256}, {64, 256}, {64, 1024}, {256, 2048}};
+  // features of the decision before iteration `it`, computed exactly as the
+  // fused kernels do after the previous iteration (before iteration 0: the
+  // source alone)
+  PolicyState ps{0u, 0ull};
+  float xnext[8];
+  policy_features(1u, (unsigned long long)(h_off[1] - h_off[0]),
+                  sssp ? (unsigned long long)G->g.m : mu, n, G->g.m, ps, false, xnext);
+  bool last_ovf = false;
+  bool pulling = false;
+  int rec = 0;
+  hipEvent_t e0 = G->ev0, e1 = G->ev1;
+  for (int it = 0;; ++it) {
+    if (rec < max_records && it % stride == 0) {
+      float *x = features + (size_t)rec * 8;
+      for (int i = 0; i < 8; ++i) x[i] = xnext[i];
+      float *t = arm_ms + (size_t)rec * SX_POLICY_ARMS;
+      sx_status s = snap.save(st);
+      if (s != SX_OK) return s;
+      for (int arm = 0; arm < SX_POLICY_ARMS; ++arm) {
+        TravArgs b = a;
+        if (arm == 0 && (pulling || last_ovf)) { t[arm] = NAN; continue; }
+        HIP_TRY(hipEventRecord(e0, st));
+        if (arm >= 1 && arm <= 4) {
+          b.P.t1 = arm_t[arm - 1][0];
+          b.P.t2 = arm_t[arm - 1][1];
+          HIP_TRY(trav_launch(TK_BALLOT1, sssp, b, it - 1, grid, st));
+          HIP_TRY(trav_launch(TK_BALLOT2, sssp, b, it - 1, grid, st));
+        }
+        if (arm <= 4) {
+          HIP_TRY(trav_launch(TK_PUSH_STEP, sssp, b, it, grid, st));
+        } else {
+          HIP_TRY(trav_launch(TK_PULL_SCAN, sssp, b, it, grid, st));
+          HIP_TRY(reset_slot(G->w.ctrl, (it + 1) % 3, st));
+          HIP_TRY(trav_launch(TK_PULL_LISTS, sssp, b, it, grid, st));
+          HIP_TRY(trav_launch(TK_PULL_STEP, sssp, b, it, grid, st));
+        }
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        t[arm] = ms;
+        s = snap.restore(st);
+        if (s != SX_OK) return s;
+      }
+      HIP_TRY(hipStreamSynchronize(st));
+      ++rec;
+    }
+    // the heuristic's own iteration, exactly as in the one-phase run loop
+    if (!pulling) {
+      HIP_TRY(reset_slot(G->w.ctrl, (it + 2) % 3, st));
+      HIP_TRY(trav_launch(TK_PUSH_STEP, sssp, a, it, grid, st));
+    } else {
+      HIP_TRY(trav_launch(TK_PULL_SCAN, sssp, a, it, grid, st));
+      HIP_TRY(reset_slot(G->w.ctrl, (it + 1) % 3, st));
+      HIP_TRY(trav_launch(TK_PULL_LISTS, sssp, a, it, grid, st));
+      HIP_TRY(trav_launch(TK_PULL_STEP, sssp, a, it, grid, st));
+    }
+    sx_status s = read_ctrl(G, st);
+    if (s != SX_OK) return s;
+    s = ctrl_error(G->h_ctrl);
+    if (s != SX_OK) return s;
+    const Counters &q = G->h_ctrl->q[(it + 1) % 3];
+    DecideIn in;
+    in.nf = q.nf;
+    in.mf = q.mf;
+    in.ovf = q.overflow;
+    in.it = it;
+    in.pulling = pulling;
+    in.vote = !sssp;
+    in.n = n;
+    in.m = G->g.m;
+    Decision d = decide_core(in, P0, mu);
+    policy_features(in.nf, in.mf, sssp ? (unsigned long long)G->g.m : mu, n, G->g.m, ps, pulling, xnext);
+    ps.nf_prev = in.nf;
+    ps.reached += in.nf;
+    last_ovf = in.ovf != 0;
+    if (d.done) break;
+    bool rebuild = d.ballot;
+    if (pulling && d.to_push) { pulling = false; rebuild = q.overflow != 0; }
+    else if (!pulling && d.to_pull) pulling = true;
+    if (rebuild && !pulling) {
+      HIP_TRY(trav_launch(TK_BALLOT1, sssp, a, it, grid, st));
+      HIP_TRY(trav_launch(TK_BALLOT2, sssp, a, it, grid, st));
+      last_ovf = false;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  *nrecords = rec;
+  return SX_OK;
+}
+
+// -------------------------------------------------------------- batches ---
+static sx_status team_workspaces(sx_ctx *ctx, int nteams, int n, long long m) {
+  if ((int)ctx->team_work.size() >= nteams && ctx->team_n >= n && ctx->team_m >= m) return SX_OK;
+  for (void *p : ctx->team_allocs) (void)hipFree(p);
+  ctx->team_allocs.clear();
+  ctx->team_work.clear();
+  n = std::max(n, ctx->team_n);
+  m = std::max(m, ctx->team_m);
+  const size_t nn = (size_t)std::max(n, 1);
+  const size_t words = (nn + 63) / 64 + 1;
+  const size_t large_cap = nn + 2 * (size_t)(m / kChunk) + 2;
+  auto al = [&](void **p, size_t bytes) -> sx_status {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 256);
+    if (e != hipSuccess) return fail(SX_ENOMEM, "team workspace: %s", hipGetErrorString(e));
+    ctx->team_allocs.push_back(*p);
+    return SX_OK;
+  };
+  for (int t = 0; t < nteams; ++t) {
+    Work w;
+    memset(&w, 0, sizeof w);
+    sx_status r;
+    for (int p = 0; p < 2; ++p) {
+      if ((r = al((void **)&w.q[p][0], 4 * nn)) != SX_OK) return r;
+      if ((r = al((void **)&w.q[p][1], 4 * nn)) != SX_OK) return r;
+      if ((r = al((void **)&w.ql[p], 8 * large_cap)) != SX_OK) return r;
+    }
+    for (int b = 0; b < NBINS; ++b)
+      if ((r = al((void **)&w.bits[b], 8 * words)) != SX_OK) return r;
+    if ((r = al((void **)&w.fbits, 8 * words)) != SX_OK) return r;
+    if ((r = al((void **)&w.wavecnt, sizeof(unsigned) * 64 * kWaves * NBINS)) != SX_OK) return r;
+    if ((r = al((void **)&w.wgc, sizeof(WgCount) * 64)) != SX_OK) return r;
+    if ((r = al((void **)&w.stamp, 4 * nn)) != SX_OK) return r;
+    if ((r = al((void **)&w.ctrl, sizeof(Ctrl))) != SX_OK) return r;
+    HIP_TRY(hipMemset(w.ctrl, 0, sizeof(Ctrl)));
+    w.qcap_small = (unsigned)nn;
+    w.qcap_med = (unsigned)nn;
+    w.qcap_large = (unsigned)std::min<size_t>(large_cap, 0xFFFFFFF0u);
+    ctx->team_work.push_back(w);
+  }
+  ctx->team_n = n;
+  ctx->team_m = m;
+  return SX_OK;
+}
+
+static sx_status validate_queries(sx_ctx *ctx, const sx_query *q, int32_t nq, int *nmax,
+                                  long long *mmax) {
+  if (!ctx || (nq > 0 && !q) || nq < 0) return fail(SX_EINVAL, "bad batch arguments");
+  *nmax = 0;
+  *mmax = 0;
+  for (int i = 0; i < nq; ++i) {
+    const sx_graph *g = q[i].g;
+    if (!g || !q[i].d_out) return fail(SX_EINVAL, "query %d: NULL graph or output", i);
+    if (g->ctx != ctx) return fail(SX_EINVAL, "query %d: graph of another context", i);
+    if (q[i].algo != SX_BFS && q[i].algo != SX_SSSP) return fail(SX_EINVAL, "query %d: BFS or SSSP only", i);
+    if (q[i].source < 0 || q[i].source >= g->g.n) return fail(SX_EINVAL, "query %d: source out of range", i);
+    if (q[i].algo == SX_SSSP && !g->weighted) return fail(SX_EINVAL, "query %d: SSSP needs weights", i);
+    *nmax = std::max(*nmax, g->g.n);
+    *mmax = std::max(*mmax, g->g.m);
+  }
+  return SX_OK;
+}
+
+extern "C" sx_status sx_run_batch(sx_ctx *ctx, const sx_query *q, int32_t nq, const sx_policy *pol,
+                                  const sx_batch_config *cfg, void *hip_stream,
+                                  sx_run_stats *per_query, double *batch_ms) {
+  int nmax;
+  long long mmax;
+  sx_status s = validate_queries(ctx, q, nq, &nmax, &mmax);
+  if (s != SX_OK) return s;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (nq == 0) {
+    if (batch_ms) *batch_ms = 0.0;
+    return SX_OK;
+  }
+  sx_batch_config c{4, 0, 0};
+  if (cfg) c = *cfg;
+  else if (ctx->tuned.team_wgs > 0) c = ctx->tuned;
+  int per = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel(), kBlock, 0));
+  const int grid = std::max(1, std::min(per * ctx->cus, kMaxGrid));
+  if (c.team_wgs < 1 || c.team_wgs > 64) return fail(SX_EINVAL, "team_wgs must be in 1..64");
+  const int team = std::min(c.team_wgs, grid);
+  const int nteams = grid / team;
+  s = team_workspaces(ctx, nteams, nmax, mmax);
+  if (s != SX_OK) return s;
+  // programme-level parameters as for a single run
+  sx_program prog;
+  memset(&prog, 0, sizeof prog);
+  prog.ctx = ctx;
+  prog.ap.algo = SX_BFS;
+  if (pol) prog.pol = *pol;
+  if (c.bin_small > 0) prog.pol.bin_small = c.bin_small;
+  if (c.bin_large > 0) prog.pol.bin_large = c.bin_large;
+  if (prog.pol.policy == SX_POLICY_LEARNED && !ctx->d_mlp)
+    return fail(SX_ESTATE, "learned policy requested but no MLP loaded");
+  BatchArgs b;
+  memset(&b, 0, sizeof b);
+  b.P = make_params(&prog, nullptr, team);
+  b.mlp = ctx->d_mlp;
+  b.nq = nq;
+  b.nteams = nteams;
+  b.team = team;
+  // device-side query table, order (largest expected time first), stats
+  std::vector<BatchQuery> hq((size_t)nq);
+  std::vector<std::pair<double, int>> key((size_t)nq);
+  for (int i = 0; i < nq; ++i) {
+    const DevGraph &g = q[i].g->g;
+    hq[i].g = g;
+    hq[i].state = (int *)q[i].d_out;
+    hq[i].algo = q[i].algo == SX_SSSP ? 1 : 0;
+    hq[i].src = q[i].source;
+    hq[i].mu0 = 0;
+    const double avg = g.n ? (double)g.m / g.n : 0.0;
+    // low average degree: a mesh-like, high-diameter graph whose run time
+    // grows with sqrt(n) levels; otherwise with the arcs
+    const double est = avg < 6.0 ? 2e3 * std::sqrt((double)g.n) : (double)g.m;
+    key[i] = {-(est * (hq[i].algo ? 2.0 : 1.0)), i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int> order((size_t)nq);
+  for (int i = 0; i < nq; ++i) order[i] = key[i].second;
+  struct Buf { void *p = nullptr; ~Buf() { if (p) (void)hipFree(p); } } bq, bo, bw, bh, bs;
+  HIP_TRY(hipMalloc(&bq.p, sizeof(BatchQuery) * nq));
+  HIP_TRY(hipMalloc(&bo.p, sizeof(int) * nq));
+  HIP_TRY(hipMalloc(&bw.p, sizeof(Work) * nteams));
+  HIP_TRY(hipMalloc(&bh.p, 256));
+  HIP_TRY(hipMalloc(&bs.p, sizeof(BatchStat) * nq));
+  HIP_TRY(hipMemcpyAsync(bq.p, hq.data(), sizeof(BatchQuery) * nq, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(bo.p, order.data(), sizeof(int) * nq, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(bw.p, ctx->team_work.data(), sizeof(Work) * nteams, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(bs.p, 0, sizeof(BatchStat) * nq, st));
+  b.q = (const BatchQuery *)bq.p;
+  b.order = (const int *)bo.p;
+  b.work = (const Work *)bw.p;
+  b.queue_head = (unsigned *)bh.p;
+  b.stats = (BatchStat *)bs.p;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, st));
+  HIP_TRY(batch_launch(b, grid, st));
+  HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::vector<BatchStat> hs((size_t)nq);
+  HIP_TRY(hipMemcpy(hs.data(), bs.p, sizeof(BatchStat) * nq, hipMemcpyDeviceToHost));
+  // team errors (watchdog) and per-query completion
+  for (int t = 0; t < nteams; ++t) {
+    unsigned err = 0;
+    HIP_TRY(hipMemcpy(&err, &ctx->team_work[t].ctrl->error.v[0], 4, hipMemcpyDeviceToHost));
+    if (err == SX_ERR_DEADLOCK) return fail(SX_EDEADLOCK, "team %d barrier watchdog fired", t);
+    if (err == SX_ERR_OVERFLOW) return fail(SX_EOVERFLOW, "distance overflow in team %d", t);
+    if (err) return fail(SX_EHIP, "team %d device error %u", t, err);
+  }
+  for (int i = 0; i < nq; ++i)
+    if (hs[i].status != EXIT_DONE) return fail(SX_EHIP, "query %d did not finish (status %d)", i, hs[i].status);
+  if (per_query)
+    for (int i = 0; i < nq; ++i) {
+      per_query[i].iterations = hs[i].iterations;
+      per_query[i].launches = 1;
+      per_query[i].pull_iters = hs[i].pull_iters;
+      per_query[i].ballot_iters = hs[i].ballot_iters;
+      per_query[i].edges_inspected = (int64_t)hs[i].edges;
+      per_query[i].vertex_expansions = (int64_t)hs[i].expansions;
+      per_query[i].device_ms = ms;
+    }
+  if (batch_ms) *batch_ms = ms;
+  return SX_OK;
+}
+
+extern "C" sx_status sx_batch_autotune(sx_ctx *ctx, const sx_query *q, int32_t nq, const sx_policy *pol,
+                                       void *hip_stream, sx_batch_config *best, double *best_ms) {
+  if (!best) return fail(SX_EINVAL, "NULL argument");
+  const int teams[] = {1, 2, 4, 8, 16, 32};
+  const int bins[][2] = {{64, 256}, {32, 1024}};
+  double bms = 1e300;
+  sx_batch_config bc{4, 0, 0};
+  for (int t : teams)
+    for (auto &bb : bins) {
+      sx_batch_config c{t, bb[0], bb[1]};
+      double ms = 0.0;
+      sx_status s = sx_run_batch(ctx, q, nq, pol, &c, hip_stream, nullptr, &ms);
+      if (s != SX_OK) return s;
+      if (ms < bms) { bms = ms; bc = c; }
+    }
+  ctx->tuned = bc;
+  *best = bc;
+  if (best_ms) *best_ms = bms;
   return SX_OK;
 }
 

@@ -94,7 +94,7 @@ SX_DEV void kscan_pass1(const KArgs &a, int k, int scan_no, LdsK &lds) {
     return a.core[v] == -1 && w.deg[v] <= k;
   };
   auto degree = [&](int i) { return total_degree(g, A[i]); };
-  ballot_count(cA, T, pred, degree, a.P, a.P.chunk, w.bits, w.wavecnt, w.wgc, lds.cnt);
+  ballot_count(hw_grid(), cA, T, pred, degree, a.P, a.P.chunk, w.bits, w.wavecnt, w.wgc, lds.cnt);
 }
 
 // Level scan, pass 2: sorted binned frontier into parity `qp`, counts into
@@ -110,7 +110,7 @@ SX_DEV unsigned kscan_pass2(const KArgs &a, int qp, int slot, int scan_no, LdsK 
   auto degree = [&](int v) { return total_degree(g, v); };
   auto vof = [&](int i) { return A[i]; };
   WgCount tot;
-  ballot_write(cA, T, degree, vof, a.P.chunk, w.bits, w.wavecnt, w.wgc, w.q[qp][0], w.q[qp][1],
+  ballot_write(hw_grid(), cA, T, degree, vof, a.P.chunk, w.bits, w.wavecnt, w.wgc, w.q[qp][0], w.q[qp][1],
                w.ql[qp], tot, lds.cnt, lds.red);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     Counters *q = &C->q[slot];
@@ -174,7 +174,7 @@ SX_DEV void kpeel(const KArgs &a, int k, int qp, int slot, LdsK &lds) {
   for (int pass = 0; pass < (g.directed ? 2 : 1); ++pass) {
     const int *off = pass ? g.in_off : g.off;
     const int *idx = pass ? g.in_idx : g.idx;
-    visit_large(w.ql[qp], cl, off, idx, a.P.chunk, op);
+    visit_large(hw_grid(), w.ql[qp], cl, off, idx, a.P.chunk, op);
     visit_med(w.q[qp][1], cm, off, idx, op, gw, nw);
     visit_small(w.q[qp][0], cs, off, idx, op, gw, nw, lds.small[wave_in_wg()]);
   }

@@ -14,11 +14,20 @@ const void *trav_kernel(int kind, int sssp);
 hipError_t trav_launch(int kind, int sssp, const TravArgs &a, int it, int grid, hipStream_t s);
 hipError_t trav_init(const TravArgs &a, int sssp, unsigned long long mu0, hipStream_t s);
 hipError_t reset_slot(Ctrl *c, int slot, hipStream_t s);
+hipError_t batch_launch(const BatchArgs &b, int grid, hipStream_t s);
+const void *batch_kernel();
 
 hipError_t kcore_launch(const KArgs &a, int grid, hipStream_t s, bool init);
 const void *kcore_kernel();
 
 hipError_t pagerank_launch(const PrArgs &a, int grid, hipStream_t s);
 const void *pagerank_kernel();
+
+hipError_t mlp_forward(const float *P, const float *X, int n, float *Y, float *H, hipStream_t s);
+hipError_t mlp_loss_grad(const float *P, const float *X, const float *T, const float *M, int n,
+                         float *Y, float *H, float *D, float *L, float *loss, float *G,
+                         hipStream_t s);
+hipError_t mlp_adam(float *P, const float *G, float *Mo, float *Vo, int step, float lr, float b1,
+                    float b2, float eps, hipStream_t s);
 
 }  // namespace sx

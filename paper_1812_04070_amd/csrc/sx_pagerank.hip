@@ -83,7 +83,7 @@ SX_DEV void pr_lists_pass1(const PrArgs &a, LdsPr &lds) {
   const int *io = a.g.in_off;
   auto pred = [&](int v) { (void)v; return true; };
   auto deg = [&](int v) { return io[v + 1] - io[v]; };
-  ballot_count(a.g.n, T, pred, deg, a.P, 0x7fffffff, a.w.bits, a.w.wavecnt, a.w.wgc, lds.cnt);
+  ballot_count(hw_grid(), a.g.n, T, pred, deg, a.P, 0x7fffffff, a.w.bits, a.w.wavecnt, a.w.wgc, lds.cnt);
 }
 SX_DEV void pr_lists_pass2(const PrArgs &a, LdsPr &lds, unsigned tot_out[3]) {
   Tiling T(a.g.n, gridDim.x * kWaves);
@@ -91,7 +91,7 @@ SX_DEV void pr_lists_pass2(const PrArgs &a, LdsPr &lds, unsigned tot_out[3]) {
   auto deg = [&](int v) { return io[v + 1] - io[v]; };
   auto ident = [](int i) { return i; };
   WgCount tot;
-  ballot_write(a.g.n, T, deg, ident, 0x7fffffff, a.w.bits, a.w.wavecnt, a.w.wgc, a.w.q[0][0],
+  ballot_write(hw_grid(), a.g.n, T, deg, ident, 0x7fffffff, a.w.bits, a.w.wavecnt, a.w.wgc, a.w.q[0][0],
                a.w.q[0][1], a.w.ql[0], tot, lds.cnt, lds.red);
   tot_out[0] = min(tot.cnt[0], a.w.qcap_small);
   tot_out[1] = min(tot.cnt[1], a.w.qcap_med);

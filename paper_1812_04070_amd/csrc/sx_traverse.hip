@@ -23,6 +23,7 @@
 //                            the same phases as one launch each (no fusion).
 #include "sx_frontier.hpp"
 #include "sx_kernels.hpp"
+#include "sx_policy.hpp"
 
 namespace sx {
 
@@ -95,7 +96,7 @@ struct LdsTrav {
 // Compute + combine over the current lists (parity it & 1, counters slot it),
 // online filter into the next lists (parity it+1, slot it+1).
 template <class Ops>
-SX_PHASE void push_phase(const TravArgs &a, const Ops &ops, int it, LdsTrav &lds) {
+SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, const Ops &ops, int it, LdsTrav &lds) {
   Ctrl *C = a.w.ctrl;
   Counters *cur = &C->q[it % 3], *nxt = &C->q[(it + 1) % 3];
   // counts are clamped to the list capacities: reads never leave the lists
@@ -104,9 +105,9 @@ SX_PHASE void push_phase(const TravArgs &a, const Ops &ops, int it, LdsTrav &lds
                  cl = min(load_relaxed(&cur->cnt[2]), a.w.qcap_large);
   const int p = it & 1;
   Lists NL = lists_for(a.w, p ^ 1, nxt);
-  NL.cap_s = online_cap(a.w, a.P, 0);
-  NL.cap_m = online_cap(a.w, a.P, 1);
-  NL.cap_l = online_cap(a.w, a.P, 2);
+  NL.cap_s = online_cap(a.w, P, 0);
+  NL.cap_m = online_cap(a.w, P, 1);
+  NL.cap_l = online_cap(a.w, P, 2);
   const DevGraph &g = a.g;
   WaveStats st;
   unsigned err = 0;
@@ -118,11 +119,11 @@ SX_PHASE void push_phase(const TravArgs &a, const Ops &ops, int it, LdsTrav &lds
       ++edges;
       if (ops.push(v, u, arc, g, err)) { act = true; du = degree_of(g.off, u); }
     }
-    online_append(act, u, du, NL, a.P, a.P.chunk, st);
+    online_append(act, u, du, NL, P, P.chunk, st);
   };
-  const unsigned gw = blockIdx.x * kWaves + wave_in_wg();
-  const unsigned nw = gridDim.x * kWaves;
-  visit_large(a.w.ql[p], cl, g.off, g.idx, a.P.chunk, op);
+  const unsigned gw = vg.bid * kWaves + wave_in_wg();
+  const unsigned nw = vg.nb * kWaves;
+  visit_large(vg, a.w.ql[p], cl, g.off, g.idx, P.chunk, op);
   visit_med(a.w.q[p][1], cm, g.off, g.idx, op, gw, nw);
   visit_small(a.w.q[p][0], cs, g.off, g.idx, op, gw, nw, lds.small[wave_in_wg()]);
   flush_stats(st, nxt);
@@ -132,34 +133,34 @@ SX_PHASE void push_phase(const TravArgs &a, const Ops &ops, int it, LdsTrav &lds
     if (err) store_relaxed(&C->error.v[0], err);
   }
   // worklist entries processed this iteration (vertex expansions)
-  if (blockIdx.x == 0 && threadIdx.x == 0)
+  if (vg.bid == 0 && threadIdx.x == 0)
     atomic_add_u64((unsigned long long *)&C->stats.v[2], (unsigned long long)(cs + cm) + cl);
 }
 
 // --------------------------------------------------------- ballot filter ---
 // Rebuild the next lists (parity it+1) from vertex metadata: pass 1 counts.
 template <class Ops>
-SX_PHASE void ballot_pass1(const TravArgs &a, const Ops &ops, LdsTrav &lds) {
+SX_PHASE void ballot_pass1(const VGrid &vg, const TravArgs &a, const Params &P, const Ops &ops, LdsTrav &lds) {
   const Work &w = a.w;
-  Tiling T(a.g.n, gridDim.x * kWaves);
+  Tiling T(a.g.n, vg.nb * kWaves);
   const int *off = a.g.off;
   auto pred = [&](int v) { return ops.next_active(v); };
   auto deg = [&](int v) { return degree_of(off, v); };
-  ballot_count(a.g.n, T, pred, deg, a.P, a.P.chunk, w.bits, w.wavecnt, w.wgc, lds.cnt);
+  ballot_count(vg, a.g.n, T, pred, deg, P, P.chunk, w.bits, w.wavecnt, w.wgc, lds.cnt);
 }
 
 // pass 2 writes the sorted lists and (workgroup 0) their counts.
-SX_PHASE void ballot_pass2(const TravArgs &a, int it, LdsTrav &lds) {
+SX_PHASE void ballot_pass2(const VGrid &vg, const TravArgs &a, const Params &P, int it, LdsTrav &lds) {
   const Work &w = a.w;
-  Tiling T(a.g.n, gridDim.x * kWaves);
+  Tiling T(a.g.n, vg.nb * kWaves);
   const int *off = a.g.off;
   auto deg = [&](int v) { return degree_of(off, v); };
   const int p = (it + 1) & 1;
   WgCount tot;
   auto ident = [](int i) { return i; };
-  ballot_write(a.g.n, T, deg, ident, a.P.chunk, w.bits, w.wavecnt, w.wgc,
+  ballot_write(vg, a.g.n, T, deg, ident, P.chunk, w.bits, w.wavecnt, w.wgc,
                w.q[p][0], w.q[p][1], w.ql[p], tot, lds.cnt, lds.red);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (vg.bid == 0 && threadIdx.x == 0) {
     Counters *nxt = &w.ctrl->q[(it + 1) % 3];
     store_relaxed(&nxt->cnt[0], tot.cnt[0]);
     store_relaxed(&nxt->cnt[1], tot.cnt[1]);
@@ -173,14 +174,14 @@ SX_PHASE void ballot_pass2(const TravArgs &a, int it, LdsTrav &lds) {
 // Scan: frontier bitmap of iteration it, and the sorted candidate lists
 // (pass 1 of a ballot filter whose predicate is "may still change").
 template <class Ops>
-SX_PHASE void pull_scan(const TravArgs &a, const Ops &ops, LdsTrav &lds) {
+SX_PHASE void pull_scan(const VGrid &vg, const TravArgs &a, const Params &P0, const Ops &ops, LdsTrav &lds) {
   const Work &w = a.w;
-  Tiling T(a.g.n, gridDim.x * kWaves);
+  Tiling T(a.g.n, vg.nb * kWaves);
   const int *off = a.g.in_off;
   const int n = a.g.n;
   // frontier words
   {
-    const unsigned gw = blockIdx.x * kWaves + wave_in_wg();
+    const unsigned gw = vg.bid * kWaves + wave_in_wg();
     const long long start = (long long)gw * T.tile;
     for (int s = 0; s < T.tile && start + s < n; s += 64) {
       const long long v = start + s + lane_id();
@@ -191,23 +192,22 @@ SX_PHASE void pull_scan(const TravArgs &a, const Ops &ops, LdsTrav &lds) {
   }
   auto pred = [&](int v) { return degree_of(off, v) > 0 && ops.pull_candidate(v); };
   auto deg = [&](int v) { return degree_of(off, v); };
-  Params P = a.P;
-  ballot_count(n, T, pred, deg, P, 0x7fffffff, w.bits, w.wavecnt, w.wgc, lds.cnt);
+  ballot_count(vg, n, T, pred, deg, P0, 0x7fffffff, w.bits, w.wavecnt, w.wgc, lds.cnt);
 }
 
 // Write the candidate lists into the parity-`it` buffers (not read by anyone
 // else in a pull iteration); counts go to slot it.
-SX_PHASE void pull_lists(const TravArgs &a, int it, LdsTrav &lds) {
+SX_PHASE void pull_lists(const VGrid &vg, const TravArgs &a, int it, LdsTrav &lds) {
   const Work &w = a.w;
-  Tiling T(a.g.n, gridDim.x * kWaves);
+  Tiling T(a.g.n, vg.nb * kWaves);
   const int *off = a.g.in_off;
   auto deg = [&](int v) { return degree_of(off, v); };
   const int p = it & 1;
   WgCount tot;
   auto ident = [](int i) { return i; };
-  ballot_write(a.g.n, T, deg, ident, 0x7fffffff, w.bits, w.wavecnt, w.wgc,
+  ballot_write(vg, a.g.n, T, deg, ident, 0x7fffffff, w.bits, w.wavecnt, w.wgc,
                w.q[p][0], w.q[p][1], w.ql[p], tot, lds.cnt, lds.red);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (vg.bid == 0 && threadIdx.x == 0) {
     Counters *cur = &w.ctrl->q[it % 3];
     store_relaxed(&cur->cnt[0], tot.cnt[0]);
     store_relaxed(&cur->cnt[1], tot.cnt[1]);
@@ -221,7 +221,7 @@ SX_DEV bool fbit(const unsigned long long *fb, int u) { return (fb[u >> 6] >> (u
 // improved vertices are recorded by the online filter into the next lists
 // (parity it+1, slot it+1) so that a switch back to push needs no scan.
 template <class Ops>
-SX_PHASE void pull_phase(const TravArgs &a, const Ops &ops, int it, LdsTrav &lds) {
+SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, const Ops &ops, int it, LdsTrav &lds) {
   Ctrl *C = a.w.ctrl;
   Counters *cur = &C->q[it % 3], *nxt = &C->q[(it + 1) % 3];
   // counts are clamped to the list capacities: reads never leave the lists
@@ -230,18 +230,18 @@ SX_PHASE void pull_phase(const TravArgs &a, const Ops &ops, int it, LdsTrav &lds
                  cl = min(load_relaxed(&cur->cnt[2]), a.w.qcap_large);
   const int p = it & 1;
   Lists NL = lists_for(a.w, p ^ 1, nxt);
-  NL.cap_s = online_cap(a.w, a.P, 0);
-  NL.cap_m = online_cap(a.w, a.P, 1);
-  NL.cap_l = online_cap(a.w, a.P, 2);
+  NL.cap_s = online_cap(a.w, P, 0);
+  NL.cap_m = online_cap(a.w, P, 1);
+  NL.cap_l = online_cap(a.w, P, 2);
   const DevGraph &g = a.g;
   const unsigned long long *fb = a.w.fbits;
   WaveStats st;
   long long edges = 0;
   const int lane = lane_id();
-  const unsigned gw = blockIdx.x * kWaves + wave_in_wg();
-  const unsigned nw = gridDim.x * kWaves;
+  const unsigned gw = vg.bid * kWaves + wave_in_wg();
+  const unsigned nw = vg.nb * kWaves;
   // One workgroup per large candidate
-  for (unsigned i = blockIdx.x; i < cl; i += gridDim.x) {
+  for (unsigned i = vg.bid; i < cl; i += vg.nb) {
     const int v = (int)(a.w.ql[p][i] & 0xffffffffu);
     const int beg = g.in_off[v], end = g.in_off[v + 1];
     unsigned best = 0xFFFFFFFFu;
@@ -283,7 +283,7 @@ SX_PHASE void pull_phase(const TravArgs &a, const Ops &ops, int it, LdsTrav &lds
       }
       __syncthreads();
     }
-    if (wave_in_wg() == 0) online_append(act, v, end - beg, NL, a.P, a.P.chunk, st);
+    if (wave_in_wg() == 0) online_append(act, v, end - beg, NL, P, P.chunk, st);
   }
   // One wavefront per medium candidate
   for (unsigned i = gw; i < cm; i += nw) {
@@ -318,7 +318,7 @@ SX_PHASE void pull_phase(const TravArgs &a, const Ops &ops, int it, LdsTrav &lds
         act = true;
       }
     }
-    online_append(act, v, end - beg, NL, a.P, a.P.chunk, st);
+    online_append(act, v, end - beg, NL, P, P.chunk, st);
   }
   // One lane per small candidate
   for (unsigned c0 = gw * 64u; c0 < cs; c0 += nw * 64u) {
@@ -353,39 +353,100 @@ SX_PHASE void pull_phase(const TravArgs &a, const Ops &ops, int it, LdsTrav &lds
         }
       }
     }
-    online_append(act, v, d, NL, a.P, a.P.chunk, st);
+    online_append(act, v, d, NL, P, P.chunk, st);
   }
   flush_stats(st, nxt);
   const long long e = wave_sum_ll(edges);
   if (lane == 0 && e) atomic_add_u64((unsigned long long *)&C->stats.v[0], (unsigned long long)e);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (vg.bid == 0 && threadIdx.x == 0) {
     atomic_add_u64((unsigned long long *)&C->stats.v[2], (unsigned long long)(cs + cm) + cl);
     atomic_add_u32(&C->stats.v[5], 1u);
   }
 }
 
 // --------------------------------------------------------- decisions ---
+// Uniform per-workgroup run state, saved in Ctrl::state across launches:
+// [0] exit reason [1] iteration [6,7] unexplored arcs [8] previous frontier
+// size [10,11] vertices activated so far [12] t1 [13] t2.
+struct RunState {
+  int it;
+  unsigned long long mu;
+  PolicyState ps;
+  Params P;
+};
+
+SX_DEV void load_state(const TravArgs &a, RunState &s) {
+  Ctrl *C = a.w.ctrl;
+  s.it = (int)load_relaxed(&C->state.v[1]);
+  s.mu = load_relaxed((unsigned long long *)&C->state.v[6]);
+  s.ps.nf_prev = load_relaxed(&C->state.v[8]);
+  s.ps.reached = load_relaxed((unsigned long long *)&C->state.v[10]);
+  s.P = a.P;
+  const unsigned t1 = load_relaxed(&C->state.v[12]), t2 = load_relaxed(&C->state.v[13]);
+  if (t1) { s.P.t1 = (int)t1; s.P.t2 = (int)t2; }
+}
+
+SX_DEV void finish(const VGrid &vg, Ctrl *C, int reason, const RunState &s) {
+  if (vg.bid == 0 && threadIdx.x == 0) {
+    store_relaxed(&C->state.v[0], (unsigned)reason);
+    store_relaxed(&C->state.v[1], (unsigned)s.it);
+    store_relaxed((unsigned long long *)&C->state.v[6], s.mu);
+    store_relaxed(&C->state.v[8], s.ps.nf_prev);
+    store_relaxed((unsigned long long *)&C->state.v[10], s.ps.reached);
+    store_relaxed(&C->state.v[12], (unsigned)s.P.t1);
+    store_relaxed(&C->state.v[13], (unsigned)s.P.t2);
+  }
+}
+
+struct LdsPolicy {
+  float p[kMlpParams];
+  float h[2 * kMlpHid];
+  float y[kMlpOut];
+};
+
+// The decision after iteration s.it: the rule of decide_core, then -- with
+// the learned policy -- the MLP's choices where the caller left them open.
+// Overflow always forces the ballot rebuild: the online lists are incomplete.
 template <class Ops>
-SX_DEV Decision decide(const TravArgs &a, int it, bool pulling, unsigned long long &mu) {
-  Counters *nxt = &a.w.ctrl->q[(it + 1) % 3];
+SX_DEV Decision decide(const TravArgs &a, RunState &s, bool pulling, LdsPolicy *pol) {
+  Counters *nxt = &a.w.ctrl->q[(s.it + 1) % 3];
   DecideIn in;
   in.nf = load_relaxed(&nxt->nf);
   in.mf = load_relaxed(&nxt->mf);
   in.ovf = load_relaxed(&nxt->overflow);
-  in.it = it;
+  in.it = s.it;
   in.pulling = pulling;
   in.vote = Ops::kVote;
   in.n = a.g.n;
   in.m = a.g.m;
-  return decide_core(in, a.P, mu);
-}
-
-SX_DEV void finish(Ctrl *C, int reason, int it, unsigned long long mu) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    store_relaxed(&C->state.v[0], (unsigned)reason);
-    store_relaxed(&C->state.v[1], (unsigned)it);
-    store_relaxed((unsigned long long *)&C->state.v[6], mu);
+  Decision d = decide_core(in, s.P, s.mu);
+  if (!d.done && a.P.learned) {
+    float x[kMlpIn];
+    policy_features(in.nf, in.mf, Ops::kVote ? s.mu : (unsigned long long)a.g.m, a.g.n, a.g.m, s.ps,
+                    pulling, x);
+    __syncthreads();
+    if (wave_in_wg() == 0) {
+      float y[kMlpOut];
+      mlp_eval_wave(pol->p, x, pol->h, y);
+      if (lane_id() == 0)
+        for (int k = 0; k < kMlpOut; ++k) pol->y[k] = y[k];
+    }
+    __syncthreads();
+    const float y0 = pol->y[0], y1 = pol->y[1], y2 = pol->y[2], y3 = pol->y[3];
+    if (a.P.direction == 0) {
+      if (!pulling) d.to_pull = y0 > 0.f;
+      else d.to_push = !(y0 > 0.f);
+    }
+    if (!pulling && !d.to_pull) d.ballot = in.ovf || (a.P.filter == 0 ? y1 > 0.f : a.P.filter == 2);
+    if (!a.P.bins_fixed) {
+      s.P.t1 = 1 << clamp_log2(y2, 2, 8);
+      const int t2 = 1 << clamp_log2(y3, 6, 12);
+      s.P.t2 = t2 > s.P.t1 ? t2 : s.P.t1;
+    }
   }
+  s.ps.nf_prev = in.nf;
+  s.ps.reached += in.nf;
+  return d;
 }
 
 template <class Ops>
@@ -397,119 +458,303 @@ SX_DEV SsspOps make_ops<SsspOps>(const TravArgs &a, int it) {
   return SsspOps{(unsigned *)a.state_i, a.w.stamp, it};
 }
 
+SX_DEV void load_policy(const TravArgs &a, LdsPolicy &pol) {
+  if (!a.P.learned) return;
+  for (int i = threadIdx.x; i < kMlpParams; i += kBlock) pol.p[i] = a.mlp[i];
+  __syncthreads();
+}
+
+SX_DEV bool entry_done(Ctrl *C) {
+  const unsigned e = load_relaxed(&C->state.v[0]);
+  return e == EXIT_DONE || e == EXIT_LIMIT || e == EXIT_ERROR;
+}
+
 // -------------------------------------------------- persistent kernels ---
 template <class Ops>
 __global__ void __launch_bounds__(kBlock) k_push_fused(TravArgs a) {
   __shared__ LdsTrav lds;
+  __shared__ LdsPolicy pol;
   Ctrl *C = a.w.ctrl;
+  const VGrid vg = hw_grid();
   GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]));
-  int it = (int)load_relaxed(&C->state.v[1]);
-  unsigned long long mu = load_relaxed((unsigned long long *)&C->state.v[6]);
-  const unsigned entry = load_relaxed(&C->state.v[0]);
-  if (entry == EXIT_DONE || entry == EXIT_LIMIT || entry == EXIT_ERROR || bar.failed()) return;
+  if (entry_done(C) || bar.failed()) return;
+  RunState s;
+  load_state(a, s);
+  load_policy(a, pol);
   // a list that overflowed while pulling is rebuilt before the first push
-  if (load_relaxed(&C->q[it % 3].overflow)) {
-    Ops ops = make_ops<Ops>(a, it - 1);
-    ballot_pass1(a, ops, lds);
-    if (!bar.sync()) { finish(C, EXIT_ERROR, it, mu); return; }
-    ballot_pass2(a, it - 1, lds);
-    if (!bar.sync()) { finish(C, EXIT_ERROR, it, mu); return; }
+  if (load_relaxed(&C->q[s.it % 3].overflow)) {
+    Ops ops = make_ops<Ops>(a, s.it - 1);
+    ballot_pass1(vg, a, s.P, ops, lds);
+    if (!bar.sync()) { finish(vg, C, EXIT_ERROR, s); return; }
+    ballot_pass2(vg, a, s.P, s.it - 1, lds);
+    if (!bar.sync()) { finish(vg, C, EXIT_ERROR, s); return; }
   }
   for (;;) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      Counters *old = &C->q[(it + 2) % 3];
+    if (vg.bid == 0 && threadIdx.x == 0) {
+      Counters *old = &C->q[(s.it + 2) % 3];
       for (int b = 0; b < NBINS; ++b) store_relaxed(&old->cnt[b], 0u);
       store_relaxed(&old->nf, 0u);
       store_relaxed(&old->mf, 0ull);
       store_relaxed(&old->overflow, 0u);
       atomic_add_u32(&C->stats.v[6], 1u);
     }
-    Ops ops = make_ops<Ops>(a, it);
-    push_phase(a, ops, it, lds);
-    if (!bar.sync()) { finish(C, EXIT_ERROR, it, mu); return; }
-    if (load_relaxed(&C->error.v[0])) { finish(C, EXIT_ERROR, it, mu); return; }
-    Decision d = decide<Ops>(a, it, false, mu);
-    if (d.done && it + 1 >= a.P.max_iters) { finish(C, EXIT_LIMIT, it + 1, mu); return; }
-    if (d.done) { finish(C, EXIT_DONE, it + 1, mu); return; }
-    if (d.to_pull) { finish(C, EXIT_SWITCH, it + 1, mu); return; }
+    Ops ops = make_ops<Ops>(a, s.it);
+    push_phase(vg, a, s.P, ops, s.it, lds);
+    if (!bar.sync()) { finish(vg, C, EXIT_ERROR, s); return; }
+    if (load_relaxed(&C->error.v[0])) { finish(vg, C, EXIT_ERROR, s); return; }
+    Decision d = decide<Ops>(a, s, false, &pol);
+    if (d.done) { ++s.it; finish(vg, C, s.it >= a.P.max_iters ? EXIT_LIMIT : EXIT_DONE, s); return; }
+    if (d.to_pull) { ++s.it; finish(vg, C, EXIT_SWITCH, s); return; }
     if (d.ballot) {
-      ballot_pass1(a, ops, lds);
-      if (!bar.sync()) { finish(C, EXIT_ERROR, it, mu); return; }
-      ballot_pass2(a, it, lds);
-      if (!bar.sync()) { finish(C, EXIT_ERROR, it, mu); return; }
+      ballot_pass1(vg, a, s.P, ops, lds);
+      if (!bar.sync()) { finish(vg, C, EXIT_ERROR, s); return; }
+      ballot_pass2(vg, a, s.P, s.it, lds);
+      if (!bar.sync()) { finish(vg, C, EXIT_ERROR, s); return; }
     }
-    ++it;
+    ++s.it;
   }
 }
 
 template <class Ops>
 __global__ void __launch_bounds__(kBlock) k_pull_fused(TravArgs a) {
   __shared__ LdsTrav lds;
+  __shared__ LdsPolicy pol;
   Ctrl *C = a.w.ctrl;
+  const VGrid vg = hw_grid();
   GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]));
-  int it = (int)load_relaxed(&C->state.v[1]);
-  unsigned long long mu = load_relaxed((unsigned long long *)&C->state.v[6]);
-  const unsigned entry = load_relaxed(&C->state.v[0]);
-  if (entry == EXIT_DONE || entry == EXIT_LIMIT || entry == EXIT_ERROR || bar.failed()) return;
+  if (entry_done(C) || bar.failed()) return;
+  RunState s;
+  load_state(a, s);
+  load_policy(a, pol);
   for (;;) {
-    Ops ops = make_ops<Ops>(a, it);
-    pull_scan(a, ops, lds);
-    if (!bar.sync()) { finish(C, EXIT_ERROR, it, mu); return; }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      Counters *nx = &C->q[(it + 1) % 3];
+    Ops ops = make_ops<Ops>(a, s.it);
+    pull_scan(vg, a, s.P, ops, lds);
+    if (!bar.sync()) { finish(vg, C, EXIT_ERROR, s); return; }
+    if (vg.bid == 0 && threadIdx.x == 0) {
+      Counters *nx = &C->q[(s.it + 1) % 3];
       for (int b = 0; b < NBINS; ++b) store_relaxed(&nx->cnt[b], 0u);
       store_relaxed(&nx->nf, 0u);
       store_relaxed(&nx->mf, 0ull);
       store_relaxed(&nx->overflow, 0u);
       atomic_add_u32(&C->stats.v[6], 1u);
     }
-    pull_lists(a, it, lds);
-    if (!bar.sync()) { finish(C, EXIT_ERROR, it, mu); return; }
-    pull_phase(a, ops, it, lds);
-    if (!bar.sync()) { finish(C, EXIT_ERROR, it, mu); return; }
-    if (load_relaxed(&C->error.v[0])) { finish(C, EXIT_ERROR, it, mu); return; }
-    Decision d = decide<Ops>(a, it, true, mu);
-    if (d.done && it + 1 >= a.P.max_iters) { finish(C, EXIT_LIMIT, it + 1, mu); return; }
-    if (d.done) { finish(C, EXIT_DONE, it + 1, mu); return; }
-    if (d.to_push) { finish(C, EXIT_SWITCH, it + 1, mu); return; }
-    ++it;
+    pull_lists(vg, a, s.it, lds);
+    if (!bar.sync()) { finish(vg, C, EXIT_ERROR, s); return; }
+    pull_phase(vg, a, s.P, ops, s.it, lds);
+    if (!bar.sync()) { finish(vg, C, EXIT_ERROR, s); return; }
+    if (load_relaxed(&C->error.v[0])) { finish(vg, C, EXIT_ERROR, s); return; }
+    Decision d = decide<Ops>(a, s, true, &pol);
+    if (d.done) { ++s.it; finish(vg, C, s.it >= a.P.max_iters ? EXIT_LIMIT : EXIT_DONE, s); return; }
+    if (d.to_push) { ++s.it; finish(vg, C, EXIT_SWITCH, s); return; }
+    ++s.it;
   }
 }
 
 // ------------------------------------------------ one-phase kernels ---
 // The same phases, one launch each; the host reads the counters between
-// launches and takes the decisions (no fusion).
+// launches and takes the decisions (no fusion).  `P` carries the thresholds
+// the host chose for this iteration.
 template <class Ops>
 __global__ void __launch_bounds__(kBlock) k_push_step(TravArgs a, int it) {
   __shared__ LdsTrav lds;
+  const VGrid vg = hw_grid();
   Ops ops = make_ops<Ops>(a, it);
-  push_phase(a, ops, it, lds);
+  push_phase(vg, a, a.P, ops, it, lds);
 }
 template <class Ops>
 __global__ void __launch_bounds__(kBlock) k_ballot1(TravArgs a, int it) {
   __shared__ LdsTrav lds;
+  const VGrid vg = hw_grid();
   Ops ops = make_ops<Ops>(a, it);
-  ballot_pass1(a, ops, lds);
+  ballot_pass1(vg, a, a.P, ops, lds);
 }
 __global__ void __launch_bounds__(kBlock) k_ballot2(TravArgs a, int it) {
   __shared__ LdsTrav lds;
-  ballot_pass2(a, it, lds);
+  const VGrid vg = hw_grid();
+  ballot_pass2(vg, a, a.P, it, lds);
 }
 template <class Ops>
 __global__ void __launch_bounds__(kBlock) k_pull_scan(TravArgs a, int it) {
   __shared__ LdsTrav lds;
+  const VGrid vg = hw_grid();
   Ops ops = make_ops<Ops>(a, it);
-  pull_scan(a, ops, lds);
+  pull_scan(vg, a, a.P, ops, lds);
 }
 __global__ void __launch_bounds__(kBlock) k_pull_lists(TravArgs a, int it) {
   __shared__ LdsTrav lds;
-  pull_lists(a, it, lds);
+  const VGrid vg = hw_grid();
+  pull_lists(vg, a, it, lds);
 }
 template <class Ops>
 __global__ void __launch_bounds__(kBlock) k_pull_step(TravArgs a, int it) {
   __shared__ LdsTrav lds;
+  const VGrid vg = hw_grid();
   Ops ops = make_ops<Ops>(a, it);
-  pull_phase(a, ops, it, lds);
+  pull_phase(vg, a, a.P, ops, it, lds);
+}
+
+// ------------------------------------------------- batched queries ---
+// Many BFS / SSSP queries over graphs of uneven size in one persistent
+// launch.  The hardware grid is split into teams of `team` workgroups; each
+// team owns a workspace (lists, stamps, bitmaps, control block with its own
+// barrier lines) and repeatedly takes the next query from a shared counter
+// (queries are ordered largest first), runs it to completion with the same
+// push / pull phases, JIT filters and decisions as the single-query kernels
+// -- both directions inside one kernel, switching in place -- synchronised by
+// a barrier over the team only, then takes the next.  Teams never wait for
+// each other, so a 6-level R-MAT query and a 4,000-level grid query overlap.
+
+SX_DEV void reset_counters(Counters *q) {
+  for (int b = 0; b < NBINS; ++b) store_relaxed(&q->cnt[b], 0u);
+  store_relaxed(&q->nf, 0u);
+  store_relaxed(&q->mf, 0ull);
+  store_relaxed(&q->overflow, 0u);
+}
+
+// Initialise one query on the team: vertex state, stamps, counters, the
+// source as the first list.  Ends with a team barrier.
+SX_DEV bool batch_init(const VGrid &vg, const TravArgs &a, bool sssp, unsigned long long mu0,
+                       GridBarrier &bar) {
+  const int n = a.g.n;
+  const long long tid = (long long)vg.bid * kBlock + threadIdx.x, nt = (long long)vg.nb * kBlock;
+  for (long long v = tid; v < n; v += nt) {
+    if (sssp) {
+      ((unsigned *)a.state_i)[v] = v == a.src ? 0u : 0xFFFFFFFFu;
+      a.w.stamp[v] = v == a.src ? 0 : -1;
+    } else {
+      a.state_i[v] = v == a.src ? 0 : -1;
+    }
+  }
+  Ctrl *C = a.w.ctrl;
+  if (vg.bid == 0 && threadIdx.x == 0) {
+    for (int s = 0; s < 3; ++s) reset_counters(&C->q[s]);
+    for (int i = 0; i < 32; ++i) {
+      store_relaxed(&C->state.v[i], 0u);
+      store_relaxed(&C->stats.v[i], 0u);
+    }
+    store_relaxed((unsigned long long *)&C->state.v[6], mu0);
+  }
+  if (!bar.sync()) return false;
+  if (vg.bid == 0 && threadIdx.x < 64) {
+    Lists L = lists_for(a.w, 0, &C->q[0]);
+    WaveStats st;
+    const bool me = threadIdx.x == 0;
+    const int d = me ? degree_of(a.g.off, a.src) : 0;
+    online_append(me, a.src, d, L, a.P, a.P.chunk, st);
+    flush_stats(st, &C->q[0]);
+  }
+  return bar.sync();
+}
+
+template <class Ops>
+SX_DEV bool batch_query(const VGrid &vg, const TravArgs &a, GridBarrier &bar, LdsTrav &lds,
+                        LdsPolicy &pol) {
+  Ctrl *C = a.w.ctrl;
+  RunState s;
+  load_state(a, s);
+  bool pulling = a.P.direction == 2;
+  for (;;) {
+    if (!pulling) {
+      if (vg.bid == 0 && threadIdx.x == 0) {
+        reset_counters(&C->q[(s.it + 2) % 3]);
+        atomic_add_u32(&C->stats.v[6], 1u);
+      }
+      Ops ops = make_ops<Ops>(a, s.it);
+      push_phase(vg, a, s.P, ops, s.it, lds);
+      if (!bar.sync()) return false;
+      if (load_relaxed(&C->error.v[0])) return false;
+      Decision d = decide<Ops>(a, s, false, &pol);
+      if (d.done) { ++s.it; finish(vg, C, s.it >= a.P.max_iters ? EXIT_LIMIT : EXIT_DONE, s); break; }
+      if (d.to_pull) { pulling = true; ++s.it; continue; }
+      if (d.ballot) {
+        ballot_pass1(vg, a, s.P, ops, lds);
+        if (!bar.sync()) return false;
+        ballot_pass2(vg, a, s.P, s.it, lds);
+        if (!bar.sync()) return false;
+      }
+      ++s.it;
+    } else {
+      Ops ops = make_ops<Ops>(a, s.it);
+      pull_scan(vg, a, s.P, ops, lds);
+      if (!bar.sync()) return false;
+      if (vg.bid == 0 && threadIdx.x == 0) {
+        reset_counters(&C->q[(s.it + 1) % 3]);
+        atomic_add_u32(&C->stats.v[6], 1u);
+      }
+      pull_lists(vg, a, s.it, lds);
+      if (!bar.sync()) return false;
+      pull_phase(vg, a, s.P, ops, s.it, lds);
+      if (!bar.sync()) return false;
+      if (load_relaxed(&C->error.v[0])) return false;
+      Decision d = decide<Ops>(a, s, true, &pol);
+      if (d.done) { ++s.it; finish(vg, C, s.it >= a.P.max_iters ? EXIT_LIMIT : EXIT_DONE, s); break; }
+      if (d.to_push) {
+        pulling = false;
+        if (load_relaxed(&C->q[(s.it + 1) % 3].overflow)) {
+          ballot_pass1(vg, a, s.P, ops, lds);
+          if (!bar.sync()) return false;
+          ballot_pass2(vg, a, s.P, s.it, lds);
+          if (!bar.sync()) return false;
+        }
+      }
+      ++s.it;
+    }
+  }
+  return bar.sync();
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch(BatchArgs b) {
+  __shared__ LdsTrav lds;
+  __shared__ LdsPolicy pol;
+  const unsigned team = blockIdx.x / (unsigned)b.team;
+  const VGrid vg{blockIdx.x % (unsigned)b.team, (unsigned)b.team};
+  if (team >= (unsigned)b.nteams) return;
+  const Work w = b.work[team];
+  Ctrl *C = w.ctrl;
+  GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]), vg);
+  TravArgs a;
+  a.w = w;
+  a.P = b.P;
+  a.mlp = b.mlp;
+  load_policy(a, pol);
+  for (;;) {
+    if (vg.bid == 0 && threadIdx.x == 0)
+      store_relaxed(&C->aux.v[20], atomic_add_u32(b.queue_head, 1u));
+    if (!bar.sync()) break;
+    const unsigned qi = load_relaxed(&C->aux.v[20]);
+    if (qi >= (unsigned)b.nq) break;
+    const BatchQuery Q = b.q[b.order[qi]];
+    a.g = Q.g;
+    a.state_i = Q.state;
+    a.src = Q.src;
+    a.P.max_iters = Q.g.n + 2;
+    const bool sssp = Q.algo == 1;
+    const unsigned long long mu0 = (unsigned long long)(Q.g.m - degree_of(Q.g.off, Q.src));
+    if (!batch_init(vg, a, sssp, mu0, bar)) break;
+    const bool ok = sssp ? batch_query<SsspOps>(vg, a, bar, lds, pol)
+                         : batch_query<BfsOps>(vg, a, bar, lds, pol);
+    if (vg.bid == 0 && threadIdx.x == 0) {
+      BatchStat &r = b.stats[b.order[qi]];
+      r.iterations = (int)load_relaxed(&C->stats.v[6]);
+      r.pull_iters = (int)load_relaxed(&C->stats.v[5]);
+      r.ballot_iters = (int)load_relaxed(&C->stats.v[4]);
+      r.edges = load_relaxed((unsigned long long *)&C->stats.v[0]);
+      r.expansions = load_relaxed((unsigned long long *)&C->stats.v[2]);
+      r.status = ok ? (int)load_relaxed(&C->state.v[0]) : -1;
+      r.team = (int)team;
+    }
+    if (!ok) break;
+  }
+}
+
+__global__ void k_batch_reset(BatchArgs b) {
+  // barrier generations restart at 0 for every team; the query counter at 0
+  const unsigned team = blockIdx.x;
+  if (team >= (unsigned)b.nteams) return;
+  Ctrl *C = b.work[team].ctrl;
+  reset_barrier(C);
+  if (threadIdx.x == 0) C->error.v[0] = 0u;
+  if (team == 0 && threadIdx.x == 0) *b.queue_head = 0u;
 }
 
 // Reset the counters of slot `slot` (one-phase mode; the fused kernels do it
@@ -638,6 +883,14 @@ hipError_t trav_init(const TravArgs &a, int sssp, unsigned long long mu0, hipStr
   hipLaunchKernelGGL(k_trav_init, dim3(grid), dim3(kBlock), 0, s, a, sssp, mu0);
   return hipGetLastError();
 }
+
+hipError_t batch_launch(const BatchArgs &b, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(b.nteams), dim3(256), 0, s, b);
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBlock), 0, s, b);
+  return hipGetLastError();
+}
+
+const void *batch_kernel() { return (const void *)k_batch; }
 
 hipError_t reset_slot(Ctrl *c, int slot, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_slot, dim3(1), dim3(64), 0, s, c, slot);

@@ -95,6 +95,8 @@ struct Params {
   int max_iters;
   float pr_d;
   int pr_iters;
+  int learned;                  // 1: the policy MLP decides (sx_policy.hpp)
+  int bins_fixed;               // 1: the caller fixed t1 / t2
 };
 
 struct TravArgs {
@@ -103,6 +105,31 @@ struct TravArgs {
   Params P;
   int *state_i;                 // BFS depth (int32) or SSSP dist (uint32) array
   int src;
+  const float *mlp;             // policy parameters (device) when P.learned
+};
+
+// Batched queries (see k_batch).
+struct BatchQuery {
+  DevGraph g;
+  int *state;                   // the query's output array
+  int algo;                     // 0 BFS, 1 SSSP
+  int src;
+  unsigned long long mu0;       // arcs not yet explored after the source
+};
+struct BatchStat {
+  int iterations, pull_iters, ballot_iters, status, team, pad;
+  unsigned long long edges, expansions;
+};
+struct BatchArgs {
+  const BatchQuery *q;
+  const int *order;             // processing order (largest first)
+  int nq;
+  const Work *work;             // [nteams] team workspaces (device)
+  int nteams, team;             // team count and workgroups per team
+  unsigned *queue_head;
+  Params P;
+  const float *mlp;
+  BatchStat *stats;             // [nq]
 };
 
 struct KArgs {

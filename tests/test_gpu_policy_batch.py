@@ -1,0 +1,179 @@
+"""GPU tests of the learned policy (MLP kernels against the fp64 oracle,
+policy independence of the results, timing collection) and of the batched
+multi-query mode (results identical to the oracle for every team size)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as ref
+import paper_1812_04070_amd as sx
+from paper_1812_04070_amd import gen
+from tests.gpu_util import announce, run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def engine():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    e = sx.Engine(0)
+    yield e
+    e.close()
+
+
+def _dev(a, eng):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(eng.device)
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(n, 8)).astype(np.float32)
+    t = np.stack([rng.integers(0, 2, n), rng.integers(0, 2, n), rng.uniform(2, 7, n),
+                  rng.uniform(7, 11, n)], 1).astype(np.float32)
+    m = (rng.random((n, 4)) < 0.8).astype(np.float32)
+    return x, t, m
+
+
+def test_mlp_forward_matches_oracle(engine):
+    import torch
+    p = ref.init_params(1).astype(np.float32)
+    x, _, _ = _data(1000, 2)
+    announce("mlp forward")
+    Y = torch.empty((1000, 4), dtype=torch.float32, device=engine.device)
+    P, X = _dev(p, engine), _dev(x, engine)
+    sx.sx_mlp_forward(engine.ctx, P.data_ptr(), X.data_ptr(), 1000, Y.data_ptr(), engine.stream())
+    y_ref, _ = ref.forward(p.astype(np.float64), x.astype(np.float64))
+    err = np.abs(Y.cpu().numpy() - y_ref).max() / np.abs(y_ref).max()
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("n", [1, 37, 4096])
+def test_mlp_grad_matches_oracle(engine, n):
+    import torch
+    p = ref.init_params(3).astype(np.float32)
+    x, t, m = _data(n, 4)
+    announce(f"mlp loss+grad n={n}")
+    P, X, T, M = (_dev(v, engine) for v in (p, x, t, m))
+    G = torch.zeros(ref.NPARAMS, dtype=torch.float32, device=engine.device)
+    L = torch.zeros(1, dtype=torch.float32, device=engine.device)
+    sx.sx_mlp_loss_grad(engine.ctx, P.data_ptr(), X.data_ptr(), T.data_ptr(), M.data_ptr(), n,
+                        L.data_ptr(), G.data_ptr(), engine.stream())
+    g_ref = ref.grad(p.astype(np.float64), x.astype(np.float64), t, m)
+    l_ref = ref.loss(p.astype(np.float64), x.astype(np.float64), t, m)
+    g = G.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(g - g_ref) <= 1e-5 * np.linalg.norm(g_ref)
+    assert abs(L.item() - l_ref) <= 1e-5 * abs(l_ref)
+
+
+def test_mlp_adam_matches_oracle(engine):
+    import torch
+    rng = np.random.default_rng(5)
+    p = ref.init_params(6).astype(np.float32)
+    g = rng.normal(size=ref.NPARAMS).astype(np.float32) * 1e-2
+    mo = rng.normal(size=ref.NPARAMS).astype(np.float32) * 1e-3
+    vo = np.abs(rng.normal(size=ref.NPARAMS)).astype(np.float32) * 1e-5
+    P, G, Mo, Vo = (_dev(v, engine) for v in (p, g, mo, vo))
+    sx.sx_mlp_adam(engine.ctx, P.data_ptr(), G.data_ptr(), Mo.data_ptr(), Vo.data_ptr(), 3, 1e-3,
+                   stream=engine.stream())
+    p2, m2, v2 = ref.adam(p.astype(np.float64), g.astype(np.float64), mo.astype(np.float64),
+                          vo.astype(np.float64), 3, lr=1e-3)
+    np.testing.assert_allclose(P.cpu().numpy(), p2, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(Mo.cpu().numpy(), m2, rtol=1e-5, atol=1e-9)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_learned_policy_keeps_results_exact(engine, seed):
+    """Any network -- here random ones -- changes only the schedule."""
+    p = (ref.init_params(seed) * 3.0).astype(np.float32)
+    sx.sx_policy_load_mlp(engine.ctx, p)
+    for name, g in [("rmat13", gen.rmat(13, seed=seed + 3, weights=(1, 64))),
+                    ("grid64", gen.grid(64, 0.1, seed=seed, weights=(1, 1000)))]:
+        src = gen.max_degree_vertex(g)
+        dg = engine.load(g)
+        for fused in (sx.SX_FUSED, sx.SX_UNFUSED):
+            pol = sx.Policy(policy=sx.SX_POLICY_LEARNED, fused=fused)
+            announce(f"learned {name} seed={seed} fused={fused}")
+            d, st = run(engine, g, sx.SX_BFS, src, pol, dg=dg)
+            np.testing.assert_array_equal(d, oracle.bfs_g(g, src))
+            x, st = run(engine, g, sx.SX_SSSP, src, pol, dg=dg)
+            np.testing.assert_array_equal(x, oracle.sssp_g(g, src))
+        dg.close()
+
+
+def test_policy_collect(engine):
+    import torch
+    g = gen.rmat(12, seed=2, weights=(1, 64))
+    src = gen.max_degree_vertex(g)
+    dg = engine.load(g)
+    out = torch.empty(g.n, dtype=torch.int32, device=engine.device)
+    for algo, ref_fn in [(sx.SX_BFS, oracle.bfs_g), (sx.SX_SSSP, oracle.sssp_g)]:
+        announce(f"collect algo={algo}")
+        f, a = sx.sx_policy_collect(engine.program(algo), dg.handle, src, out.data_ptr(), engine.stream())
+        assert len(f) >= 3 and f.shape[1] == 8 and a.shape[1] == sx.SX_POLICY_ARMS
+        assert np.all(np.isfinite(a[:, 1:])) and np.all(a[:, 1:] > 0)
+        h = engine.to_host(dg, algo, out)
+        np.testing.assert_array_equal(h, ref_fn(g, src))
+    dg.close()
+
+
+def _batch_graphs():
+    return [gen.rmat(10, seed=21, weights=(1, 64)), gen.rmat(13, seed=22, weights=(1, 64)),
+            gen.grid(48, 0.1, seed=23, weights=(1, 64)), gen.grid(100, 0.1, seed=24, weights=(1, 64)),
+            gen.random_graph(300, 0.02, seed=25, weights=(1, 64))]
+
+
+@pytest.mark.parametrize("team", [1, 4, 32])
+@pytest.mark.parametrize("learned", [False, True])
+def test_batch_matches_oracle(engine, team, learned):
+    import torch
+    graphs = _batch_graphs()
+    dgs = [engine.load(g) for g in graphs]
+    rng = np.random.default_rng(team)
+    queries, refs, outs = [], [], []
+    for i in range(24):
+        gi = i % len(graphs)
+        g = graphs[gi]
+        cand = np.nonzero(g.out_degree() > 0)[0]
+        s = int(rng.choice(cand))
+        algo = sx.SX_BFS if i % 2 == 0 else sx.SX_SSSP
+        out = torch.empty(g.n, dtype=torch.int32, device=engine.device)
+        outs.append(out)
+        queries.append((dgs[gi].handle, algo, s, out.data_ptr()))
+        refs.append((gi, algo, oracle.bfs_g(g, s) if algo == sx.SX_BFS else oracle.sssp_g(g, s)))
+    if learned:
+        sx.sx_policy_load_mlp(engine.ctx, (ref.init_params(9) * 3.0).astype(np.float32))
+    pol = sx.Policy(policy=sx.SX_POLICY_LEARNED if learned else sx.SX_POLICY_HEURISTIC).c()
+    cfg = sx.sx_batch_config(team, 0, 0)
+    announce(f"batch team={team} learned={learned}")
+    ms, stats = sx.sx_run_batch(engine.ctx, queries, pol, cfg, engine.stream())
+    assert ms > 0
+    for (gi, algo, r), out in zip(refs, outs):
+        h = engine.to_host(dgs[gi], algo, out)
+        np.testing.assert_array_equal(h, r)
+    for d in dgs:
+        d.close()
+
+
+def test_batch_autotune(engine):
+    import torch
+    graphs = _batch_graphs()[:3]
+    dgs = [engine.load(g) for g in graphs]
+    outs, queries = [], []
+    for i, g in enumerate(graphs):
+        out = torch.empty(g.n, dtype=torch.int32, device=engine.device)
+        outs.append(out)
+        queries.append((dgs[i].handle, sx.SX_SSSP, gen.max_degree_vertex(g), out.data_ptr()))
+    announce("batch autotune")
+    cfg, ms = sx.sx_batch_autotune(engine.ctx, queries, None, engine.stream())
+    assert cfg["team_wgs"] in (1, 2, 4, 8, 16, 32) and ms > 0
+    ms2, _ = sx.sx_run_batch(engine.ctx, queries, None, None, engine.stream())
+    for i, g in enumerate(graphs):
+        np.testing.assert_array_equal(engine.to_host(dgs[i], sx.SX_SSSP, outs[i]),
+                                      oracle.sssp_g(g, gen.max_degree_vertex(g)))
+    for d in dgs:
+        d.close()
