@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--scale", type=int, default=22, help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--fused", type=int, default=0, help="0 auto, 1 fused, 2 unfused")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched / learned-policy leg")
     return ap.parse_args()
 
 
@@ -87,11 +88,89 @@ def cpu_leg(g, src, ref_step_edges):
     }, (d, x, c)
 
 
+def batched_leg(eng, sx, gen, log):
+    """256 BFS/SSSP queries over 64 graphs: sequential single-query runs with
+    the heuristic policy against one batched launch (autotuned teams), with
+    the heuristic and with the learned policy.  Results must be identical."""
+    import torch
+    t0 = time.perf_counter()
+    graphs, queries = gen.batch_workload()
+    log(f"[bench] batch workload: {len(graphs)} graphs, {len(queries)} queries, gen {time.perf_counter()-t0:.1f}s")
+    dgs = [eng.load(g) for g in graphs]
+    algo = {"bfs": sx.SX_BFS, "sssp": sx.SX_SSSP}
+    outs_single = [torch.empty(graphs[gi].n, dtype=torch.int32, device=eng.device) for gi, _, _ in queries]
+    outs_batch = [torch.empty(graphs[gi].n, dtype=torch.int32, device=eng.device) for gi, _, _ in queries]
+    heur = sx.Policy()
+    # single-query form, heuristic policy: one sx_run per query, back to back
+    def singles():
+        for (gi, a, s), o in zip(queries, outs_single):
+            eng.run(dgs[gi], algo[a], s, heur, out=o)
+    singles()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        singles()
+    torch.cuda.synchronize()
+    single_ms = 1e3 * (time.perf_counter() - t0) / reps
+    qs = [(dgs[gi].handle, algo[a], s, o.data_ptr()) for (gi, a, s), o in zip(queries, outs_batch)]
+    cfg, tune_ms = sx.sx_batch_autotune(eng.ctx, qs, heur.c(), eng.stream())
+    log(f"[bench] autotuned batch config {cfg} ({tune_ms:.2f} ms)")
+
+    def batch(pol):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            ms, _ = sx.sx_run_batch(eng.ctx, qs, pol, None, eng.stream())
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / reps, ms
+
+    batch_ms, batch_dev_ms = batch(heur.c())
+    same = all(torch.equal(a, b) for a, b in zip(outs_single, outs_batch))
+    res = {"graphs": len(graphs), "queries": len(queries), "single_query_ms": round(single_ms, 3),
+           "batch_ms": round(batch_ms, 3), "batch_device_ms": round(batch_dev_ms, 3),
+           "speedup_batched_vs_single": round(single_ms / batch_ms, 3), "team_config": cfg,
+           "identical_to_single": bool(same)}
+    params = load_trained_policy()
+    if params is not None:
+        sx.sx_policy_load_mlp(eng.ctx, params)
+        lp = sx.Policy(policy=sx.SX_POLICY_LEARNED)
+        lbatch_ms, _ = batch(lp.c())
+        same_l = all(torch.equal(a, b) for a, b in zip(outs_single, outs_batch))
+        # learned policy in the single-query form as well
+        def singles_l():
+            for (gi, a, s), o in zip(queries, outs_batch):
+                eng.run(dgs[gi], algo[a], s, lp, out=o)
+        singles_l()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            singles_l()
+        torch.cuda.synchronize()
+        lsingle_ms = 1e3 * (time.perf_counter() - t0) / reps
+        same_l = same_l and all(torch.equal(a, b) for a, b in zip(outs_single, outs_batch))
+        res.update({"learned_batch_ms": round(lbatch_ms, 3), "learned_single_query_ms": round(lsingle_ms, 3),
+                    "speedup_learned_batched_vs_heuristic_single": round(single_ms / lbatch_ms, 3),
+                    "speedup_learned_vs_heuristic_single": round(single_ms / lsingle_ms, 3),
+                    "learned_identical": bool(same_l)})
+    for d in dgs:
+        d.close()
+    return res
+
+
+def load_trained_policy():
+    path = os.path.join(ROOT, "paper_1812_04070_amd", "policy_mlp.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return np.asarray(json.load(f)["params"], dtype=np.float32)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the engine has no multi-GPU "
-              "path: every GPU box here has one GPU.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the engine has no multi-GPU "
+              "path; the sharding design is described but not built.", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1812_04070_amd as sx
@@ -178,7 +257,11 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "algorithmic_bytes": nbytes, "traffic": None},
     }
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    if not args.no_batch:
+        result["batched"] = batched_leg(eng, sx, gen, log)
     if not args.no_cpu:
+        log("[bench] cpu oracle leg")
         cpu, (rd, rx, rc) = cpu_leg(g, src, step_edges)
         result["cpu_baseline"] = cpu
         result["bit_exact"] = bool(np.array_equal(d, rd) and np.array_equal(x, rx) and np.array_equal(c, rc))

@@ -141,6 +141,12 @@ struct GridBarrier {
   // returns false when the watchdog fired (this or another workgroup)
   SX_DEV bool sync() {
     const unsigned target = gen + 1;
+    if (nblk == 1) {
+      // a single workgroup: the workgroup barrier orders its global memory
+      __syncthreads();
+      gen = target;
+      return !failed();
+    }
     __syncthreads();
     bool ok = true;
     if (rank == 0) {

@@ -262,8 +262,10 @@ SX_DEV void ballot_write(const VGrid &vg, int n, const Tiling &T, Deg degree, Ve
 // Small bin: a wavefront takes 64 vertices, stages their row starts and a
 // prefix sum of their degrees in LDS, then walks the concatenated arcs 64 at
 // a time (one arc per lane), so lanes stay busy however degrees vary.
+// Worklist entries outside [0, n) are skipped (a defence: lists only ever
+// hold vertex ids, but a read never leaves the CSR).
 template <class Op>
-SX_DEV void visit_small(const int *list, unsigned cnt, const int *off, const int *idx, Op &op,
+SX_DEV void visit_small(int n, const int *list, unsigned cnt, const int *off, const int *idx, Op &op,
                         unsigned gw, unsigned nwaves, int *lds /* 3*64 per wave */) {
   const int lane = lane_id();
   int *l_v = lds, *l_beg = lds + 64, *l_ex = lds + 128;
@@ -271,9 +273,12 @@ SX_DEV void visit_small(const int *list, unsigned cnt, const int *off, const int
     const unsigned i = c * 64u + lane;
     int v = -1, beg = 0, deg = 0;
     if (i < cnt) {
-      v = list[i];
-      beg = off[v];
-      deg = off[v + 1] - beg;
+      const int x = list[i];
+      if ((unsigned)x < (unsigned)n) {
+        v = x;
+        beg = off[v];
+        deg = off[v + 1] - beg;
+      }
     }
     const int incl = wave_incl_scan(deg);
     const int total = __shfl(incl, 63);
@@ -305,11 +310,12 @@ SX_DEV void visit_small(const int *list, unsigned cnt, const int *off, const int
 
 // Medium bin: one wavefront per vertex.
 template <class Op>
-SX_DEV void visit_med(const int *list, unsigned cnt, const int *off, const int *idx, Op &op,
+SX_DEV void visit_med(int n, const int *list, unsigned cnt, const int *off, const int *idx, Op &op,
                       unsigned gw, unsigned nwaves) {
   const int lane = lane_id();
   for (unsigned i = gw; i < cnt; i += nwaves) {
     const int v = list[i];
+    if ((unsigned)v >= (unsigned)n) continue;
     const int beg = off[v], end = off[v + 1];
     for (int a = beg; a < end; a += 64) {
       const int arc = a + lane;
@@ -322,11 +328,12 @@ SX_DEV void visit_med(const int *list, unsigned cnt, const int *off, const int *
 
 // Large bin: one workgroup per item (a chunk of `chunk` arcs of one vertex).
 template <class Op>
-SX_DEV void visit_large(const VGrid &vg, const unsigned long long *list, unsigned cnt, const int *off,
-                        const int *idx, int chunk, Op &op) {
+SX_DEV void visit_large(const VGrid &vg, int n, const unsigned long long *list, unsigned cnt,
+                        const int *off, const int *idx, int chunk, Op &op) {
   for (unsigned i = vg.bid; i < cnt; i += vg.nb) {
     const unsigned long long it = list[i];
     const int v = (int)(it & 0xffffffffu);
+    if ((unsigned)v >= (unsigned)n) continue;
     const int c = (int)(it >> 32);
     const int vb = off[v], ve = off[v + 1];
     const long long b0 = (long long)vb + (long long)c * chunk;

@@ -511,9 +511,10 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
       } else {
         HIP_TRY(trav_launch(TK_PULL_SCAN, sssp, a, it, grid, st));
         HIP_TRY(reset_slot(G->w.ctrl, (it + 1) % 3, st));
+        HIP_TRY(reset_slot(G->w.ctrl, (it + 2) % 3, st));
         HIP_TRY(trav_launch(TK_PULL_LISTS, sssp, a, it, grid, st));
         HIP_TRY(trav_launch(TK_PULL_STEP, sssp, a, it, grid, st));
-        launches += 4;
+        launches += 5;
       }
       sx_status s = read_ctrl(G, st);
       if (s != SX_OK) return s;
@@ -766,6 +767,7 @@ extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_
     } else {
       HIP_TRY(trav_launch(TK_PULL_SCAN, sssp, a, it, grid, st));
       HIP_TRY(reset_slot(G->w.ctrl, (it + 1) % 3, st));
+      HIP_TRY(reset_slot(G->w.ctrl, (it + 2) % 3, st));
       HIP_TRY(trav_launch(TK_PULL_LISTS, sssp, a, it, grid, st));
       HIP_TRY(trav_launch(TK_PULL_STEP, sssp, a, it, grid, st));
     }

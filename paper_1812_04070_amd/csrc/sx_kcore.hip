@@ -138,11 +138,19 @@ SX_DEV void kpeel(const KArgs &a, int k, int qp, int slot, LdsK &lds) {
   // mark the frontier deleted with core number k
   {
     const unsigned tid = blockIdx.x * kBlock + threadIdx.x, nt = gridDim.x * kBlock;
-    for (unsigned i = tid; i < cs; i += nt) a.core[w.q[qp][0][i]] = k;
-    for (unsigned i = tid; i < cm; i += nt) a.core[w.q[qp][1][i]] = k;
+    const unsigned un = (unsigned)g.n;
+    for (unsigned i = tid; i < cs; i += nt) {
+      const int v = w.q[qp][0][i];
+      if ((unsigned)v < un) a.core[v] = k;
+    }
+    for (unsigned i = tid; i < cm; i += nt) {
+      const int v = w.q[qp][1][i];
+      if ((unsigned)v < un) a.core[v] = k;
+    }
     for (unsigned i = tid; i < cl; i += nt) {
       const unsigned long long it = w.ql[qp][i];
-      if ((it >> 32) == 0) a.core[(int)(it & 0xffffffffu)] = k;
+      const unsigned v = (unsigned)(it & 0xffffffffu);
+      if ((it >> 32) == 0 && v < un) a.core[v] = k;
     }
   }
   Lists NL;
@@ -174,9 +182,9 @@ SX_DEV void kpeel(const KArgs &a, int k, int qp, int slot, LdsK &lds) {
   for (int pass = 0; pass < (g.directed ? 2 : 1); ++pass) {
     const int *off = pass ? g.in_off : g.off;
     const int *idx = pass ? g.in_idx : g.idx;
-    visit_large(hw_grid(), w.ql[qp], cl, off, idx, a.P.chunk, op);
-    visit_med(w.q[qp][1], cm, off, idx, op, gw, nw);
-    visit_small(w.q[qp][0], cs, off, idx, op, gw, nw, lds.small[wave_in_wg()]);
+    visit_large(hw_grid(), g.n, w.ql[qp], cl, off, idx, a.P.chunk, op);
+    visit_med(g.n, w.q[qp][1], cm, off, idx, op, gw, nw);
+    visit_small(g.n, w.q[qp][0], cs, off, idx, op, gw, nw, lds.small[wave_in_wg()]);
   }
   flush_stats(st, nxt);
   const long long e = wave_sum_ll(edges);

@@ -122,6 +122,7 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const unsigned cnt[3], LdsPr &l
   // one workgroup per large vertex
   for (unsigned i = blockIdx.x; i < cnt[2]; i += gridDim.x) {
     const int v = (int)(w.ql[0][i] & 0xffffffffu);
+    if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
     for (int e = beg + (int)threadIdx.x; e < end; e += kBlock) { cadd(s, src[ii[e]]); ++edges; }
@@ -133,6 +134,7 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const unsigned cnt[3], LdsPr &l
   // one wavefront per medium vertex
   for (unsigned i = gw; i < cnt[1]; i += nw) {
     const int v = w.q[0][1][i];
+    if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
     for (int e = beg + lane; e < end; e += 64) { cadd(s, src[ii[e]]); ++edges; }
@@ -142,6 +144,7 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const unsigned cnt[3], LdsPr &l
   // one lane per small vertex
   for (unsigned i = gw * 64u + lane; i < cnt[0] + 0u; i += nw * 64u) {
     const int v = w.q[0][0][i];
+    if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
     for (int e = beg; e < end; ++e) cadd(s, src[ii[e]]);

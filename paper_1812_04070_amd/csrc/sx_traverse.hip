@@ -66,6 +66,13 @@ struct SsspOps {
   SX_DEV bool pull_candidate(int v) const { (void)v; return true; }
 };
 
+SX_DEV void reset_counters(Counters *q) {
+  for (int b = 0; b < NBINS; ++b) store_relaxed(&q->cnt[b], 0u);
+  store_relaxed(&q->nf, 0u);
+  store_relaxed(&q->mf, 0ull);
+  store_relaxed(&q->overflow, 0u);
+}
+
 SX_DEV int degree_of(const int *off, int v) { return off[v + 1] - off[v]; }
 
 SX_DEV Lists lists_for(const Work &w, int parity, Counters *c) {
@@ -123,9 +130,9 @@ SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   };
   const unsigned gw = vg.bid * kWaves + wave_in_wg();
   const unsigned nw = vg.nb * kWaves;
-  visit_large(vg, a.w.ql[p], cl, g.off, g.idx, P.chunk, op);
-  visit_med(a.w.q[p][1], cm, g.off, g.idx, op, gw, nw);
-  visit_small(a.w.q[p][0], cs, g.off, g.idx, op, gw, nw, lds.small[wave_in_wg()]);
+  visit_large(vg, g.n, a.w.ql[p], cl, g.off, g.idx, P.chunk, op);
+  visit_med(g.n, a.w.q[p][1], cm, g.off, g.idx, op, gw, nw);
+  visit_small(g.n, a.w.q[p][0], cs, g.off, g.idx, op, gw, nw, lds.small[wave_in_wg()]);
   flush_stats(st, nxt);
   const long long e = wave_sum_ll(edges);
   if (lane_id() == 0) {
@@ -243,6 +250,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   // One workgroup per large candidate
   for (unsigned i = vg.bid; i < cl; i += vg.nb) {
     const int v = (int)(a.w.ql[p][i] & 0xffffffffu);
+    if ((unsigned)v >= (unsigned)g.n) continue;
     const int beg = g.in_off[v], end = g.in_off[v + 1];
     unsigned best = 0xFFFFFFFFu;
     if (!Ops::kVote) best = load_relaxed(&((unsigned *)a.state_i)[v]);
@@ -288,6 +296,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   // One wavefront per medium candidate
   for (unsigned i = gw; i < cm; i += nw) {
     const int v = a.w.q[p][1][i];
+    if ((unsigned)v >= (unsigned)g.n) continue;
     const int beg = g.in_off[v], end = g.in_off[v + 1];
     unsigned best = 0xFFFFFFFFu;
     bool found = false;
@@ -325,7 +334,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
     const unsigned i = c0 + lane;
     bool act = false;
     int v = 0, d = 0;
-    if (i < cs) {
+    if (i < cs && (unsigned)a.w.q[p][0][i] < (unsigned)g.n) {
       v = a.w.q[p][0][i];
       const int beg = g.in_off[v], end = g.in_off[v + 1];
       d = end - beg;
@@ -531,11 +540,10 @@ __global__ void __launch_bounds__(kBlock) k_pull_fused(TravArgs a) {
     pull_scan(vg, a, s.P, ops, lds);
     if (!bar.sync()) { finish(vg, C, EXIT_ERROR, s); return; }
     if (vg.bid == 0 && threadIdx.x == 0) {
-      Counters *nx = &C->q[(s.it + 1) % 3];
-      for (int b = 0; b < NBINS; ++b) store_relaxed(&nx->cnt[b], 0u);
-      store_relaxed(&nx->nf, 0u);
-      store_relaxed(&nx->mf, 0ull);
-      store_relaxed(&nx->overflow, 0u);
+      // this iteration appends to slot it+1; a push iteration that may follow
+      // appends to slot it+2: both start empty (nobody reads either now)
+      reset_counters(&C->q[(s.it + 1) % 3]);
+      reset_counters(&C->q[(s.it + 2) % 3]);
       atomic_add_u32(&C->stats.v[6], 1u);
     }
     pull_lists(vg, a, s.it, lds);
@@ -603,13 +611,6 @@ __global__ void __launch_bounds__(kBlock) k_pull_step(TravArgs a, int it) {
 // -- both directions inside one kernel, switching in place -- synchronised by
 // a barrier over the team only, then takes the next.  Teams never wait for
 // each other, so a 6-level R-MAT query and a 4,000-level grid query overlap.
-
-SX_DEV void reset_counters(Counters *q) {
-  for (int b = 0; b < NBINS; ++b) store_relaxed(&q->cnt[b], 0u);
-  store_relaxed(&q->nf, 0u);
-  store_relaxed(&q->mf, 0ull);
-  store_relaxed(&q->overflow, 0u);
-}
 
 // Initialise one query on the team: vertex state, stamps, counters, the
 // source as the first list.  Ends with a team barrier.
@@ -679,6 +680,7 @@ SX_DEV bool batch_query(const VGrid &vg, const TravArgs &a, GridBarrier &bar, Ld
       if (!bar.sync()) return false;
       if (vg.bid == 0 && threadIdx.x == 0) {
         reset_counters(&C->q[(s.it + 1) % 3]);
+        reset_counters(&C->q[(s.it + 2) % 3]);
         atomic_add_u32(&C->stats.v[6], 1u);
       }
       pull_lists(vg, a, s.it, lds);

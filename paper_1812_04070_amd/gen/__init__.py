@@ -249,3 +249,32 @@ def workload_graph(name: str, scale_override: Optional[int] = None, side_overrid
     if name == "rmat24d":
         return rmat(scale_override or 24, seed=4, directed=True)
     raise KeyError(name)
+
+
+def batch_workload(n_rmat: int = 48, n_grid: int = 16, n_queries: int = 256, scale_range=(12, 20),
+                   side_range=(256, 2048), seed: int = 1000):
+    """The batched workload: n_rmat undirected R-MAT graphs (edge factor 16,
+    scales uniform in scale_range) and n_grid grids (sides uniform in
+    side_range, 10 % of edges deleted), all with weights in [1, 64]; then
+    n_queries queries with sources drawn uniformly over non-isolated vertices
+    of a uniformly chosen graph, alternating BFS and SSSP.
+    Graph i uses seed `seed + i`.  Returns (graphs, queries) with queries as
+    (graph index, 'bfs' | 'sssp', source)."""
+    rng = np.random.default_rng(seed)
+    graphs = []
+    for i in range(n_rmat):
+        s = int(rng.integers(scale_range[0], scale_range[1] + 1))
+        graphs.append(rmat(s, seed=seed + i, weights=(1, 64), weight_seed=seed + 5000 + i))
+    for j in range(n_grid):
+        side = int(rng.integers(side_range[0], side_range[1] + 1))
+        graphs.append(grid(side, 0.1, seed=seed + n_rmat + j, weights=(1, 64),
+                           weight_seed=seed + 6000 + j))
+    qrng = np.random.default_rng(7)
+    queries = []
+    for k in range(n_queries):
+        gi = int(qrng.integers(0, len(graphs)))
+        deg = graphs[gi].out_degree()
+        cand = np.flatnonzero(deg > 0)
+        src = int(cand[qrng.integers(0, len(cand))])
+        queries.append((gi, "bfs" if k % 2 == 0 else "sssp", src))
+    return graphs, queries

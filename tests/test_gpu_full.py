@@ -1,0 +1,81 @@
+"""Parity at the full workload sizes, in the configuration bench.py times:
+R-MAT scale 22 (BFS, SSSP, k-core), the 4096^2 grid (BFS, SSSP) and the
+directed R-MAT scale 24 (PageRank within 1e-6 relative L1, k-core).  The
+oracle computes every output element (serial C, seconds per run)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1812_04070_amd as sx
+from paper_1812_04070_amd import gen
+from tests.gpu_util import announce, rel_l1, run
+from tests import pins
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def engine():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    e = sx.Engine(0)
+    yield e
+    e.close()
+
+
+def test_rmat22(engine):
+    g = gen.workload_graph("rmat22")
+    src = gen.max_degree_vertex(g)
+    dg = engine.load(g)
+    announce("rmat22 bfs")
+    d, st = run(engine, g, sx.SX_BFS, src, dg=dg)
+    ref_d = oracle.bfs_g(g, src)
+    np.testing.assert_array_equal(d, ref_d)
+    announce("rmat22 sssp")
+    x, st = run(engine, g, sx.SX_SSSP, src, dg=dg)
+    np.testing.assert_array_equal(x, oracle.sssp_g(g, src))
+    announce("rmat22 kcore")
+    c, st = run(engine, g, sx.SX_KCORE, dg=dg)
+    np.testing.assert_array_equal(c, oracle.kcore_g(g))
+    # the forced arms give the same bytes at full size too
+    for name, pol in [("push-only", sx.Policy(direction=sx.SX_DIR_PUSH)),
+                      ("unfused", sx.Policy(fused=sx.SX_UNFUSED))]:
+        announce(f"rmat22 bfs {name}")
+        d2, _ = run(engine, g, sx.SX_BFS, src, pol, dg=dg)
+        np.testing.assert_array_equal(d2, ref_d)
+    dg.close()
+
+
+def test_grid4096(engine):
+    g = gen.workload_graph("grid4096")
+    dg = engine.load(g)
+    announce("grid4096 bfs")
+    d, st = run(engine, g, sx.SX_BFS, 0, dg=dg)
+    np.testing.assert_array_equal(d, oracle.bfs_g(g, 0))
+    assert st["iterations"] >= 8000
+    announce("grid4096 sssp")
+    x, st = run(engine, g, sx.SX_SSSP, 0, dg=dg)
+    ref = oracle.sssp_g(g, 0)
+    np.testing.assert_array_equal(x, ref)
+    dg.close()
+
+
+def test_rmat24_directed(engine):
+    g = gen.workload_graph("rmat24d")
+    dg = engine.load(g)
+    announce("rmat24d pagerank")
+    r, st = run(engine, g, sx.SX_PAGERANK, dg=dg)
+    ref = oracle.pagerank_g(g)
+    err = rel_l1(r, ref)
+    print(f"pagerank s24 rel L1 = {err:.3e}, {st['device_ms']:.2f} ms", flush=True)
+    assert err <= 1e-6
+    assert abs(float(r.astype(np.float64).sum()) - 1.0) < 1e-4
+    announce("rmat24d kcore")
+    c, st = run(engine, g, sx.SX_KCORE, dg=dg)
+    ref_c = oracle.kcore_g(g)
+    np.testing.assert_array_equal(c, ref_c)
+    pins.kcore_certificate_fast(g.n, g.offsets, g.indices, c, g.in_offsets, g.in_indices)
+    dg.close()
