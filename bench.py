@@ -107,12 +107,14 @@ def batched_leg(eng, sx, gen, log):
             eng.run(dgs[gi], algo[a], s, heur, out=o)
     singles()
     torch.cuda.synchronize()
-    reps = 3
+    log("[bench] batch: single-query warm-up done")
+    reps = 1
     t0 = time.perf_counter()
     for _ in range(reps):
         singles()
     torch.cuda.synchronize()
     single_ms = 1e3 * (time.perf_counter() - t0) / reps
+    log(f"[bench] batch: single-query form {single_ms:.1f} ms")
     qs = [(dgs[gi].handle, algo[a], s, o.data_ptr()) for (gi, a, s), o in zip(queries, outs_batch)]
     cfg, tune_ms = sx.sx_batch_autotune(eng.ctx, qs, heur.c(), eng.stream())
     log(f"[bench] autotuned batch config {cfg} ({tune_ms:.2f} ms)")
@@ -126,6 +128,7 @@ def batched_leg(eng, sx, gen, log):
         return 1e3 * (time.perf_counter() - t) / reps, ms
 
     batch_ms, batch_dev_ms = batch(heur.c())
+    log(f"[bench] batch: batched form {batch_ms:.1f} ms")
     same = all(torch.equal(a, b) for a, b in zip(outs_single, outs_batch))
     res = {"graphs": len(graphs), "queries": len(queries), "single_query_ms": round(single_ms, 3),
            "batch_ms": round(batch_ms, 3), "batch_device_ms": round(batch_dev_ms, 3),

@@ -128,13 +128,18 @@ void sx_program_destroy(sx_program *p);
  *  bin_large  degree from which a workgroup takes chunks of a vertex (256)
  *  online_cap online-filter capacity in entries per wavefront of the grid
  *             (default 64, the paper's overflow threshold)
- *  fused      SX_FUSED (persistent kernels + global barrier, Section 5) |
- *             SX_UNFUSED (one launch per phase and iteration) | 0 = auto
+ *  fused      SX_FUSED (persistent kernels + software global barrier,
+ *             Section 5) | SX_UNFUSED (one launch per phase and iteration,
+ *             the host deciding between launches) | SX_SEQUENCED (one launch
+ *             per phase, decisions taken on the device at the start of the
+ *             next launch, launches enqueued ahead: the kernel boundary is
+ *             the global barrier) | 0 = auto (sequenced for BFS, SSSP and
+ *             k-core, fused for PageRank)
  *  policy     SX_POLICY_HEURISTIC | SX_POLICY_LEARNED (MLP; needs
  *             sx_policy_load_mlp first)                                       */
 enum { SX_DIR_AUTO = 0, SX_DIR_PUSH = 1, SX_DIR_PULL = 2 };
 enum { SX_FILTER_JIT = 0, SX_FILTER_ONLINE = 1, SX_FILTER_BALLOT = 2 };
-enum { SX_FUSE_AUTO = 0, SX_FUSED = 1, SX_UNFUSED = 2 };
+enum { SX_FUSE_AUTO = 0, SX_FUSED = 1, SX_UNFUSED = 2, SX_SEQUENCED = 3 };
 enum { SX_POLICY_HEURISTIC = 0, SX_POLICY_LEARNED = 1 };
 
 typedef struct {

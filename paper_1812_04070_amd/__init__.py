@@ -33,7 +33,7 @@ SX_BFS, SX_SSSP, SX_KCORE, SX_PAGERANK = 0, 1, 2, 3
 # policy enums
 SX_DIR_AUTO, SX_DIR_PUSH, SX_DIR_PULL = 0, 1, 2
 SX_FILTER_JIT, SX_FILTER_ONLINE, SX_FILTER_BALLOT = 0, 1, 2
-SX_FUSE_AUTO, SX_FUSED, SX_UNFUSED = 0, 1, 2
+SX_FUSE_AUTO, SX_FUSED, SX_UNFUSED, SX_SEQUENCED = 0, 1, 2, 3
 SX_POLICY_HEURISTIC, SX_POLICY_LEARNED = 0, 1
 
 ALGOS = {"bfs": SX_BFS, "sssp": SX_SSSP, "kcore": SX_KCORE, "pagerank": SX_PAGERANK}

@@ -366,7 +366,7 @@ extern "C" sx_status sx_program_set_policy(sx_program *p, const sx_policy *pol) 
   if (!p || !pol) return fail(SX_EINVAL, "NULL argument");
   if (pol->direction < 0 || pol->direction > 2) return fail(SX_EINVAL, "bad direction");
   if (pol->filter < 0 || pol->filter > 2) return fail(SX_EINVAL, "bad filter");
-  if (pol->fused < 0 || pol->fused > 2) return fail(SX_EINVAL, "bad fused");
+  if (pol->fused < 0 || pol->fused > 3) return fail(SX_EINVAL, "bad fused");
   if (pol->policy < 0 || pol->policy > 1) return fail(SX_EINVAL, "bad policy");
   if (pol->bin_small < 0 || pol->bin_large < 0 || pol->online_cap < 0 || pol->grid_wgs < 0)
     return fail(SX_EINVAL, "negative policy field");
@@ -457,9 +457,13 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
                                sx_run_stats *stats) {
   const int sssp = p->ap.algo == SX_SSSP;
   sx_ctx *ctx = p->ctx;
-  const bool fused = p->pol.fused != SX_UNFUSED;
+  const bool fused = p->pol.fused == SX_FUSED;
+  const bool sequenced = p->pol.fused == SX_SEQUENCED || p->pol.fused == SX_FUSE_AUTO;
   int grid;
-  if (fused) {
+  if (sequenced) {
+    grid = plain_grid(ctx, seq_kernel(sssp));
+    if (p->pol.grid_wgs > 0) grid = std::min(grid, p->pol.grid_wgs);
+  } else if (fused) {
     grid = std::min(persistent_grid(ctx, trav_kernel(TK_PUSH_FUSED, sssp), p->pol.grid_wgs),
                     persistent_grid(ctx, trav_kernel(TK_PULL_FUSED, sssp), p->pol.grid_wgs));
   } else {
@@ -475,16 +479,32 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   a.src = src;
   a.mlp = ctx->d_mlp;
   if (a.P.learned && !ctx->d_mlp) return fail(SX_ESTATE, "learned policy without loaded MLP");
-  // unexplored arcs (BFS direction rule)
-  int h_off[2] = {0, 0};
-  HIP_TRY(hipMemcpyAsync(h_off, G->g.off + src, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  unsigned long long mu = (unsigned long long)(G->g.m - (h_off[1] - h_off[0]));
+  // unexplored arcs (BFS direction rule): computed on the device by the
+  // initialisation kernel; the one-phase loop reads it back below
+  unsigned long long mu = 0;
   int launches = 0;
   HIP_TRY(hipEventRecord(G->ev0, st));
-  HIP_TRY(trav_init(a, sssp, mu, st));
+  HIP_TRY(trav_init(a, sssp, 0ull, st));
   ++launches;
-  if (fused) {
+  if (sequenced) {
+    HIP_TRY(seq_start(G->w.ctrl, p->pol.direction == SX_DIR_PULL, st));
+    unsigned L = 0;
+    int batch = 8;
+    for (;;) {
+      for (int k = 0; k < batch; ++k) HIP_TRY(seq_launch(sssp, a, L++, grid, st));
+      launches += batch;
+      HIP_TRY(hipEventRecord(G->ev1, st));
+      sx_status s = read_ctrl(G, st);
+      if (s != SX_OK) return s;
+      s = ctrl_error(G->h_ctrl);
+      if (s != SX_OK) return s;
+      const unsigned ph = G->h_ctrl->seq[L & 1].v[0];
+      if (ph == SEQ_LIMIT) return fail(SX_EHIP, "iteration limit reached (engine bug)");
+      if (ph >= SEQ_DONE) break;
+      batch = std::min(batch * 2, 64);
+      if (L > (unsigned)(8 * (long long)G->g.n + 1024)) return fail(SX_EHIP, "run did not converge");
+    }
+  } else if (fused) {
     bool pull_next = p->pol.direction == SX_DIR_PULL;
     for (int batch = 0;; ++batch) {
       for (int k = 0; k < 4; ++k) {
@@ -503,6 +523,11 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   } else {
     bool pulling = p->pol.direction == SX_DIR_PULL;
     PolicyState ps{0u, 0ull};
+    {
+      sx_status s0 = read_ctrl(G, st);
+      if (s0 != SX_OK) return s0;
+      mu = *(const unsigned long long *)&G->h_ctrl->state.v[6];
+    }
     for (int it = 0;; ++it) {
       if (!pulling) {
         HIP_TRY(reset_slot(G->w.ctrl, (it + 2) % 3, st));
@@ -578,7 +603,10 @@ static sx_status run_kcore(sx_program *p, sx_graph *G, void *d_out, hipStream_t 
     if (stats) memset(stats, 0, sizeof *stats);
     return SX_OK;
   }
-  const int grid = persistent_grid(p->ctx, kcore_kernel(), p->pol.grid_wgs);
+  const bool sequenced = p->pol.fused != SX_FUSED;
+  const int grid = sequenced ? std::min(plain_grid(p->ctx, kcore_seq_kernel()),
+                                        p->pol.grid_wgs > 0 ? p->pol.grid_wgs : kMaxGrid)
+                             : persistent_grid(p->ctx, kcore_kernel(), p->pol.grid_wgs);
   KArgs a;
   memset(&a, 0, sizeof a);
   a.g = G->g;
@@ -589,6 +617,29 @@ static sx_status run_kcore(sx_program *p, sx_graph *G, void *d_out, hipStream_t 
   HIP_TRY(hipEventRecord(G->ev0, st));
   HIP_TRY(kcore_launch(a, grid, st, true));
   ++launches;
+  if (sequenced) {
+    HIP_TRY(kcore_seq_launch(a, 0, grid, st, true));
+    unsigned L = 0;
+    int batch = 16;
+    for (;;) {
+      for (int k = 0; k < batch; ++k) HIP_TRY(kcore_seq_launch(a, L++, grid, st, false));
+      launches += batch;
+      HIP_TRY(hipEventRecord(G->ev1, st));
+      sx_status s = read_ctrl(G, st);
+      if (s != SX_OK) return s;
+      s = ctrl_error(G->h_ctrl);
+      if (s != SX_OK) return s;
+      const unsigned ph = G->h_ctrl->seq[L & 1].v[0];
+      if (ph == SEQ_LIMIT) return fail(SX_EHIP, "k-core step limit reached (engine bug)");
+      if (ph >= SEQ_DONE) break;
+      batch = std::min(batch * 2, 256);
+    }
+    HIP_TRY(hipEventSynchronize(G->ev1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
+    fill_stats(G->h_ctrl, launches, ms, stats);
+    return SX_OK;
+  }
   for (;;) {
     HIP_TRY(kcore_launch(a, grid, st, false));
     ++launches;

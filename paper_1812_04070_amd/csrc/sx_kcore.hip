@@ -258,6 +258,93 @@ __global__ void __launch_bounds__(kBlock) k_kcore_fused(KArgs a) {
   }
 }
 
+// Sequenced form of the same loop: one launch per phase (scan pass 1, scan
+// pass 2, peel), the decision taken at the start of the launch after a
+// scan or a peel; launch L reads Ctrl::seq[L & 1] and writes seq[(L+1) & 1]:
+// [0] phase [1] k [2] scan number [3] step [4] decision due (1 after a scan,
+// 2 after a peel).
+enum : unsigned { KP_SCAN1 = 0, KP_SCAN2 = 1, KP_PEEL = 2, KP_DONE = 6, KP_ERROR = 7, KP_LIMIT = 8 };
+
+__global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
+  __shared__ LdsK lds;
+  Ctrl *C = a.w.ctrl;
+  const Line &in = C->seq[L & 1];
+  Line &out = C->seq[(L + 1) & 1];
+  unsigned phase = load_relaxed(&in.v[0]);
+  int k = (int)load_relaxed(&in.v[1]);
+  int scan_no = (int)load_relaxed(&in.v[2]);
+  int step = (int)load_relaxed(&in.v[3]);
+  unsigned due = load_relaxed(&in.v[4]);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  auto save = [&](unsigned ph) {
+    if (lead) {
+      store_relaxed(&out.v[0], ph);
+      store_relaxed(&out.v[1], (unsigned)k);
+      store_relaxed(&out.v[2], (unsigned)scan_no);
+      store_relaxed(&out.v[3], (unsigned)step);
+      store_relaxed(&out.v[4], due);
+    }
+  };
+  if (phase >= KP_DONE) { save(phase); return; }
+  if (load_relaxed(&C->error.v[0])) { due = 0; save(KP_ERROR); return; }
+  if (step > 4 * a.g.n + 64) { due = 0; save(KP_LIMIT); return; }
+  if (due == 1) {
+    // after a scan (scan_no already advanced): frontier of the level or a jump
+    const int s_prev = scan_no - 1;
+    Counters *q = &C->q[(step + 1) % 3];
+    const unsigned nfr = load_relaxed(&q->nf);
+    const unsigned survivors = load_relaxed(&C->aux.v[(s_prev + 1) % 3]);
+    const unsigned mind = load_relaxed(&C->aux.v[3 + s_prev % 3]);
+    if (nfr == 0) {
+      if (survivors == 0) { due = 0; save(KP_DONE); return; }
+      k = (int)mind > k + 1 ? (int)mind : k + 1;
+      phase = KP_SCAN1;
+    } else {
+      phase = KP_PEEL;
+      ++step;
+    }
+    due = 0;
+  } else if (due == 2) {
+    Counters *nx = &C->q[(step % 3 + 1) % 3];
+    const unsigned nf = load_relaxed(&nx->nf);
+    const unsigned ovf = load_relaxed(&nx->overflow);
+    if (nf == 0) { ++k; phase = KP_SCAN1; }
+    else if (ovf || a.P.filter == 2) phase = KP_SCAN1;
+    else { phase = KP_PEEL; ++step; }
+    due = 0;
+  }
+  switch (phase) {
+    case KP_SCAN1:
+      kscan_pass1(a, k, scan_no, lds);
+      save(KP_SCAN2);
+      return;
+    case KP_SCAN2:
+      kscan_pass2(a, (step + 1) & 1, (step + 1) % 3, scan_no, lds);
+      ++scan_no;
+      due = 1;
+      save(KP_SCAN2);
+      return;
+    case KP_PEEL:
+      kpeel(a, k, step & 1, step % 3, lds);
+      if (lead) atomic_add_u32(&C->stats.v[6], 1u);
+      due = 2;
+      save(KP_PEEL);
+      return;
+  }
+}
+
+__global__ void k_kcore_seq_start(Ctrl *C) {
+  if (threadIdx.x < 32) C->seq[0].v[threadIdx.x] = 0u;   // scan 1 of level 0
+}
+
+hipError_t kcore_seq_launch(const KArgs &a, unsigned L, int grid, hipStream_t s, bool start) {
+  if (start) hipLaunchKernelGGL(k_kcore_seq_start, dim3(1), dim3(64), 0, s, a.w.ctrl);
+  else hipLaunchKernelGGL(k_kcore_seq, dim3(grid), dim3(kBlock), 0, s, a, L);
+  return hipGetLastError();
+}
+
+const void *kcore_seq_kernel() { return (const void *)k_kcore_seq; }
+
 __global__ void k_kcore_init(KArgs a) {
   const int n = a.g.n;
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;

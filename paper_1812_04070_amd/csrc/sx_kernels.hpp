@@ -15,10 +15,17 @@ hipError_t trav_launch(int kind, int sssp, const TravArgs &a, int it, int grid, 
 hipError_t trav_init(const TravArgs &a, int sssp, unsigned long long mu0, hipStream_t s);
 hipError_t reset_slot(Ctrl *c, int slot, hipStream_t s);
 hipError_t batch_launch(const BatchArgs &b, int grid, hipStream_t s);
+hipError_t seq_start(Ctrl *c, bool pull_first, hipStream_t s);
+hipError_t seq_launch(int sssp, const TravArgs &a, unsigned L, int grid, hipStream_t s);
+const void *seq_kernel(int sssp);
+// phases of the sequenced mode (Ctrl::seq[..].v[0])
+enum : unsigned { SEQ_DONE = 6, SEQ_ERROR = 7, SEQ_LIMIT = 8 };
 const void *batch_kernel();
 
 hipError_t kcore_launch(const KArgs &a, int grid, hipStream_t s, bool init);
 const void *kcore_kernel();
+hipError_t kcore_seq_launch(const KArgs &a, unsigned L, int grid, hipStream_t s, bool start);
+const void *kcore_seq_kernel();
 
 hipError_t pagerank_launch(const PrArgs &a, int grid, hipStream_t s);
 const void *pagerank_kernel();

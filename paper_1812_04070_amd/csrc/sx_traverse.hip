@@ -338,20 +338,47 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
       v = a.w.q[p][0][i];
       const int beg = g.in_off[v], end = g.in_off[v + 1];
       d = end - beg;
+      // four in-arcs per round: their ids and bitmap words are loaded
+      // independently, so a lane waits for two memory round trips per four
+      // arcs instead of per arc
       if (Ops::kVote) {
-        for (int arc = beg; arc < end; ++arc) {
+        int arc = beg;
+        for (; arc + 4 <= end; arc += 4) {
+          const int u0 = g.in_idx[arc], u1 = g.in_idx[arc + 1], u2 = g.in_idx[arc + 2],
+                    u3 = g.in_idx[arc + 3];
+          edges += 4;
+          if (fbit(fb, u0) | fbit(fb, u1) | fbit(fb, u2) | fbit(fb, u3)) { act = true; break; }
+        }
+        for (; !act && arc < end; ++arc) {
           ++edges;
-          if (fbit(fb, g.in_idx[arc])) { act = true; break; }
+          if (fbit(fb, g.in_idx[arc])) act = true;
         }
         if (act) store_relaxed(&a.state_i[v], it + 1);
       } else {
         unsigned best = load_relaxed(&((unsigned *)a.state_i)[v]);
         const unsigned old = best;
-        for (int arc = beg; arc < end; ++arc) {
+        const unsigned *dist = (const unsigned *)a.state_i;
+        int arc = beg;
+        for (; arc + 4 <= end; arc += 4) {
+          int u[4];
+          bool h[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) u[j] = g.in_idx[arc + j];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) h[j] = fbit(fb, u[j]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (h[j]) {
+              const unsigned c = load_relaxed(&dist[u[j]]) + g.in_w[arc + j];
+              best = c < best ? c : best;
+            }
+          edges += 4;
+        }
+        for (; arc < end; ++arc) {
           ++edges;
-          const int u = g.in_idx[arc];
-          if (fbit(fb, u)) {
-            const unsigned c = load_relaxed(&((unsigned *)a.state_i)[u]) + g.in_w[arc];
+          const int u1 = g.in_idx[arc];
+          if (fbit(fb, u1)) {
+            const unsigned c = load_relaxed(&dist[u1]) + g.in_w[arc];
             best = c < best ? c : best;
           }
         }
@@ -601,6 +628,166 @@ __global__ void __launch_bounds__(kBlock) k_pull_step(TravArgs a, int it) {
   pull_phase(vg, a, a.P, ops, it, lds);
 }
 
+// ------------------------------------------------------ sequenced mode ---
+// The fused loop of Section 5 with the kernel boundary as its global
+// barrier: every launch runs exactly one phase and hands the run state to
+// the next launch through Ctrl::seq (launch L reads seq[L & 1] and writes
+// seq[(L + 1) & 1]).  After a compute phase the next launch first takes the
+// decision -- every workgroup reads the same counters and decides the same
+// way, as after a barrier -- and then runs the phase it chose.  The host
+// enqueues launches ahead in batches and reads the state only between
+// batches, so there is no host round trip per iteration, the per-phase
+// synchronisation costs one kernel boundary (~2.5 us on MI355X, against
+// ~6-10 us for a software barrier over a full persistent grid) and each
+// phase runs at the occupancy of its own small register budget.
+enum : unsigned {
+  PH_PUSH = 0, PH_BALLOT1 = 1, PH_BALLOT2 = 2, PH_PULL_SCAN = 3, PH_PULL_LISTS = 4,
+  PH_PULL = 5, PH_DONE = 6, PH_ERROR = 7, PH_LIMIT = 8
+};
+// seq line layout: [0] phase [1] iteration [2,3] unexplored arcs [4] previous
+// frontier size [6,7] activated so far [8] t1 [9] t2 [10] pulling [11] a
+// decision is due before the phase
+struct SeqState {
+  unsigned phase, it, pulling, decide;
+  unsigned long long mu, reached;
+  unsigned nf_prev, t1, t2;
+};
+SX_DEV SeqState seq_load(const Line &l) {
+  SeqState s;
+  s.phase = load_relaxed(&l.v[0]);
+  s.it = load_relaxed(&l.v[1]);
+  s.mu = load_relaxed((const unsigned long long *)&l.v[2]);
+  s.nf_prev = load_relaxed(&l.v[4]);
+  s.reached = load_relaxed((const unsigned long long *)&l.v[6]);
+  s.t1 = load_relaxed(&l.v[8]);
+  s.t2 = load_relaxed(&l.v[9]);
+  s.pulling = load_relaxed(&l.v[10]);
+  s.decide = load_relaxed(&l.v[11]);
+  return s;
+}
+SX_DEV void seq_store(Line &l, const SeqState &s) {
+  store_relaxed(&l.v[0], s.phase);
+  store_relaxed(&l.v[1], s.it);
+  store_relaxed((unsigned long long *)&l.v[2], s.mu);
+  store_relaxed(&l.v[4], s.nf_prev);
+  store_relaxed((unsigned long long *)&l.v[6], s.reached);
+  store_relaxed(&l.v[8], s.t1);
+  store_relaxed(&l.v[9], s.t2);
+  store_relaxed(&l.v[10], s.pulling);
+  store_relaxed(&l.v[11], s.decide);
+}
+
+template <class Ops>
+__global__ void __launch_bounds__(kBlock) k_seq(TravArgs a, unsigned L) {
+  __shared__ LdsTrav lds;
+  __shared__ LdsPolicy pol;
+  Ctrl *C = a.w.ctrl;
+  const VGrid vg = hw_grid();
+  SeqState q = seq_load(C->seq[L & 1]);
+  Line &out = C->seq[(L + 1) & 1];
+  const bool lead = vg.bid == 0 && threadIdx.x == 0;
+  if (q.phase >= PH_DONE) {
+    if (lead) seq_store(out, q);
+    return;
+  }
+  if (load_relaxed(&C->error.v[0])) {
+    q.phase = PH_ERROR;
+    if (lead) seq_store(out, q);
+    return;
+  }
+  RunState s;
+  s.it = (int)q.it;
+  s.mu = q.mu;
+  s.ps.nf_prev = q.nf_prev;
+  s.ps.reached = q.reached;
+  s.P = a.P;
+  if (q.t1) { s.P.t1 = (int)q.t1; s.P.t2 = (int)q.t2; }
+  if (q.decide) {
+    load_policy(a, pol);
+    const bool pulling = q.pulling != 0;
+    Decision d = decide<Ops>(a, s, pulling, &pol);
+    q.decide = 0;
+    if (d.done) {
+      q.phase = (s.it + 1 >= a.P.max_iters) ? PH_LIMIT : PH_DONE;
+    } else if (!pulling) {
+      if (d.to_pull) { q.pulling = 1; q.phase = PH_PULL_SCAN; ++s.it; }
+      else if (d.ballot) q.phase = PH_BALLOT1;           // rebuild the lists of it+1
+      else { q.phase = PH_PUSH; ++s.it; }
+    } else {
+      if (d.to_push) {
+        q.pulling = 0;
+        if (load_relaxed(&C->q[(s.it + 1) % 3].overflow)) q.phase = PH_BALLOT1;
+        else { q.phase = PH_PUSH; ++s.it; }
+      } else { q.phase = PH_PULL_SCAN; ++s.it; }
+    }
+    if (q.phase >= PH_DONE) {
+      q.it = (unsigned)s.it;
+      if (lead) seq_store(out, q);
+      return;
+    }
+  }
+  const int it = s.it;
+  Ops ops = make_ops<Ops>(a, it);
+  unsigned next = q.phase;
+  switch (q.phase) {
+    case PH_PUSH:
+      if (lead) {
+        reset_counters(&C->q[(it + 2) % 3]);
+        atomic_add_u32(&C->stats.v[6], 1u);
+      }
+      push_phase(vg, a, s.P, ops, it, lds);
+      q.decide = 1;
+      break;
+    case PH_BALLOT1:
+      ballot_pass1(vg, a, s.P, ops, lds);
+      next = PH_BALLOT2;
+      break;
+    case PH_BALLOT2:
+      ballot_pass2(vg, a, s.P, it, lds);
+      next = PH_PUSH;
+      ++s.it;
+      break;
+    case PH_PULL_SCAN:
+      if (lead) {
+        reset_counters(&C->q[(it + 1) % 3]);
+        reset_counters(&C->q[(it + 2) % 3]);
+        atomic_add_u32(&C->stats.v[6], 1u);
+      }
+      pull_scan(vg, a, s.P, ops, lds);
+      next = PH_PULL_LISTS;
+      break;
+    case PH_PULL_LISTS:
+      pull_lists(vg, a, it, lds);
+      next = PH_PULL;
+      break;
+    case PH_PULL:
+      pull_phase(vg, a, s.P, ops, it, lds);
+      q.decide = 1;
+      break;
+  }
+  if (lead) {
+    q.phase = next;
+    q.it = (unsigned)s.it;
+    q.mu = s.mu;
+    q.nf_prev = s.ps.nf_prev;
+    q.reached = s.ps.reached;
+    q.t1 = (unsigned)s.P.t1;
+    q.t2 = (unsigned)s.P.t2;
+    seq_store(out, q);
+  }
+}
+
+// first state of a sequenced run (after k_trav_init)
+__global__ void k_seq_start(Ctrl *C, unsigned pull_first) {
+  if (threadIdx.x == 0) {
+    SeqState q{};
+    q.phase = pull_first ? PH_PULL_SCAN : PH_PUSH;
+    q.pulling = pull_first;
+    q.mu = *(unsigned long long *)&C->state.v[6];
+    seq_store(C->seq[0], q);
+  }
+}
+
 // ------------------------------------------------- batched queries ---
 // Many BFS / SSSP queries over graphs of uneven size in one persistent
 // launch.  The hardware grid is split into teams of `team` workgroups; each
@@ -798,7 +985,9 @@ __global__ void k_trav_init(TravArgs a, int is_sssp, unsigned long long mu0) {
       }
       for (int i = 0; i < 32; ++i) { C->state.v[i] = 0; C->stats.v[i] = 0; }
       C->error.v[0] = 0;
-      *(unsigned long long *)&C->state.v[6] = mu0;
+      // arcs not yet explored: all but the source's
+      *(unsigned long long *)&C->state.v[6] =
+          mu0 ? mu0 : (unsigned long long)(a.g.m - degree_of(a.g.off, a.src));
     }
     __builtin_amdgcn_wave_barrier();
     __threadfence_block();
@@ -884,6 +1073,21 @@ hipError_t trav_init(const TravArgs &a, int sssp, unsigned long long mu0, hipStr
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(k_trav_init, dim3(grid), dim3(kBlock), 0, s, a, sssp, mu0);
   return hipGetLastError();
+}
+
+hipError_t seq_start(Ctrl *c, bool pull_first, hipStream_t s) {
+  hipLaunchKernelGGL(k_seq_start, dim3(1), dim3(64), 0, s, c, pull_first ? 1u : 0u);
+  return hipGetLastError();
+}
+
+hipError_t seq_launch(int sssp, const TravArgs &a, unsigned L, int grid, hipStream_t s) {
+  if (sssp) hipLaunchKernelGGL(k_seq<SsspOps>, dim3(grid), dim3(kBlock), 0, s, a, L);
+  else hipLaunchKernelGGL(k_seq<BfsOps>, dim3(grid), dim3(kBlock), 0, s, a, L);
+  return hipGetLastError();
+}
+
+const void *seq_kernel(int sssp) {
+  return sssp ? (const void *)k_seq<SsspOps> : (const void *)k_seq<BfsOps>;
 }
 
 hipError_t batch_launch(const BatchArgs &b, int grid, hipStream_t s) {

@@ -44,6 +44,8 @@ struct Ctrl {
                                 // ballot iters, [5] pull iters, [6] iterations
   Counters q[3];
   Line aux;                     // algorithm scratch (k-core: min alive degree)
+  Line seq[2];                  // sequenced mode: run state handed from launch
+                                // L (reads seq[L&1]) to launch L+1
   Line flags[kMaxGrid];         // barrier arrival words, one line per workgroup
 };
 

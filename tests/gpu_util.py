@@ -25,7 +25,10 @@ def run(engine, g, algo, source=-1, policy=None, dg=None, **kw):
 
 
 ARMS = [
-    ("auto-jit-fused", sx.Policy()),
+    ("auto-jit", sx.Policy()),
+    ("pull-seq", sx.Policy(direction=sx.SX_DIR_PULL, fused=sx.SX_SEQUENCED)),
+    ("push-ballot-seq", sx.Policy(direction=sx.SX_DIR_PUSH, filter=sx.SX_FILTER_BALLOT, fused=sx.SX_SEQUENCED)),
+    ("auto-jit-fused", sx.Policy(fused=sx.SX_FUSED)),
     ("push-online-fused", sx.Policy(direction=sx.SX_DIR_PUSH, filter=sx.SX_FILTER_ONLINE, fused=sx.SX_FUSED)),
     ("push-ballot-fused", sx.Policy(direction=sx.SX_DIR_PUSH, filter=sx.SX_FILTER_BALLOT, fused=sx.SX_FUSED)),
     ("pull-fused", sx.Policy(direction=sx.SX_DIR_PULL, fused=sx.SX_FUSED)),
