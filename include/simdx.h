@@ -122,12 +122,16 @@ void sx_program_destroy(sx_program *p);
 /* Per-iteration choices (Sections 4 and 5).  Each field 0 = automatic.
  *  direction  SX_DIR_AUTO | SX_DIR_PUSH | SX_DIR_PULL
  *  filter     SX_FILTER_JIT (online filter, ballot filter on overflow) |
- *             SX_FILTER_ONLINE (never overflow: capacity = n) |
+ *             SX_FILTER_ONLINE (online filter without a capacity limit of
+ *             its own: a workgroup may fill its whole region, about 2n / G
+ *             entries per bin; a full region still falls back to the ballot
+ *             filter, which keeps results exact) |
  *             SX_FILTER_BALLOT (always rebuild the worklist by ballot scan)
  *  bin_small  degree below which one lane takes a vertex (default 64)
  *  bin_large  degree from which a workgroup takes chunks of a vertex (256)
- *  online_cap online-filter capacity in entries per wavefront of the grid
- *             (default 64, the paper's overflow threshold)
+ *  online_cap SX_FILTER_JIT only: online-filter capacity in entries per
+ *             wavefront and bin (a workgroup of 8 wavefronts overflows past
+ *             8 x online_cap entries in a bin); 0 = the workgroup's region
  *  fused      SX_FUSED (persistent kernels + software global barrier,
  *             Section 5) | SX_UNFUSED (one launch per phase and iteration,
  *             the host deciding between launches) | SX_SEQUENCED (one launch
@@ -222,7 +226,11 @@ sx_status sx_batch_autotune(sx_ctx *ctx, const sx_query *queries, int32_t nq, co
                             void *hip_stream, sx_batch_config *best, double *best_ms);
 
 /* Library/build facts for the measurement harness: kernel register use and
- * persistent-grid sizing (the Eq. 1 analogue).  name: "bfs_push", ... */
+ * persistent-grid sizing (the Eq. 1 analogue).  name: one of "bfs_fused",
+ * "sssp_fused", "bfs_seq", "sssp_seq", "bfs_push_step", "bfs_pull_step",
+ * "sssp_push_step", "sssp_pull_step", "ballot_scan", "pull_scan",
+ * "kcore_fused", "kcore_seq", "pagerank_fused", "batch".
+ * Errors: SX_EINVAL (unknown name), SX_EHIP. */
 typedef struct {
   int32_t vgprs, sgprs, lds_bytes, block, wgs_per_cu, grid_wgs, cus;
 } sx_kernel_info;

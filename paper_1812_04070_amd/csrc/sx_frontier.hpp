@@ -1,34 +1,38 @@
 // Just-in-time task management (Section 4) on CDNA4.
 //
 // Worklists are split by degree into three bins (Section 4, step I):
-//   small  (deg < t1)        one lane per vertex          (the Thread kernel)
-//   medium (t1 <= deg < t2)  one 64-lane wavefront        (the Warp kernel)
-//   large  (deg >= t2)       one workgroup per chunk of   (the CTA kernel; hub
-//                            `chunk` arcs                  rows are split so a
-//                                                          single vertex can
-//                                                          occupy many CUs)
-// Two filters build the next worklists (Section 4):
-//   online filter  active vertices are appended while compute runs, one
-//                  atomic per wavefront and bin (ballot -> popcount -> lane
-//                  prefix); unsorted; overflows when a bin passes its capacity;
-//   ballot filter  after a barrier, wavefronts scan contiguous tiles of the
-//                  vertex metadata, turn the active test into 64-bit ballot
-//                  words, and a grid-wide exclusive scan of the per-tile counts
-//                  places every tile: the lists come out sorted and unique.
+//   small  (deg < t1)        processed a lane per vertex   (the Thread kernel)
+//   medium (t1 <= deg < t2)  a 64-lane wavefront per vertex (the Warp kernel)
+//   large  (deg >= t2)       a workgroup per chunk of       (the CTA kernel; hub
+//                            `chunk` arcs                    rows are split so a
+//                                                           single vertex can
+//                                                           occupy many CUs)
+//
+// Storage follows the paper's thread bins (Section 3.3): every workgroup
+// appends into its own region of each bin array -- positions come from an
+// LDS counter, so building a worklist needs no global atomic at all -- and
+// at the end of the phase publishes one record per workgroup (items per
+// bin, vertices, their arcs, overflow).  On MI355X this matters: every
+// device-scope atomic on one address is serialised (~11 ns each, measured),
+// so one atomic per wavefront on a shared queue counter costs ~70 us per
+// phase with 6,000 wavefronts.  The next phase builds, in LDS, the prefix of
+// the records and reads item i of a bin from the region that holds it: the
+// concatenation of the regions in workgroup order is the worklist.
+//
+// Two filters fill the bins (Section 4):
+//   online filter  active vertices are appended while compute runs (ballot ->
+//                  popcount -> one LDS atomic per wavefront and bin -> lane
+//                  offsets by mbcnt); a region that is full sets the
+//                  overflow flag: the JIT control then rebuilds the lists with
+//   ballot filter  each workgroup scans a contiguous range of vertex metadata
+//                  in wavefront-contiguous tiles, turns the active test into
+//                  64-bit ballot words, counts them, and writes the actives in
+//                  tile order: the lists come out sorted and unique.
 #pragma once
 
 #include "sx_device.hpp"
 
 namespace sx {
-
-// Next-iteration worklists and their counters.
-struct Lists {
-  int *s;                       // small bin vertices
-  int *m;                       // medium bin vertices
-  unsigned long long *l;        // large bin items: chunk << 32 | vertex
-  Counters *c;
-  unsigned cap_s, cap_m, cap_l; // capacities (online filter overflow limits)
-};
 
 SX_DEV int bin_of(int deg, const Params &P) {
   return deg < P.t1 ? BIN_SMALL : (deg < P.t2 ? BIN_MED : BIN_LARGE);
@@ -37,235 +41,365 @@ SX_DEV int chunks_of(int deg, int chunk) {
   return (int)(((long long)deg + chunk - 1) / chunk);
 }
 
-// Per-wavefront statistics accumulated in registers and flushed once.
+// One parity of the bin arrays, seen by a grid of G workgroups.
+struct Regions {
+  int *s, *m;
+  unsigned long long *l;
+  unsigned cap_s, cap_m, cap_l;
+};
+SX_DEV Regions regions(const Work &w, int parity, unsigned G) {
+  Regions r;
+  r.s = w.reg_s[parity];
+  r.m = w.reg_m[parity];
+  r.l = w.reg_l[parity];
+  r.cap_s = w.tot_s / G;
+  r.cap_m = w.tot_m / G;
+  r.cap_l = w.tot_l / G;
+  return r;
+}
+
+// ---------------------------------------------------------- producing ---
+struct LdsBins {
+  unsigned cnt[NBINS];
+  unsigned ovf;
+  unsigned lim[NBINS];
+  unsigned nf[kWaves];
+  unsigned long long mf[kWaves];
+};
+
+// Per-lane frontier statistics, reduced once at the end of the phase.
 struct WaveStats {
   unsigned nf = 0;
   unsigned long long mf = 0;
 };
 
-// Online filter: every lane of the wavefront calls this (convergent).  Lanes
-// with `valid` append vertex v (degree deg) to its bin.  Large vertices add
-// one item per chunk of arcs.  Sets c->overflow when a bin passes capacity.
-SX_DEV void online_append(bool valid, int v, int deg, const Lists &L, const Params &P, int chunk,
-                          WaveStats &st) {
+// Start of a producing phase (all threads).  `limit` caps each bin's region
+// use (the online-filter overflow threshold); 0 = the whole region.
+SX_DEV void bins_begin(LdsBins &b, const Regions &R, unsigned limit) {
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NBINS; ++i) b.cnt[i] = 0;
+    b.ovf = 0;
+    b.lim[0] = limit && limit < R.cap_s ? limit : R.cap_s;
+    b.lim[1] = limit && limit < R.cap_m ? limit : R.cap_m;
+    b.lim[2] = limit && limit < R.cap_l ? limit : R.cap_l;
+  }
+  __syncthreads();
+}
+
+// Online filter: every lane of the wavefront calls (convergent).  Lanes with
+// `valid` append vertex v (degree deg) to its bin in this workgroup's region;
+// a large vertex adds one item per chunk of arcs.
+SX_DEV void bins_append(bool valid, int v, int deg, const Regions &R, unsigned bid, const Params &P,
+                        int chunk, LdsBins &b, WaveStats &st) {
   const uint64_t any = ballot(valid);
   if (any == 0) return;
   const int lane = lane_id();
-  const int b = valid ? bin_of(deg, P) : -1;
+  const int bn = valid ? bin_of(deg, P) : -1;
   if (valid) { st.nf += 1; st.mf += (unsigned long long)deg; }
 #pragma unroll
   for (int bin = 0; bin < 2; ++bin) {
-    const uint64_t mk = ballot(b == bin);
+    const uint64_t mk = ballot(bn == bin);
     if (mk == 0) continue;
     const int leader = __ffsll((long long)mk) - 1;
     unsigned base = 0;
-    if (lane == leader) base = atomic_add_u32(&L.c->cnt[bin], (unsigned)__popcll(mk));
+    if (lane == leader) base = atomicAdd(&b.cnt[bin], (unsigned)__popcll(mk));
     base = __shfl(base, leader);
-    const unsigned cap = bin == 0 ? L.cap_s : L.cap_m;
-    if (b == bin) {
+    if (bn == bin) {
       const unsigned pos = base + lane_prefix(mk);
-      if (pos < cap) (bin == 0 ? L.s : L.m)[pos] = v;
+      if (pos < b.lim[bin]) {
+        if (bin == 0) R.s[(size_t)bid * R.cap_s + pos] = v;
+        else R.m[(size_t)bid * R.cap_m + pos] = v;
+      } else {
+        b.ovf = 1;
+      }
     }
-    if (lane == leader && base + (unsigned)__popcll(mk) > cap) store_relaxed(&L.c->overflow, 1u);
   }
-  const uint64_t ml = ballot(b == BIN_LARGE);
+  const uint64_t ml = ballot(bn == BIN_LARGE);
   if (ml) {
-    const int k = (b == BIN_LARGE) ? chunks_of(deg, chunk) : 0;
+    const int k = (bn == BIN_LARGE) ? chunks_of(deg, chunk) : 0;
     const int incl = wave_incl_scan(k);
     const int total = __shfl(incl, 63);
     unsigned base = 0;
-    if (lane == 63) base = atomic_add_u32(&L.c->cnt[BIN_LARGE], (unsigned)total);
+    if (lane == 63) base = atomicAdd(&b.cnt[BIN_LARGE], (unsigned)total);
     base = __shfl(base, 63);
     const unsigned pos = base + (unsigned)(incl - k);
-    for (int c = 0; c < k; ++c)
-      if (pos + c < L.cap_l) L.l[pos + c] = ((unsigned long long)c << 32) | (unsigned)v;
-    if (lane == 63 && base + (unsigned)total > L.cap_l) store_relaxed(&L.c->overflow, 1u);
+    for (int c = 0; c < k; ++c) {
+      if (pos + c < b.lim[BIN_LARGE])
+        R.l[(size_t)bid * R.cap_l + pos + c] = ((unsigned long long)c << 32) | (unsigned)v;
+      else
+        b.ovf = 1;
+    }
   }
 }
 
-// Flush per-wavefront frontier statistics into the counters (one atomic per
-// wavefront per phase).
-SX_DEV void flush_stats(WaveStats &st, Counters *c) {
+// End of a producing phase (all threads): publish this workgroup's record.
+// Counts past the limit mark overflow; entries beyond it were not written.
+SX_DEV void bins_end(LdsBins &b, WaveStats &st, WgRec *rec_slot, unsigned bid) {
   const int nf = wave_sum_i((int)st.nf);
   const long long mf = wave_sum_ll((long long)st.mf);
-  if (lane_id() == 0 && nf) {
-    atomic_add_u32(&c->nf, (unsigned)nf);
-    atomic_add_u64(&c->mf, (unsigned long long)mf);
+  if (lane_id() == 0) {
+    b.nf[wave_in_wg()] = (unsigned)nf;
+    b.mf[wave_in_wg()] = (unsigned long long)mf;
   }
-  st.nf = 0; st.mf = 0;
+  st.nf = 0;
+  st.mf = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    WgRec r;
+    unsigned tnf = 0;
+    unsigned long long tmf = 0;
+    for (int w = 0; w < kWaves; ++w) { tnf += b.nf[w]; tmf += b.mf[w]; }
+    unsigned ovf = b.ovf;
+    for (int i = 0; i < NBINS; ++i) {
+      r.cnt[i] = b.cnt[i] < b.lim[i] ? b.cnt[i] : b.lim[i];
+      if (b.cnt[i] > b.lim[i]) ovf = 1;
+    }
+    r.nf = tnf;
+    r.mf = tmf;
+    r.ovf = ovf;
+    for (int i = 0; i < 9; ++i) r.pad[i] = 0;
+    rec_slot[bid] = r;
+  }
+  __syncthreads();
 }
 
-// ------------------------------------------------------- ballot filter ---
-// Tiles: global wavefront gw owns vertices [gw*tile, (gw+1)*tile), tile a
-// multiple of 64, so consecutive wavefronts own consecutive ranges and the
-// concatenation in wavefront order is sorted.
-struct Tiling {
-  int tile;
-  unsigned nwaves;
-  SX_DEV Tiling(int n, unsigned nw) : nwaves(nw) {
-    long long t = ((long long)n + nw - 1) / nw;
-    tile = (int)((t + 63) / 64 * 64);
-    if (tile < 64) tile = 64;
+// ---------------------------------------------------------- consuming ---
+struct LdsView {
+  unsigned pre[NBINS][kMaxGrid + 1];
+  unsigned tmp[kWaves * 4];
+};
+
+struct Totals {
+  unsigned cnt[NBINS];          // items per bin (within the regions)
+  unsigned nf;                  // vertices appended (all, also past capacity)
+  unsigned long long mf;
+  unsigned ovf;                 // some region overflowed
+};
+
+// Prefix of the records of one slot (all threads); the totals are identical
+// in every workgroup.
+SX_DEV Totals view_build(const WgRec *rec, unsigned G, const Regions &R, LdsView &V,
+                         long long *red /* kWaves */) {
+  const unsigned t = threadIdx.x;  // owns records 2t and 2t+1
+  unsigned c[2][NBINS] = {{0, 0, 0}, {0, 0, 0}};
+  unsigned long long mf = 0;
+  unsigned nf = 0, ovf = 0;
+  const unsigned caps[NBINS] = {R.cap_s, R.cap_m, R.cap_l};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const unsigned w = 2 * t + k;
+    if (w < G) {
+      const WgRec r = rec[w];
+#pragma unroll
+      for (int b = 0; b < NBINS; ++b) {
+        c[k][b] = r.cnt[b] < caps[b] ? r.cnt[b] : caps[b];
+        ovf |= r.cnt[b] > caps[b] ? 1u : 0u;
+      }
+      nf += r.nf;
+      mf += r.mf;
+      ovf |= r.ovf;
+    }
+  }
+  unsigned tot[NBINS];
+#pragma unroll
+  for (int b = 0; b < NBINS; ++b) {
+    const int s = (int)(c[0][b] + c[1][b]);
+    const int incl = wave_incl_scan(s);
+    if (lane_id() == 63) V.tmp[wave_in_wg() * 4 + b] = (unsigned)incl;
+    __syncthreads();
+    unsigned base = 0, all = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      const unsigned x = V.tmp[w * 4 + b];
+      if (w < wave_in_wg()) base += x;
+      all += x;
+    }
+    const unsigned ex = base + (unsigned)(incl - s);
+    if (2 * t < G) V.pre[b][2 * t] = ex;
+    if (2 * t + 1 < G) V.pre[b][2 * t + 1] = ex + c[0][b];
+    if (t == 0) V.pre[b][G] = all;
+    tot[b] = all;
+    __syncthreads();
+  }
+  Totals T;
+#pragma unroll
+  for (int b = 0; b < NBINS; ++b) T.cnt[b] = tot[b];
+  T.nf = (unsigned)wg_sum_ll<kBlock>((long long)nf, red);
+  T.mf = (unsigned long long)wg_sum_ll<kBlock>((long long)mf, red);
+  T.ovf = wg_sum_ll<kBlock>((long long)ovf, red) ? 1u : 0u;
+  return T;
+}
+
+// largest r < G with pre[r] <= i (for i < pre[G])
+SX_DEV unsigned view_find(const unsigned *pre, unsigned G, unsigned i) {
+  unsigned lo = 0, hi = G - 1;
+  while (lo < hi) {
+    const unsigned mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Item i of each bin through a view (lambdas for the visitors)
+struct ViewRef {
+  const LdsView *V;
+  Regions R;
+  unsigned G;
+  SX_DEV int small(unsigned i) const {
+    const unsigned r = view_find(V->pre[BIN_SMALL], G, i);
+    return R.s[(size_t)r * R.cap_s + (i - V->pre[BIN_SMALL][r])];
+  }
+  SX_DEV int med(unsigned i) const {
+    const unsigned r = view_find(V->pre[BIN_MED], G, i);
+    return R.m[(size_t)r * R.cap_m + (i - V->pre[BIN_MED][r])];
+  }
+  SX_DEV unsigned long long large(unsigned i) const {
+    const unsigned r = view_find(V->pre[BIN_LARGE], G, i);
+    return R.l[(size_t)r * R.cap_l + (i - V->pre[BIN_LARGE][r])];
   }
 };
 
-// Pass 1: evaluate `pred(v) -> bool` and the degree for every vertex of this
-// wavefront's tile; store ballot words per bin; accumulate per-wave and
-// per-workgroup counts.  `wavecnt` (global) receives [gw][NBINS] counts;
-// `wgc` (global) the workgroup totals.  Every thread of the workgroup calls.
-template <class Pred, class Deg>
-SX_DEV void ballot_count(const VGrid &vg, int n, const Tiling &T, Pred pred, Deg degree, const Params &P, int chunk,
-                         unsigned long long *const bits[NBINS], unsigned *wavecnt, WgCount *wgc,
-                         unsigned *lds /* kWaves * 6 */) {
-  const unsigned gw = vg.bid * kWaves + wave_in_wg();
-  const int lane = lane_id();
-  const long long start = (long long)gw * T.tile;
+// ------------------------------------------------------- ballot filter ---
+// Workgroup `bid` scans positions [lo, hi) (lo a multiple of 64); wavefront w
+// takes a contiguous sub-range, so the output order is the position order.
+// probe(pos, valid) is called convergently by whole wavefronts and returns
+// whether the entry at `pos` is active (false where !valid); vertex_of(pos)
+// and degree(v) give its vertex and degree.  The ballot words go to `bits`
+// (one 64-bit word per 64 positions per bin), are counted, and after a
+// workgroup barrier re-read and written into this workgroup's regions.  One
+// pass over the metadata and no grid-wide step: the range is contiguous, so
+// the concatenation of the regions in workgroup order is sorted.
+struct LdsBallot {
+  unsigned wcnt[kWaves][NBINS];
+  unsigned wnf[kWaves];
+  unsigned wovf[kWaves];
+  unsigned long long wmf[kWaves];
+};
+
+template <class Probe, class Deg, class VertexOf>
+SX_DEV void ballot_fill_range(long long lo, long long hi, unsigned bid, Probe probe, Deg degree,
+                              VertexOf vertex_of, const Params &P, int chunk,
+                              unsigned long long *const bits[NBINS], const Regions &R,
+                              WgRec *rec_slot, LdsBallot &lb) {
+  const long long len = hi > lo ? hi - lo : 0;
+  const long long per_wave = ((len + kWaves - 1) / kWaves + 63) / 64 * 64;
+  const int lane = lane_id(), wv = wave_in_wg();
+  const long long start = lo + (long long)wv * per_wave;
+  const long long end = start + per_wave < hi ? start + per_wave : hi;
   unsigned c[NBINS] = {0, 0, 0};
   unsigned long long mf = 0;
-  for (int s = 0; s < T.tile; s += 64) {
-    const long long v = start + s + lane;
-    bool p = false;
-    int d = 0;
-    if (v < n) {
-      p = pred((int)v);
-      if (p) d = degree((int)v);
-    }
+  unsigned nfv = 0;
+  for (long long s = start; s < end; s += 64) {
+    const long long i = s + lane;
+    const bool p = probe(i, i < end);
+    const int d = p ? degree(vertex_of(i)) : 0;
     const int b = p ? bin_of(d, P) : -1;
-    if (start + s < n) {
-      const long long word = (start + s) >> 6;
+    const long long word = s >> 6;
 #pragma unroll
-      for (int bin = 0; bin < NBINS; ++bin) {
-        const uint64_t mk = ballot(b == bin);
-        if (lane == 0) bits[bin][word] = mk;
-        if (bin < BIN_LARGE) c[bin] += (unsigned)__popcll(mk);
-      }
-      const int k = (b == BIN_LARGE) ? chunks_of(d, chunk) : 0;
-      c[BIN_LARGE] += (unsigned)wave_sum_i(k);
-      mf += (unsigned long long)wave_sum_ll(p ? d : 0);
+    for (int bin = 0; bin < NBINS; ++bin) {
+      const uint64_t mk = ballot(b == bin);
+      if (lane == 0) bits[bin][word] = mk;
+      if (bin < BIN_LARGE) c[bin] += (unsigned)__popcll(mk);
     }
+    const int k = (b == BIN_LARGE) ? chunks_of(d, chunk) : 0;
+    c[BIN_LARGE] += (unsigned)wave_sum_i(k);
+    nfv += (unsigned)__popcll(ballot(p));
+    mf += (unsigned long long)wave_sum_ll(p ? d : 0);
   }
   if (lane == 0) {
+    for (int bin = 0; bin < NBINS; ++bin) lb.wcnt[wv][bin] = c[bin];
+    lb.wnf[wv] = nfv;
+    lb.wmf[wv] = mf;
+  }
+  __syncthreads();
+  unsigned pos[NBINS] = {0, 0, 0}, tot[NBINS] = {0, 0, 0};
+  for (int w = 0; w < kWaves; ++w)
     for (int bin = 0; bin < NBINS; ++bin) {
-      wavecnt[gw * NBINS + bin] = c[bin];
-      lds[wave_in_wg() * 6 + bin] = c[bin];
+      if (w < wv) pos[bin] += lb.wcnt[w][bin];
+      tot[bin] += lb.wcnt[w][bin];
     }
-    lds[wave_in_wg() * 6 + 3] = (unsigned)(mf & 0xffffffffu);
-    lds[wave_in_wg() * 6 + 4] = (unsigned)(mf >> 32);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    WgCount t{};
-    for (int w = 0; w < kWaves; ++w) {
-      for (int bin = 0; bin < NBINS; ++bin) t.cnt[bin] += lds[w * 6 + bin];
-      t.mf += (unsigned long long)lds[w * 6 + 3] | ((unsigned long long)lds[w * 6 + 4] << 32);
-    }
-    // vertices = small + medium + (large vertices, counted from the words in pass 2)
-    wgc[vg.bid] = t;
-  }
-  __syncthreads();
-}
-
-// Pass 2: place this wavefront's actives (position i of the scanned range
-// holds vertex vertex_of(i)).  Grid totals are returned in `tot`, identical
-// in every workgroup.
-template <class Deg, class VertexOf>
-SX_DEV void ballot_write(const VGrid &vg, int n, const Tiling &T, Deg degree, VertexOf vertex_of, int chunk,
-                         unsigned long long *const bits[NBINS], const unsigned *wavecnt,
-                         const WgCount *wgc, int *out_s, int *out_m, unsigned long long *out_l,
-                         WgCount &tot, unsigned *lds /* kWaves * 8 */, long long *red /* kWaves */) {
-  // workgroup base = sum over lower workgroups, grid totals = sum over all;
-  // 32-bit counts (n < 2^31 and large items <= n + m / chunk).
-  unsigned acc[2 * NBINS];
-#pragma unroll
-  for (int i = 0; i < 2 * NBINS; ++i) acc[i] = 0;
-  unsigned long long mf = 0;
-#pragma unroll 1
-  for (unsigned b = threadIdx.x; b < vg.nb; b += kBlock) {
-    const WgCount w = wgc[b];
-    const bool lower = b < vg.bid;
-#pragma unroll
-    for (int bin = 0; bin < NBINS; ++bin) {
-      acc[NBINS + bin] += w.cnt[bin];
-      acc[bin] += lower ? w.cnt[bin] : 0u;
-    }
-    mf += w.mf;
-  }
-  // workgroup reduction of the 6 counts and mf through LDS
-#pragma unroll
-  for (int i = 0; i < 2 * NBINS; ++i) acc[i] = (unsigned)wave_sum_i((int)acc[i]);
-  mf = (unsigned long long)wave_sum_ll((long long)mf);
-  __syncthreads();
-  if (lane_id() == 0) {
-#pragma unroll
-    for (int i = 0; i < 2 * NBINS; ++i) lds[wave_in_wg() * 8 + i] = acc[i];
-    red[wave_in_wg()] = (long long)mf;
-  }
-  __syncthreads();
-  unsigned r[2 * NBINS];
-#pragma unroll
-  for (int i = 0; i < 2 * NBINS; ++i) {
-    unsigned t = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) t += lds[w * 8 + i];
-    r[i] = t;
-  }
-  unsigned long long mft = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) mft += (unsigned long long)red[w];
-  __syncthreads();
-  const unsigned wv = wave_in_wg();
-  const unsigned gw = vg.bid * kWaves + wv;
-  unsigned pos[NBINS];
-#pragma unroll
-  for (int bin = 0; bin < NBINS; ++bin) {
-    unsigned p = r[bin];
-#pragma unroll 1
-    for (unsigned w = vg.bid * kWaves; w < gw; ++w) p += wavecnt[w * NBINS + bin];
-    pos[bin] = p;
-  }
-  const int lane = lane_id();
-  const long long start = (long long)gw * T.tile;
-  unsigned large_vertices = 0;
-  for (int s = 0; s < T.tile && start + s < n; s += 64) {
-    const long long word = (start + s) >> 6;
+  const unsigned caps[NBINS] = {R.cap_s, R.cap_m, R.cap_l};
+  bool ovf = false;
+  for (long long s = start; s < end; s += 64) {
+    const long long word = s >> 6;
     const uint64_t ms = bits[BIN_SMALL][word];
     const uint64_t mm = bits[BIN_MED][word];
     const uint64_t ml = bits[BIN_LARGE][word];
     const bool in_any = ((ms | mm | ml) >> lane) & 1ull;
-    const int v = in_any ? vertex_of((int)(start + s + lane)) : 0;
-    if ((ms >> lane) & 1ull) out_s[pos[BIN_SMALL] + lane_prefix(ms)] = v;
-    if ((mm >> lane) & 1ull) out_m[pos[BIN_MED] + lane_prefix(mm)] = v;
+    const int v = in_any ? vertex_of(s + lane) : 0;
+    if ((ms >> lane) & 1ull) {
+      const unsigned q = pos[BIN_SMALL] + lane_prefix(ms);
+      if (q < caps[BIN_SMALL]) R.s[(size_t)bid * R.cap_s + q] = v;
+      else ovf = true;
+    }
+    if ((mm >> lane) & 1ull) {
+      const unsigned q = pos[BIN_MED] + lane_prefix(mm);
+      if (q < caps[BIN_MED]) R.m[(size_t)bid * R.cap_m + q] = v;
+      else ovf = true;
+    }
     pos[BIN_SMALL] += (unsigned)__popcll(ms);
     pos[BIN_MED] += (unsigned)__popcll(mm);
     if (ml) {
       const int k = ((ml >> lane) & 1ull) ? chunks_of(degree(v), chunk) : 0;
       const int incl = wave_incl_scan(k);
-      const unsigned p = pos[BIN_LARGE] + (unsigned)(incl - k);
-      for (int c = 0; c < k; ++c) out_l[p + c] = ((unsigned long long)c << 32) | (unsigned)v;
+      const unsigned q = pos[BIN_LARGE] + (unsigned)(incl - k);
+      for (int cc = 0; cc < k; ++cc) {
+        if (q + cc < caps[BIN_LARGE])
+          R.l[(size_t)bid * R.cap_l + q + cc] = ((unsigned long long)cc << 32) | (unsigned)v;
+        else
+          ovf = true;
+      }
       pos[BIN_LARGE] += (unsigned)__shfl(incl, 63);
-      large_vertices += (unsigned)__popcll(ml);
     }
   }
-  tot.cnt[0] = r[NBINS + 0];
-  tot.cnt[1] = r[NBINS + 1];
-  tot.cnt[2] = r[NBINS + 2];
-  tot.mf = mft;
-  tot.nf = 0;  // filled by the caller when needed
-  (void)large_vertices;
+  const bool any_ovf = ballot(ovf) != 0;
+  if (lane == 0) lb.wovf[wv] = any_ovf ? 1u : 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    WgRec r;
+    unsigned long long tmf = 0;
+    unsigned tnf = 0, o = 0;
+    for (int w = 0; w < kWaves; ++w) { tmf += lb.wmf[w]; tnf += lb.wnf[w]; o |= lb.wovf[w]; }
+    for (int bin = 0; bin < NBINS; ++bin) {
+      r.cnt[bin] = tot[bin] < caps[bin] ? tot[bin] : caps[bin];
+      if (tot[bin] > caps[bin]) o = 1;
+    }
+    r.nf = tnf;
+    r.mf = tmf;
+    r.ovf = o;
+    for (int i = 0; i < 9; ++i) r.pad[i] = 0;
+    rec_slot[bid] = r;
+  }
+  __syncthreads();
+}
+
+// Positions [0, count) split over the grid in contiguous ranges (multiples
+// of 64 * kWaves); pred(i) is the active test of position i, vertex_of(i)
+// its vertex.
+template <class Pred, class Deg, class VertexOf>
+SX_DEV void ballot_fill(const VGrid &vg, int count, Pred pred, Deg degree, VertexOf vertex_of,
+                        const Params &P, int chunk, unsigned long long *const bits[NBINS],
+                        const Regions &R, WgRec *rec_slot, LdsBallot &lb) {
+  const long long unit = 64 * kWaves;
+  const long long per_wg = (((long long)count + vg.nb - 1) / vg.nb + unit - 1) / unit * unit;
+  const long long lo = (long long)vg.bid * per_wg;
+  const long long hi = lo + per_wg < count ? lo + per_wg : count;
+  auto probe = [&](long long i, bool ok) { return ok && pred((int)i); };
+  auto vof = [&](long long i) { return vertex_of((int)i); };
+  ballot_fill_range(lo, hi, vg.bid, probe, degree, vof, P, chunk, bits, R, rec_slot, lb);
 }
 
 // ------------------------------------------------- worklist traversal ---
 // Visit every arc of every worklist entry.  `op(v, u, arc, lane_valid)` is
-// called convergently by whole wavefronts; it returns nothing and performs
-// Compute + Combine for arc v->u and the online append itself.
+// called convergently by whole wavefronts; it performs Compute + Combine for
+// arc v->u and the online append itself.  Entries outside [0, n) are
+// skipped (a defence: lists only ever hold vertex ids).
 
 // Small bin: a wavefront takes 64 vertices, stages their row starts and a
 // prefix sum of their degrees in LDS, then walks the concatenated arcs 64 at
 // a time (one arc per lane), so lanes stay busy however degrees vary.
-// Worklist entries outside [0, n) are skipped (a defence: lists only ever
-// hold vertex ids, but a read never leaves the CSR).
-template <class Op>
-SX_DEV void visit_small(int n, const int *list, unsigned cnt, const int *off, const int *idx, Op &op,
+template <class Acc, class Op>
+SX_DEV void visit_small(int n, Acc item, unsigned cnt, const int *off, const int *idx, Op &op,
                         unsigned gw, unsigned nwaves, int *lds /* 3*64 per wave */) {
   const int lane = lane_id();
   int *l_v = lds, *l_beg = lds + 64, *l_ex = lds + 128;
@@ -273,7 +407,7 @@ SX_DEV void visit_small(int n, const int *list, unsigned cnt, const int *off, co
     const unsigned i = c * 64u + lane;
     int v = -1, beg = 0, deg = 0;
     if (i < cnt) {
-      const int x = list[i];
+      const int x = item(i);
       if ((unsigned)x < (unsigned)n) {
         v = x;
         beg = off[v];
@@ -291,11 +425,11 @@ SX_DEV void visit_small(int n, const int *list, unsigned cnt, const int *off, co
       const bool ok = e < total;
       int owner = 0;
       if (ok) {
-        // largest owner with l_ex[owner] <= e
         int lo = 0, hi = 63;
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
-          if (l_ex[mid] <= e) lo = mid; else hi = mid - 1;
+          if (l_ex[mid] <= e) lo = mid;
+          else hi = mid - 1;
         }
         owner = lo;
       }
@@ -309,12 +443,12 @@ SX_DEV void visit_small(int n, const int *list, unsigned cnt, const int *off, co
 }
 
 // Medium bin: one wavefront per vertex.
-template <class Op>
-SX_DEV void visit_med(int n, const int *list, unsigned cnt, const int *off, const int *idx, Op &op,
+template <class Acc, class Op>
+SX_DEV void visit_med(int n, Acc item, unsigned cnt, const int *off, const int *idx, Op &op,
                       unsigned gw, unsigned nwaves) {
   const int lane = lane_id();
   for (unsigned i = gw; i < cnt; i += nwaves) {
-    const int v = list[i];
+    const int v = item(i);
     if ((unsigned)v >= (unsigned)n) continue;
     const int beg = off[v], end = off[v + 1];
     for (int a = beg; a < end; a += 64) {
@@ -327,17 +461,17 @@ SX_DEV void visit_med(int n, const int *list, unsigned cnt, const int *off, cons
 }
 
 // Large bin: one workgroup per item (a chunk of `chunk` arcs of one vertex).
-template <class Op>
-SX_DEV void visit_large(const VGrid &vg, int n, const unsigned long long *list, unsigned cnt,
-                        const int *off, const int *idx, int chunk, Op &op) {
+template <class Acc, class Op>
+SX_DEV void visit_large(const VGrid &vg, int n, Acc item, unsigned cnt, const int *off,
+                        const int *idx, int chunk, Op &op) {
   for (unsigned i = vg.bid; i < cnt; i += vg.nb) {
-    const unsigned long long it = list[i];
+    const unsigned long long it = item(i);
     const int v = (int)(it & 0xffffffffu);
     if ((unsigned)v >= (unsigned)n) continue;
     const int c = (int)(it >> 32);
     const int vb = off[v], ve = off[v + 1];
     const long long b0 = (long long)vb + (long long)c * chunk;
-    const int beg = (int)b0;
+    const int beg = (int)(b0 < ve ? b0 : ve);
     const int end = (int)((b0 + chunk) < ve ? (b0 + chunk) : ve);
     for (int a = beg; a < end; a += kBlock) {
       const int arc = a + (int)threadIdx.x;
@@ -345,6 +479,19 @@ SX_DEV void visit_large(const VGrid &vg, int n, const unsigned long long *list, 
       const int u = ok ? idx[arc] : 0;
       op(v, u, arc, ok);
     }
+  }
+}
+
+// Statistics: arcs inspected and worklist entries processed, added by each
+// workgroup into one of 64 lines (spread so that the atomics do not
+// serialise on one address).
+SX_DEV void add_stats(Ctrl *C, unsigned bid, long long edges_lane, unsigned long long entries,
+                      long long *red) {
+  const long long e = wg_sum_ll<kBlock>(edges_lane, red);
+  if (threadIdx.x == 0) {
+    Line &l = C->statw[bid % kStatLines];
+    if (e) atomic_add_u64((unsigned long long *)&l.v[0], (unsigned long long)e);
+    if (entries) atomic_add_u64((unsigned long long *)&l.v[2], entries);
   }
 }
 

@@ -213,6 +213,77 @@ static void free_graph(sx_graph *G) {
 
 static const int kChunk = 4 * kBlock;  // arcs per large-bin item
 
+// Worklist storage for grids of up to `gmax` workgroups (regions: workgroup b
+// of G owns 1/G of every bin array).  The sizes make every list a ballot scan
+// builds fit its regions for any G <= gmax:
+//   a scan over `count` positions gives each workgroup at most
+//   count / G + 512 of them (ranges are multiples of 512), so the small and
+//   medium arrays hold 2n + 1024 gmax entries (the first n + 512 gmax for
+//   scans, the rest headroom for the online filter);
+//   a large vertex adds ceil(deg / chunk) <= deg / chunk + 1 items, so a
+//   range of r vertices adds at most r + arcs / chunk: the large array holds
+//   n + 1024 gmax + gmax (ceil(arcs / chunk) + 1) entries, with arcs the
+//   degree sum (2m for the k-core of a directed graph: in- plus out-arcs);
+//   the k-core alive arrays hold n + 256 gmax entries (regions multiples of
+//   64 holding a contiguous n / G range at the start).
+struct Sizing {
+  size_t tot_s, tot_l, tot_a, words, fwords;
+};
+static Sizing work_sizing(long long n, long long m, bool directed, int gmax) {
+  Sizing z;
+  const size_t nn = (size_t)std::max<long long>(n, 1);
+  const size_t arcs = (size_t)(directed ? 2 * m : m);
+  z.tot_s = 2 * nn + 1024 * (size_t)gmax;
+  z.tot_a = nn + 256 * (size_t)gmax;
+  z.tot_l = nn + 1024 * (size_t)gmax + (size_t)gmax * ((arcs + kChunk - 1) / kChunk + 1);
+  z.words = (std::max(z.tot_a, nn) + 63) / 64 + 1;
+  z.fwords = (nn + 63) / 64 + 1;
+  return z;
+}
+
+// Allocate a workspace through `al(void **, bytes)`; `full` adds the k-core
+// and PageRank arrays.
+template <class Alloc>
+static sx_status work_alloc(Alloc al, long long n, long long m, bool directed, int gmax, bool full,
+                            Work &w) {
+  memset(&w, 0, sizeof w);
+  const Sizing z = work_sizing(n, m, directed, gmax);
+  if (z.tot_l > 0xFFFFFFF0ull || z.tot_s > 0xFFFFFFF0ull)
+    return fail(SX_EUNSUPPORTED, "graph too large for 32-bit worklist indices");
+  const size_t nn = (size_t)std::max<long long>(n, 1);
+  sx_status r;
+#define ALLOC(ptr, bytes)                                  \
+  do {                                                     \
+    if ((r = al((void **)&(ptr), (bytes))) != SX_OK) return r; \
+  } while (0)
+  for (int p = 0; p < 2; ++p) {
+    ALLOC(w.reg_s[p], 4 * z.tot_s);
+    ALLOC(w.reg_m[p], 4 * z.tot_s);
+    ALLOC(w.reg_l[p], 8 * z.tot_l);
+  }
+  w.tot_s = (unsigned)z.tot_s;
+  w.tot_m = (unsigned)z.tot_s;
+  w.tot_l = (unsigned)z.tot_l;
+  ALLOC(w.rec, sizeof(WgRec) * NSLOTS * kMaxGrid);
+  for (int b = 0; b < NBINS; ++b) ALLOC(w.bits[b], 8 * z.words);
+  ALLOC(w.fbits, 8 * z.fwords);
+  ALLOC(w.stamp, 4 * nn);
+  ALLOC(w.ctrl, sizeof(Ctrl));
+  if (full) {
+    for (int p = 0; p < 2; ++p) {
+      ALLOC(w.alive[p], 4 * z.tot_a);
+      ALLOC(w.contrib[p], 4 * nn);
+    }
+    w.tot_a = (unsigned)z.tot_a;
+    ALLOC(w.alive_cnt, 4 * 2 * kMaxGrid);
+    ALLOC(w.alive_min, 4 * 2 * kMaxGrid);
+    ALLOC(w.deg, 4 * nn);
+    ALLOC(w.dang, 4 * 4 * kMaxGrid);
+  }
+#undef ALLOC
+  return SX_OK;
+}
+
 static sx_status validate_host(const sx_graph_desc *d) {
   const int32_t *off = d->offsets;
   if (off[0] != 0) return fail(SX_EINVAL, "offsets[0] != 0");
@@ -302,27 +373,8 @@ extern "C" sx_status sx_graph_load(sx_ctx *ctx, const sx_graph_desc *d, void *hi
   }
   // workspace
   Work &w = G->w;
-  const size_t nn = (size_t)std::max(n, 1);
-  const size_t words = (nn + 63) / 64 + 1;
-  const size_t large_cap = nn + (size_t)(m / kChunk) + 2 + (size_t)(m / kChunk);
-  w.qcap_small = (unsigned)nn;
-  w.qcap_med = (unsigned)nn;
-  w.qcap_large = (unsigned)std::min<size_t>(large_cap, 0xFFFFFFF0u);
-  for (int p = 0; p < 2; ++p) {
-    TRY(dalloc_t(G, &w.q[p][0], nn));
-    TRY(dalloc_t(G, &w.q[p][1], nn));
-    TRY(dalloc_t(G, &w.ql[p], large_cap));
-    TRY(dalloc_t(G, &w.contrib[p], nn));
-    TRY(dalloc_t(G, &w.alive[p], nn));
-  }
-  for (int b = 0; b < NBINS; ++b) TRY(dalloc_t(G, &w.bits[b], words));
-  TRY(dalloc_t(G, &w.fbits, words));
-  TRY(dalloc_t(G, &w.wavecnt, (size_t)kMaxGrid * kWaves * NBINS));
-  TRY(dalloc_t(G, &w.wgc, (size_t)kMaxGrid));
-  TRY(dalloc_t(G, &w.stamp, nn));
-  TRY(dalloc_t(G, &w.deg, nn));
-  TRY(dalloc_t(G, &w.dang, (size_t)4 * kMaxGrid));
-  TRY(dalloc_t(G, &w.ctrl, 1));
+  TRY(work_alloc([&](void **p, size_t bytes) { return dalloc(G, p, bytes); }, n, m, !undirected,
+                 kMaxGrid, true, w));
   HTRY(hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), st));
   HTRY(hipHostMalloc((void **)&G->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
   HTRY(hipEventCreate(&G->ev0));
@@ -407,10 +459,12 @@ static Params make_params(const sx_program *p, const sx_graph *G, int grid) {
   P.t2 = pol.bin_large > 0 ? pol.bin_large : 256;
   if (P.t2 < P.t1) P.t2 = P.t1;
   P.chunk = kChunk;
-  const long long per_wave = pol.online_cap > 0 ? pol.online_cap : 64;
-  long long cap = per_wave * (long long)grid * kWaves;
-  if (pol.filter == SX_FILTER_ONLINE) cap = LLONG_MAX;
-  P.online_cap = (unsigned)std::min<long long>(cap, 0xFFFFFFF0ll);
+  // online filter limit per workgroup and bin: the caller's entries per
+  // wavefront (JIT filter only); otherwise the whole region
+  const long long lim = pol.filter == SX_FILTER_JIT && pol.online_cap > 0
+                            ? (long long)pol.online_cap * kWaves : 0;
+  P.online_cap = (unsigned)std::min<long long>(lim, 0xFFFFFFF0ll);
+  (void)grid;
   P.filter = pol.filter;
   P.direction = pol.direction;
   P.alpha = 14.0f;
@@ -437,14 +491,21 @@ static sx_status ctrl_error(const Ctrl *c) {
   if (c->error.v[0] == SX_ERR_DEADLOCK)
     return fail(SX_EDEADLOCK, "global barrier watchdog fired");
   if (c->error.v[0] == SX_ERR_OVERFLOW) return fail(SX_EOVERFLOW, "distance reached 0xFFFFFFFF");
+  if (c->error.v[0] == SX_ERR_CAPACITY)
+    return fail(SX_EHIP, "a scanned worklist exceeded its regions (engine bug)");
   if (c->error.v[0]) return fail(SX_EHIP, "device error %u", c->error.v[0]);
   return SX_OK;
 }
 
 static void fill_stats(const Ctrl *c, int launches, float ms, sx_run_stats *stats) {
   if (!stats) return;
-  stats->edges_inspected = (int64_t)(*(const unsigned long long *)&c->stats.v[0]);
-  stats->vertex_expansions = (int64_t)(*(const unsigned long long *)&c->stats.v[2]);
+  unsigned long long e = 0, x = 0;
+  for (int i = 0; i < kStatLines; ++i) {
+    e += *(const unsigned long long *)&c->statw[i].v[0];
+    x += *(const unsigned long long *)&c->statw[i].v[2];
+  }
+  stats->edges_inspected = (int64_t)e;
+  stats->vertex_expansions = (int64_t)x;
   stats->ballot_iters = (int32_t)c->stats.v[4];
   stats->pull_iters = (int32_t)c->stats.v[5];
   stats->iterations = (int32_t)c->stats.v[6];
@@ -453,6 +514,63 @@ static void fill_stats(const Ctrl *c, int launches, float ms, sx_run_stats *stat
 }
 
 // ---------------------------------------------------- BFS / SSSP runs ---
+// Totals of one record slot (the host side of view_build).
+struct HostTotals {
+  unsigned long long cnt[NBINS], mf;
+  unsigned nf, ovf;
+};
+static sx_status read_totals(const Work &w, int slot, int grid, hipStream_t st,
+                             std::vector<WgRec> &buf, HostTotals &T) {
+  buf.resize((size_t)grid);
+  HIP_TRY(hipMemcpyAsync(buf.data(), w.rec + (size_t)slot * kMaxGrid, sizeof(WgRec) * grid,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  memset(&T, 0, sizeof T);
+  for (const WgRec &r : buf) {
+    for (int b = 0; b < NBINS; ++b) T.cnt[b] += r.cnt[b];
+    T.nf += r.nf;
+    T.mf += r.mf;
+    T.ovf |= r.ovf;
+  }
+  return SX_OK;
+}
+
+// The host decision of the one-phase loop: decide_core plus the learned
+// policy, evaluated exactly as the device does it.
+static Decision host_decide(const sx_ctx *ctx, const sx_policy &pol, Params &P, bool sssp,
+                            const sx_graph *G, int it, bool pulling, const HostTotals &T,
+                            unsigned long long &mu, PolicyState &ps) {
+  DecideIn in;
+  in.nf = T.nf;
+  in.mf = T.mf;
+  in.ovf = T.ovf;
+  in.it = it;
+  in.pulling = pulling;
+  in.vote = !sssp;
+  in.n = G->g.n;
+  in.m = G->g.m;
+  Decision d = decide_core(in, P, mu);
+  if (!d.done && P.learned) {
+    float x[kMlpIn], y[kMlpOut];
+    policy_features(in.nf, in.mf, sssp ? (unsigned long long)G->g.m : mu, G->g.n, G->g.m, ps,
+                    pulling, x);
+    mlp_eval_host(ctx->mlp.data(), x, y);
+    if (pol.direction == SX_DIR_AUTO) {
+      if (!pulling) d.to_pull = y[0] > 0.f;
+      else d.to_push = !(y[0] > 0.f);
+    }
+    if (!pulling && !d.to_pull) d.ballot = in.ovf || (P.filter == 0 ? y[1] > 0.f : P.filter == 2);
+    if (!P.bins_fixed) {
+      P.t1 = 1 << clamp_log2(y[2], 2, 8);
+      const int t2 = 1 << clamp_log2(y[3], 6, 12);
+      P.t2 = std::max(t2, P.t1);
+    }
+  }
+  ps.nf_prev = in.nf;
+  ps.reached += in.nf;
+  return d;
+}
+
 static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out, hipStream_t st,
                                sx_run_stats *stats) {
   const int sssp = p->ap.algo == SX_SSSP;
@@ -461,11 +579,10 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   const bool sequenced = p->pol.fused == SX_SEQUENCED || p->pol.fused == SX_FUSE_AUTO;
   int grid;
   if (sequenced) {
-    grid = plain_grid(ctx, seq_kernel(sssp));
+    grid = plain_grid(ctx, trav_kernel(TK_SEQ, sssp));
     if (p->pol.grid_wgs > 0) grid = std::min(grid, p->pol.grid_wgs);
   } else if (fused) {
-    grid = std::min(persistent_grid(ctx, trav_kernel(TK_PUSH_FUSED, sssp), p->pol.grid_wgs),
-                    persistent_grid(ctx, trav_kernel(TK_PULL_FUSED, sssp), p->pol.grid_wgs));
+    grid = persistent_grid(ctx, trav_kernel(TK_FUSED, sssp), p->pol.grid_wgs);
   } else {
     grid = plain_grid(ctx, trav_kernel(TK_PUSH_STEP, sssp));
     if (p->pol.grid_wgs > 0) grid = std::min(grid, p->pol.grid_wgs);
@@ -479,19 +596,17 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   a.src = src;
   a.mlp = ctx->d_mlp;
   if (a.P.learned && !ctx->d_mlp) return fail(SX_ESTATE, "learned policy without loaded MLP");
-  // unexplored arcs (BFS direction rule): computed on the device by the
-  // initialisation kernel; the one-phase loop reads it back below
-  unsigned long long mu = 0;
   int launches = 0;
   HIP_TRY(hipEventRecord(G->ev0, st));
-  HIP_TRY(trav_init(a, sssp, 0ull, st));
+  // unexplored arcs (BFS direction rule) are computed on the device
+  HIP_TRY(trav_init(a, sssp, 0ull, grid, st));
   ++launches;
   if (sequenced) {
     HIP_TRY(seq_start(G->w.ctrl, p->pol.direction == SX_DIR_PULL, st));
     unsigned L = 0;
     int batch = 8;
     for (;;) {
-      for (int k = 0; k < batch; ++k) HIP_TRY(seq_launch(sssp, a, L++, grid, st));
+      for (int k = 0; k < batch; ++k) HIP_TRY(trav_launch(TK_SEQ, sssp, a, (int)L++, 0, grid, st));
       launches += batch;
       HIP_TRY(hipEventRecord(G->ev1, st));
       sx_status s = read_ctrl(G, st);
@@ -505,12 +620,12 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
       if (L > (unsigned)(8 * (long long)G->g.n + 1024)) return fail(SX_EHIP, "run did not converge");
     }
   } else if (fused) {
-    bool pull_next = p->pol.direction == SX_DIR_PULL;
+    int pull_next = p->pol.direction == SX_DIR_PULL ? 1 : 0;
     for (int batch = 0;; ++batch) {
       for (int k = 0; k < 4; ++k) {
-        HIP_TRY(trav_launch(pull_next ? TK_PULL_FUSED : TK_PUSH_FUSED, sssp, a, 0, grid, st));
+        HIP_TRY(trav_launch(TK_FUSED, sssp, a, 0, pull_next, grid, st));
         ++launches;
-        pull_next = !pull_next;
+        pull_next ^= 1;
       }
       HIP_TRY(hipEventRecord(G->ev1, st));
       sx_status s = read_ctrl(G, st);
@@ -522,67 +637,43 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
     }
   } else {
     bool pulling = p->pol.direction == SX_DIR_PULL;
+    bool rebuilt = false;
     PolicyState ps{0u, 0ull};
-    {
-      sx_status s0 = read_ctrl(G, st);
-      if (s0 != SX_OK) return s0;
-      mu = *(const unsigned long long *)&G->h_ctrl->state.v[6];
-    }
+    sx_status s0 = read_ctrl(G, st);
+    if (s0 != SX_OK) return s0;
+    unsigned long long mu = *(const unsigned long long *)&G->h_ctrl->state.v[6];
+    std::vector<WgRec> buf;
     for (int it = 0;; ++it) {
       if (!pulling) {
-        HIP_TRY(reset_slot(G->w.ctrl, (it + 2) % 3, st));
-        HIP_TRY(trav_launch(TK_PUSH_STEP, sssp, a, it, grid, st));
-        launches += 2;
+        HIP_TRY(trav_launch(TK_PUSH_STEP, sssp, a, it, rebuilt ? 1 : 0, grid, st));
+        launches += 1;
       } else {
-        HIP_TRY(trav_launch(TK_PULL_SCAN, sssp, a, it, grid, st));
-        HIP_TRY(reset_slot(G->w.ctrl, (it + 1) % 3, st));
-        HIP_TRY(reset_slot(G->w.ctrl, (it + 2) % 3, st));
-        HIP_TRY(trav_launch(TK_PULL_LISTS, sssp, a, it, grid, st));
-        HIP_TRY(trav_launch(TK_PULL_STEP, sssp, a, it, grid, st));
-        launches += 5;
+        HIP_TRY(trav_launch(TK_PULL_SCAN, sssp, a, it, 0, grid, st));
+        HIP_TRY(trav_launch(TK_PULL_STEP, sssp, a, it, 0, grid, st));
+        launches += 2;
       }
       sx_status s = read_ctrl(G, st);
       if (s != SX_OK) return s;
       s = ctrl_error(G->h_ctrl);
       if (s != SX_OK) return s;
-      const Counters &q = G->h_ctrl->q[(it + 1) % 3];
-      DecideIn in;
-      in.nf = q.nf;
-      in.mf = q.mf;
-      in.ovf = q.overflow;
-      in.it = it;
-      in.pulling = pulling;
-      in.vote = !sssp;
-      in.n = G->g.n;
-      in.m = G->g.m;
-      Decision d = decide_core(in, a.P, mu);
-      if (!d.done && a.P.learned) {
-        float x[kMlpIn], y[kMlpOut];
-        policy_features(in.nf, in.mf, sssp ? (unsigned long long)G->g.m : mu, G->g.n, G->g.m, ps,
-                        pulling, x);
-        mlp_eval_host(ctx->mlp.data(), x, y);
-        if (p->pol.direction == SX_DIR_AUTO) {
-          if (!pulling) d.to_pull = y[0] > 0.f;
-          else d.to_push = !(y[0] > 0.f);
-        }
-        if (!pulling && !d.to_pull)
-          d.ballot = in.ovf || (a.P.filter == 0 ? y[1] > 0.f : a.P.filter == 2);
-        if (!a.P.bins_fixed) {
-          a.P.t1 = 1 << clamp_log2(y[2], 2, 8);
-          const int t2 = 1 << clamp_log2(y[3], 6, 12);
-          a.P.t2 = std::max(t2, a.P.t1);
-        }
-      }
-      ps.nf_prev = in.nf;
-      ps.reached += in.nf;
+      HostTotals T;
+      s = read_totals(G->w, (it + 1) % 3, grid, st, buf, T);
+      if (s != SX_OK) return s;
+      Decision d = host_decide(ctx, p->pol, a.P, sssp, G, it, pulling, T, mu, ps);
       if (d.done) break;
-      bool rebuild = d.ballot;
-      if (pulling && d.to_push) { pulling = false; rebuild = q.overflow != 0; }
-      else if (!pulling && d.to_pull) pulling = true;
-      if (rebuild && !pulling) {
-        HIP_TRY(trav_launch(TK_BALLOT1, sssp, a, it, grid, st));
-        HIP_TRY(trav_launch(TK_BALLOT2, sssp, a, it, grid, st));
-        launches += 2;
+      bool rebuild = false;
+      if (!pulling) {
+        if (d.to_pull) pulling = true;
+        else rebuild = d.ballot;
+      } else if (d.to_push) {
+        pulling = false;
+        rebuild = T.ovf != 0;
+      }
+      rebuilt = false;
+      if (rebuild) {
+        HIP_TRY(trav_launch(TK_BALLOT, sssp, a, it, 0, grid, st));
+        launches += 1;
+        rebuilt = true;
       }
     }
     HIP_TRY(hipEventRecord(G->ev1, st));
@@ -742,16 +833,17 @@ extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_
   a.P = make_params(&hp, G, grid);
   a.state_i = (int *)d_out;
   a.src = src;
-  const Params P0 = a.P;
+  const Work &w = G->w;
   Snapshot snap;
   for (int par = 0; par < 2; ++par) {
-    snap.items.push_back({G->w.q[par][0], sizeof(int) * (size_t)n});
-    snap.items.push_back({G->w.q[par][1], sizeof(int) * (size_t)n});
-    snap.items.push_back({G->w.ql[par], sizeof(unsigned long long) * G->w.qcap_large});
+    snap.items.push_back({w.reg_s[par], sizeof(int) * (size_t)w.tot_s});
+    snap.items.push_back({w.reg_m[par], sizeof(int) * (size_t)w.tot_m});
+    snap.items.push_back({w.reg_l[par], sizeof(unsigned long long) * (size_t)w.tot_l});
   }
+  snap.items.push_back({w.rec, sizeof(WgRec) * NSLOTS * kMaxGrid});
   snap.items.push_back({d_out, sizeof(int) * (size_t)n});
-  snap.items.push_back({G->w.stamp, sizeof(int) * (size_t)n});
-  snap.items.push_back({G->w.ctrl, sizeof(Ctrl)});
+  snap.items.push_back({w.stamp, sizeof(int) * (size_t)n});
+  snap.items.push_back({w.ctrl, sizeof(Ctrl)});
   for (auto &it : snap.items) {
     void *c = nullptr;
     hipError_t e = hipMalloc(&c, it.second);
@@ -762,19 +854,19 @@ extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_
   HIP_TRY(hipMemcpyAsync(h_off, G->g.off + src, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   unsigned long long mu = (unsigned long long)(G->g.m - (h_off[1] - h_off[0]));
-  HIP_TRY(trav_init(a, sssp, mu, st));
+  HIP_TRY(trav_init(a, sssp, mu, grid, st));
   const int arm_t[4][2] = {{16, 256}, {64, 256}, {64, 1024}, {256, 2048}};
   // features of the decision before iteration `it`, computed exactly as the
-  // fused kernels do after the previous iteration (before iteration 0: the
-  // source alone)
+  // device does after the previous iteration (before iteration 0: the source
+  // alone)
   PolicyState ps{0u, 0ull};
   float xnext[8];
   policy_features(1u, (unsigned long long)(h_off[1] - h_off[0]),
                   sssp ? (unsigned long long)G->g.m : mu, n, G->g.m, ps, false, xnext);
-  bool last_ovf = false;
-  bool pulling = false;
+  bool last_ovf = false, pulling = false, rebuilt = false;
   int rec = 0;
   hipEvent_t e0 = G->ev0, e1 = G->ev1;
+  std::vector<WgRec> buf;
   for (int it = 0;; ++it) {
     if (rec < max_records && it % stride == 0) {
       float *x = features + (size_t)rec * 8;
@@ -784,21 +876,20 @@ extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_
       if (s != SX_OK) return s;
       for (int arm = 0; arm < SX_POLICY_ARMS; ++arm) {
         TravArgs b = a;
+        // arm 0 pushes the online lists: not available after a pull
+        // iteration or an overflow
         if (arm == 0 && (pulling || last_ovf)) { t[arm] = NAN; continue; }
         HIP_TRY(hipEventRecord(e0, st));
         if (arm >= 1 && arm <= 4) {
           b.P.t1 = arm_t[arm - 1][0];
           b.P.t2 = arm_t[arm - 1][1];
-          HIP_TRY(trav_launch(TK_BALLOT1, sssp, b, it - 1, grid, st));
-          HIP_TRY(trav_launch(TK_BALLOT2, sssp, b, it - 1, grid, st));
-        }
-        if (arm <= 4) {
-          HIP_TRY(trav_launch(TK_PUSH_STEP, sssp, b, it, grid, st));
+          HIP_TRY(trav_launch(TK_BALLOT, sssp, b, it - 1, 0, grid, st));
+          HIP_TRY(trav_launch(TK_PUSH_STEP, sssp, b, it, 1, grid, st));
+        } else if (arm == 0) {
+          HIP_TRY(trav_launch(TK_PUSH_STEP, sssp, b, it, rebuilt ? 1 : 0, grid, st));
         } else {
-          HIP_TRY(trav_launch(TK_PULL_SCAN, sssp, b, it, grid, st));
-          HIP_TRY(reset_slot(G->w.ctrl, (it + 1) % 3, st));
-          HIP_TRY(trav_launch(TK_PULL_LISTS, sssp, b, it, grid, st));
-          HIP_TRY(trav_launch(TK_PULL_STEP, sssp, b, it, grid, st));
+          HIP_TRY(trav_launch(TK_PULL_SCAN, sssp, b, it, 0, grid, st));
+          HIP_TRY(trav_launch(TK_PULL_STEP, sssp, b, it, 0, grid, st));
         }
         HIP_TRY(hipEventRecord(e1, st));
         HIP_TRY(hipEventSynchronize(e1));
@@ -813,41 +904,37 @@ extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_
     }
     // the heuristic's own iteration, exactly as in the one-phase run loop
     if (!pulling) {
-      HIP_TRY(reset_slot(G->w.ctrl, (it + 2) % 3, st));
-      HIP_TRY(trav_launch(TK_PUSH_STEP, sssp, a, it, grid, st));
+      HIP_TRY(trav_launch(TK_PUSH_STEP, sssp, a, it, rebuilt ? 1 : 0, grid, st));
     } else {
-      HIP_TRY(trav_launch(TK_PULL_SCAN, sssp, a, it, grid, st));
-      HIP_TRY(reset_slot(G->w.ctrl, (it + 1) % 3, st));
-      HIP_TRY(reset_slot(G->w.ctrl, (it + 2) % 3, st));
-      HIP_TRY(trav_launch(TK_PULL_LISTS, sssp, a, it, grid, st));
-      HIP_TRY(trav_launch(TK_PULL_STEP, sssp, a, it, grid, st));
+      HIP_TRY(trav_launch(TK_PULL_SCAN, sssp, a, it, 0, grid, st));
+      HIP_TRY(trav_launch(TK_PULL_STEP, sssp, a, it, 0, grid, st));
     }
     sx_status s = read_ctrl(G, st);
     if (s != SX_OK) return s;
     s = ctrl_error(G->h_ctrl);
     if (s != SX_OK) return s;
-    const Counters &q = G->h_ctrl->q[(it + 1) % 3];
-    DecideIn in;
-    in.nf = q.nf;
-    in.mf = q.mf;
-    in.ovf = q.overflow;
-    in.it = it;
-    in.pulling = pulling;
-    in.vote = !sssp;
-    in.n = n;
-    in.m = G->g.m;
-    Decision d = decide_core(in, P0, mu);
-    policy_features(in.nf, in.mf, sssp ? (unsigned long long)G->g.m : mu, n, G->g.m, ps, pulling, xnext);
-    ps.nf_prev = in.nf;
-    ps.reached += in.nf;
-    last_ovf = in.ovf != 0;
+    HostTotals T;
+    s = read_totals(w, (it + 1) % 3, grid, st, buf, T);
+    if (s != SX_OK) return s;
+    Params P0 = a.P;
+    const PolicyState ps_before = ps;
+    Decision d = host_decide(p->ctx, hp.pol, P0, sssp, G, it, pulling, T, mu, ps);
+    policy_features(T.nf, T.mf, sssp ? (unsigned long long)G->g.m : mu, n, G->g.m, ps_before,
+                    pulling, xnext);
+    last_ovf = T.ovf != 0;
     if (d.done) break;
-    bool rebuild = d.ballot;
-    if (pulling && d.to_push) { pulling = false; rebuild = q.overflow != 0; }
-    else if (!pulling && d.to_pull) pulling = true;
-    if (rebuild && !pulling) {
-      HIP_TRY(trav_launch(TK_BALLOT1, sssp, a, it, grid, st));
-      HIP_TRY(trav_launch(TK_BALLOT2, sssp, a, it, grid, st));
+    bool rebuild = false;
+    if (!pulling) {
+      if (d.to_pull) pulling = true;
+      else rebuild = d.ballot;
+    } else if (d.to_push) {
+      pulling = false;
+      rebuild = T.ovf != 0;
+    }
+    rebuilt = false;
+    if (rebuild) {
+      HIP_TRY(trav_launch(TK_BALLOT, sssp, a, it, 0, grid, st));
+      rebuilt = true;
       last_ovf = false;
     }
   }
@@ -857,6 +944,8 @@ extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_
 }
 
 // -------------------------------------------------------------- batches ---
+static const int kMaxTeam = 64;  // workgroups per team (sx_batch_config)
+
 static sx_status team_workspaces(sx_ctx *ctx, int nteams, int n, long long m) {
   if ((int)ctx->team_work.size() >= nteams && ctx->team_n >= n && ctx->team_m >= m) return SX_OK;
   for (void *p : ctx->team_allocs) (void)hipFree(p);
@@ -864,9 +953,6 @@ static sx_status team_workspaces(sx_ctx *ctx, int nteams, int n, long long m) {
   ctx->team_work.clear();
   n = std::max(n, ctx->team_n);
   m = std::max(m, ctx->team_m);
-  const size_t nn = (size_t)std::max(n, 1);
-  const size_t words = (nn + 63) / 64 + 1;
-  const size_t large_cap = nn + 2 * (size_t)(m / kChunk) + 2;
   auto al = [&](void **p, size_t bytes) -> sx_status {
     hipError_t e = hipMalloc(p, bytes ? bytes : 256);
     if (e != hipSuccess) return fail(SX_ENOMEM, "team workspace: %s", hipGetErrorString(e));
@@ -875,24 +961,11 @@ static sx_status team_workspaces(sx_ctx *ctx, int nteams, int n, long long m) {
   };
   for (int t = 0; t < nteams; ++t) {
     Work w;
-    memset(&w, 0, sizeof w);
-    sx_status r;
-    for (int p = 0; p < 2; ++p) {
-      if ((r = al((void **)&w.q[p][0], 4 * nn)) != SX_OK) return r;
-      if ((r = al((void **)&w.q[p][1], 4 * nn)) != SX_OK) return r;
-      if ((r = al((void **)&w.ql[p], 8 * large_cap)) != SX_OK) return r;
-    }
-    for (int b = 0; b < NBINS; ++b)
-      if ((r = al((void **)&w.bits[b], 8 * words)) != SX_OK) return r;
-    if ((r = al((void **)&w.fbits, 8 * words)) != SX_OK) return r;
-    if ((r = al((void **)&w.wavecnt, sizeof(unsigned) * 64 * kWaves * NBINS)) != SX_OK) return r;
-    if ((r = al((void **)&w.wgc, sizeof(WgCount) * 64)) != SX_OK) return r;
-    if ((r = al((void **)&w.stamp, 4 * nn)) != SX_OK) return r;
-    if ((r = al((void **)&w.ctrl, sizeof(Ctrl))) != SX_OK) return r;
+    // teams have at most kMaxTeam workgroups; directed graphs of the batch
+    // only push / pull (no k-core), so `arcs` is m
+    sx_status r = work_alloc(al, n, m, false, kMaxTeam, false, w);
+    if (r != SX_OK) return r;
     HIP_TRY(hipMemset(w.ctrl, 0, sizeof(Ctrl)));
-    w.qcap_small = (unsigned)nn;
-    w.qcap_med = (unsigned)nn;
-    w.qcap_large = (unsigned)std::min<size_t>(large_cap, 0xFFFFFFF0u);
     ctx->team_work.push_back(w);
   }
   ctx->team_n = n;
@@ -937,7 +1010,7 @@ extern "C" sx_status sx_run_batch(sx_ctx *ctx, const sx_query *q, int32_t nq, co
   int per = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel(), kBlock, 0));
   const int grid = std::max(1, std::min(per * ctx->cus, kMaxGrid));
-  if (c.team_wgs < 1 || c.team_wgs > 64) return fail(SX_EINVAL, "team_wgs must be in 1..64");
+  if (c.team_wgs < 1 || c.team_wgs > kMaxTeam) return fail(SX_EINVAL, "team_wgs must be in 1..%d", kMaxTeam);
   const int team = std::min(c.team_wgs, grid);
   const int nteams = grid / team;
   s = team_workspaces(ctx, nteams, nmax, mmax);
@@ -1012,6 +1085,7 @@ extern "C" sx_status sx_run_batch(sx_ctx *ctx, const sx_query *q, int32_t nq, co
     HIP_TRY(hipMemcpy(&err, &ctx->team_work[t].ctrl->error.v[0], 4, hipMemcpyDeviceToHost));
     if (err == SX_ERR_DEADLOCK) return fail(SX_EDEADLOCK, "team %d barrier watchdog fired", t);
     if (err == SX_ERR_OVERFLOW) return fail(SX_EOVERFLOW, "distance overflow in team %d", t);
+    if (err == SX_ERR_CAPACITY) return fail(SX_EHIP, "team %d: scanned worklist exceeded its regions", t);
     if (err) return fail(SX_EHIP, "team %d device error %u", t, err);
   }
   for (int i = 0; i < nq; ++i)
@@ -1088,18 +1162,20 @@ extern "C" sx_status sx_kernel_info_get(sx_ctx *ctx, const char *name, sx_kernel
   if (!ctx || !name || !out) return fail(SX_EINVAL, "NULL argument");
   struct Named { const char *name; const void *k; bool persistent; };
   const Named table[] = {
-      {"bfs_push_fused", trav_kernel(TK_PUSH_FUSED, 0), true},
-      {"bfs_pull_fused", trav_kernel(TK_PULL_FUSED, 0), true},
-      {"sssp_push_fused", trav_kernel(TK_PUSH_FUSED, 1), true},
-      {"sssp_pull_fused", trav_kernel(TK_PULL_FUSED, 1), true},
+      {"bfs_fused", trav_kernel(TK_FUSED, 0), true},
+      {"sssp_fused", trav_kernel(TK_FUSED, 1), true},
+      {"bfs_seq", trav_kernel(TK_SEQ, 0), false},
+      {"sssp_seq", trav_kernel(TK_SEQ, 1), false},
       {"bfs_push_step", trav_kernel(TK_PUSH_STEP, 0), false},
       {"bfs_pull_step", trav_kernel(TK_PULL_STEP, 0), false},
       {"sssp_push_step", trav_kernel(TK_PUSH_STEP, 1), false},
       {"sssp_pull_step", trav_kernel(TK_PULL_STEP, 1), false},
-      {"ballot_count", trav_kernel(TK_BALLOT1, 0), false},
-      {"ballot_write", trav_kernel(TK_BALLOT2, 0), false},
+      {"ballot_scan", trav_kernel(TK_BALLOT, 0), false},
+      {"pull_scan", trav_kernel(TK_PULL_SCAN, 0), false},
       {"kcore_fused", kcore_kernel(), true},
+      {"kcore_seq", kcore_seq_kernel(), false},
       {"pagerank_fused", pagerank_kernel(), true},
+      {"batch", batch_kernel(), true},
   };
   for (const Named &t : table) {
     if (strcmp(t.name, name) != 0) continue;

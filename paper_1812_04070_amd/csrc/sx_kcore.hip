@@ -13,23 +13,29 @@
 //            only one that activates the neighbour, so every vertex enters a
 //            frontier exactly once.
 //
-// Task management: a level starts with a ballot-filter scan over the list of
-// vertices still alive (sorted, binned frontier of degree <= k, plus the
-// compacted list of survivors and their minimum degree so that empty levels
-// are skipped); the deletions within a level are chained by the online
-// filter.  The JIT switch of Section 4 applies: an overflowing online filter
-// is replaced by a fresh scan of the alive list.  A directed graph counts in-
-// plus out-arcs; deleting v decrements through both its CSR and CSC rows.
+// Task management: a level starts with a ballot-filter scan of the vertices
+// still alive.  Every workgroup keeps its own alive list (a region of the
+// alive arrays) and scans only that: the frontier (degree <= k) goes
+// sorted and binned into its bin regions, the survivors (degree > k) are
+// compacted into its region of the other alive array, with their count and
+// minimum degree in per-workgroup words, so that empty levels are skipped
+// without a grid-wide atomic.  The deletions within a level are chained by
+// the online filter.  The JIT switch of Section 4 applies: an overflowing
+// online filter is replaced by a fresh scan.  A directed graph counts in- plus
+// out-arcs; deleting v decrements through both its CSR and CSC rows.
 #include "sx_frontier.hpp"
 #include "sx_kernels.hpp"
 
 namespace sx {
 
-
 struct LdsK {
   int small[kWaves][192];
-  unsigned cnt[kWaves * 8];
+  LdsBins bins;
+  LdsView view;
+  LdsBallot ball;
   long long red[kWaves];
+  unsigned wmin[kWaves];
+  unsigned surv;
 };
 
 SX_DEV int total_degree(const DevGraph &g, int v) {
@@ -38,129 +44,118 @@ SX_DEV int total_degree(const DevGraph &g, int v) {
   return d;
 }
 
-// aux line layout: scan number s reads alive list (s & 1) whose length is
-// aux[s % 3], appends the survivors to list (s+1) & 1, length aux[(s+1) % 3],
-// and their minimum degree to aux[3 + s % 3]; it resets the slots of scan
-// s+2 (length) and s+1 (minimum), which nobody reads any more.  [10] level
-// k, [11] scan number, [12] next step kind (0 scan, 1 peel), [13] step index.
-enum { AUX_K = 10, AUX_SCAN = 11, AUX_KIND = 12, AUX_STEP = 13 };
+// Alive regions: workgroup b of G owns entries [b * cap, b * cap + cnt) of
+// each alive array, cap a multiple of 64 (scan positions align with the
+// ballot words).
+SX_DEV unsigned alive_cap(const Work &w, unsigned G) { return (w.tot_a / G) & ~63u; }
 
-// Level scan, pass 1: positions [0, cA) of the alive list.
-SX_DEV void kscan_pass1(const KArgs &a, int k, int scan_no, LdsK &lds) {
+// Level scan number s at level k: reads this workgroup's alive list in
+// alive[s & 1], writes the frontier into parity `fp`, slot SLOT_SCAN, and the
+// survivors into alive[(s + 1) & 1] with their count / minimum degree.
+SX_DEV void kscan(const VGrid &vg, const KArgs &a, int k, int s, int fp, LdsK &lds) {
   const Work &w = a.w;
-  Ctrl *C = w.ctrl;
-  const int pa = scan_no & 1;
-  const int cA = (int)load_relaxed(&C->aux.v[scan_no % 3]);
-  const int *A = w.alive[pa];
-  int *B = w.alive[pa ^ 1];
-  unsigned *surv = &C->aux.v[(scan_no + 1) % 3];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    store_relaxed(&C->aux.v[(scan_no + 2) % 3], 0u);
-    store_relaxed(&C->aux.v[3 + (scan_no + 1) % 3], 0xFFFFFFFFu);
-  }
   const DevGraph &g = a.g;
-  Tiling T(cA, gridDim.x * kWaves);
-  // survivors: alive with degree > k, appended (one atomic per wavefront)
-  {
-    const unsigned gw = blockIdx.x * kWaves + wave_in_wg();
-    const long long start = (long long)gw * T.tile;
-    unsigned mind = 0xFFFFFFFFu;
-    for (int s = 0; s < T.tile && start + s < cA; s += 64) {
-      const long long i = start + s + lane_id();
-      bool keep = false;
-      int v = 0;
-      if (i < cA) {
-        v = A[i];
-        if (a.core[v] == -1) {
-          const int d = w.deg[v];
-          if (d > k) { keep = true; mind = (unsigned)d < mind ? (unsigned)d : mind; }
-        }
-      }
-      const uint64_t mk = ballot(keep);
-      if (mk) {
-        unsigned base = 0;
-        if (lane_id() == 0) base = atomic_add_u32(surv, (unsigned)__popcll(mk));
-        base = __shfl(base, 0);
-        if (keep) B[base + lane_prefix(mk)] = v;
+  const unsigned G = vg.nb, bid = vg.bid;
+  const unsigned cap = alive_cap(w, G);
+  const long long lo = (long long)bid * cap;
+  const unsigned cnt = w.alive_cnt[(size_t)(s & 1) * kMaxGrid + bid];
+  const long long hi = lo + (cnt < cap ? cnt : cap);
+  const int *A = w.alive[s & 1];
+  int *B = w.alive[(s + 1) & 1] + lo;
+  if (threadIdx.x == 0) lds.surv = 0;
+  __syncthreads();
+  unsigned mind = 0xFFFFFFFFu;
+  auto probe = [&](long long i, bool ok) {
+    int v = 0, d = 0;
+    bool alive = false;
+    if (ok) {
+      v = A[i];
+      alive = (unsigned)v < (unsigned)g.n && a.core[v] == -1;
+      if (alive) d = w.deg[v];
+    }
+    const bool keep = alive && d > k;
+    const uint64_t mk = ballot(keep);
+    if (mk) {
+      const int leader = __ffsll((long long)mk) - 1;
+      unsigned base = 0;
+      if (lane_id() == leader) base = atomicAdd(&lds.surv, (unsigned)__popcll(mk));
+      base = __shfl(base, leader);
+      if (keep) {
+        B[base + lane_prefix(mk)] = v;
+        mind = (unsigned)d < mind ? (unsigned)d : mind;
       }
     }
-    mind = wave_min_u(mind);
-    if (lane_id() == 0 && mind != 0xFFFFFFFFu)
-      __hip_atomic_fetch_min(&C->aux.v[3 + scan_no % 3], mind, __ATOMIC_RELAXED, SX_AG);
-  }
-  // frontier: alive with degree <= k, ballot words per degree bin
-  auto pred = [&](int i) {
-    const int v = A[i];
-    return a.core[v] == -1 && w.deg[v] <= k;
+    return alive && d <= k;
   };
-  auto degree = [&](int i) { return total_degree(g, A[i]); };
-  ballot_count(hw_grid(), cA, T, pred, degree, a.P, a.P.chunk, w.bits, w.wavecnt, w.wgc, lds.cnt);
-}
-
-// Level scan, pass 2: sorted binned frontier into parity `qp`, counts into
-// slot `slot`; returns the frontier size (vertices + large items, identical
-// in all workgroups).
-SX_DEV unsigned kscan_pass2(const KArgs &a, int qp, int slot, int scan_no, LdsK &lds) {
-  const Work &w = a.w;
-  Ctrl *C = w.ctrl;
-  const int cA = (int)load_relaxed(&C->aux.v[scan_no % 3]);
-  const int *A = w.alive[scan_no & 1];
-  const DevGraph &g = a.g;
-  Tiling T(cA, gridDim.x * kWaves);
   auto degree = [&](int v) { return total_degree(g, v); };
-  auto vof = [&](int i) { return A[i]; };
-  WgCount tot;
-  ballot_write(hw_grid(), cA, T, degree, vof, a.P.chunk, w.bits, w.wavecnt, w.wgc, w.q[qp][0], w.q[qp][1],
-               w.ql[qp], tot, lds.cnt, lds.red);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    Counters *q = &C->q[slot];
-    store_relaxed(&q->cnt[0], tot.cnt[0]);
-    store_relaxed(&q->cnt[1], tot.cnt[1]);
-    store_relaxed(&q->cnt[2], tot.cnt[2]);
-    store_relaxed(&q->nf, tot.cnt[0] + tot.cnt[1] + tot.cnt[2]);
-    store_relaxed(&q->overflow, 0u);
-    atomic_add_u32(&C->stats.v[4], 1u);
+  auto vof = [&](long long i) { return A[i]; };
+  ballot_fill_range(lo, hi, bid, probe, degree, vof, a.P, a.P.chunk, w.bits, regions(w, fp, G),
+                    w.rec + (size_t)SLOT_SCAN * kMaxGrid, lds.ball);
+  mind = wave_min_u(mind);
+  if (lane_id() == 0) lds.wmin[wave_in_wg()] = mind;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kWaves; ++i) mind = lds.wmin[i] < mind ? lds.wmin[i] : mind;
+    w.alive_cnt[(size_t)((s + 1) & 1) * kMaxGrid + bid] = lds.surv;
+    w.alive_min[(size_t)((s + 1) & 1) * kMaxGrid + bid] = mind;
+    if (bid == 0) atomic_add_u32(&w.ctrl->stats.v[4], 1u);
   }
-  return tot.cnt[0] + tot.cnt[1] + tot.cnt[2];
 }
 
-// Peel step: delete the frontier (slot `slot`, parity `qp`), decrement the
-// neighbours, online filter into slot (slot+1)%3, parity qp^1.
-SX_DEV void kpeel(const KArgs &a, int k, int qp, int slot, LdsK &lds) {
+// Survivors of the last scan (alive parity p): total count and minimum
+// degree over all workgroups (all threads get both).
+SX_DEV void alive_totals(const VGrid &vg, const Work &w, int p, LdsK &lds, unsigned long long &cnt,
+                         unsigned &mind) {
+  long long c = 0;
+  unsigned m = 0xFFFFFFFFu;
+  for (unsigned b = threadIdx.x; b < vg.nb; b += kBlock) {
+    c += w.alive_cnt[(size_t)p * kMaxGrid + b];
+    const unsigned x = w.alive_min[(size_t)p * kMaxGrid + b];
+    m = x < m ? x : m;
+  }
+  cnt = (unsigned long long)wg_sum_ll<kBlock>(c, lds.red);
+  m = wave_min_u(m);
+  if (lane_id() == 0) lds.wmin[wave_in_wg()] = m;
+  __syncthreads();
+  mind = 0xFFFFFFFFu;
+  for (int i = 0; i < kWaves; ++i) mind = lds.wmin[i] < mind ? lds.wmin[i] : mind;
+  __syncthreads();
+}
+
+SX_DEV Totals kview(const VGrid &vg, const KArgs &a, int slot, int parity, LdsK &lds, ViewRef &ref) {
+  ref.V = &lds.view;
+  ref.R = regions(a.w, parity, vg.nb);
+  ref.G = vg.nb;
+  return view_build(a.w.rec + (size_t)slot * kMaxGrid, vg.nb, ref.R, lds.view, lds.red);
+}
+
+// Peel step j: delete the frontier (view `cur`), decrement the neighbours,
+// online filter into slot (j + 1) % 3, parity (j + 1) & 1.
+SX_DEV void kpeel(const VGrid &vg, const KArgs &a, int k, int j, const ViewRef &cur, const Totals &T,
+                  LdsK &lds) {
   const Work &w = a.w;
-  Ctrl *C = w.ctrl;
-  Counters *cur = &C->q[slot], *nxt = &C->q[(slot + 1) % 3];
-  // counts are clamped to the list capacities: reads never leave the lists
-  const unsigned cs = min(load_relaxed(&cur->cnt[0]), w.qcap_small),
-                 cm = min(load_relaxed(&cur->cnt[1]), w.qcap_med),
-                 cl = min(load_relaxed(&cur->cnt[2]), w.qcap_large);
   const DevGraph &g = a.g;
+  const unsigned cs = T.cnt[BIN_SMALL], cm = T.cnt[BIN_MED], cl = T.cnt[BIN_LARGE];
   // mark the frontier deleted with core number k
   {
-    const unsigned tid = blockIdx.x * kBlock + threadIdx.x, nt = gridDim.x * kBlock;
+    const unsigned tid = vg.bid * kBlock + threadIdx.x, nt = vg.nb * kBlock;
     const unsigned un = (unsigned)g.n;
     for (unsigned i = tid; i < cs; i += nt) {
-      const int v = w.q[qp][0][i];
+      const int v = cur.small(i);
       if ((unsigned)v < un) a.core[v] = k;
     }
     for (unsigned i = tid; i < cm; i += nt) {
-      const int v = w.q[qp][1][i];
+      const int v = cur.med(i);
       if ((unsigned)v < un) a.core[v] = k;
     }
     for (unsigned i = tid; i < cl; i += nt) {
-      const unsigned long long it = w.ql[qp][i];
+      const unsigned long long it = cur.large(i);
       const unsigned v = (unsigned)(it & 0xffffffffu);
       if ((it >> 32) == 0 && v < un) a.core[v] = k;
     }
   }
-  Lists NL;
-  NL.s = w.q[qp ^ 1][0];
-  NL.m = w.q[qp ^ 1][1];
-  NL.l = w.ql[qp ^ 1];
-  NL.c = nxt;
-  NL.cap_s = a.P.online_cap < w.qcap_small ? a.P.online_cap : w.qcap_small;
-  NL.cap_m = a.P.online_cap < w.qcap_med ? a.P.online_cap : w.qcap_med;
-  NL.cap_l = a.P.online_cap < w.qcap_large ? a.P.online_cap : w.qcap_large;
+  const Regions NR = regions(w, (j + 1) & 1, vg.nb);
+  bins_begin(lds.bins, NR, a.P.online_cap);
   WaveStats st;
   long long edges = 0;
   int *deg = w.deg;
@@ -175,166 +170,176 @@ SX_DEV void kpeel(const KArgs &a, int k, int qp, int slot, LdsK &lds) {
         if (old == k + 1) { act = true; du = total_degree(g, u); }
       }
     }
-    online_append(act, u, du, NL, a.P, a.P.chunk, st);
+    bins_append(act, u, du, NR, vg.bid, a.P, a.P.chunk, lds.bins, st);
   };
-  const unsigned gw = blockIdx.x * kWaves + wave_in_wg();
-  const unsigned nw = gridDim.x * kWaves;
+  const unsigned gw = vg.bid * kWaves + wave_in_wg();
+  const unsigned nw = vg.nb * kWaves;
   for (int pass = 0; pass < (g.directed ? 2 : 1); ++pass) {
     const int *off = pass ? g.in_off : g.off;
     const int *idx = pass ? g.in_idx : g.idx;
-    visit_large(hw_grid(), g.n, w.ql[qp], cl, off, idx, a.P.chunk, op);
-    visit_med(g.n, w.q[qp][1], cm, off, idx, op, gw, nw);
-    visit_small(g.n, w.q[qp][0], cs, off, idx, op, gw, nw, lds.small[wave_in_wg()]);
+    visit_large(vg, g.n, [&](unsigned i) { return cur.large(i); }, cl, off, idx, a.P.chunk, op);
+    visit_med(g.n, [&](unsigned i) { return cur.med(i); }, cm, off, idx, op, gw, nw);
+    visit_small(g.n, [&](unsigned i) { return cur.small(i); }, cs, off, idx, op, gw, nw,
+                lds.small[wave_in_wg()]);
   }
-  flush_stats(st, nxt);
-  const long long e = wave_sum_ll(edges);
-  if (lane_id() == 0 && e) atomic_add_u64((unsigned long long *)&C->stats.v[0], (unsigned long long)e);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    atomic_add_u64((unsigned long long *)&C->stats.v[2], (unsigned long long)(cs + cm) + cl);
-    Counters *old = &C->q[(slot + 2) % 3];
-    for (int b = 0; b < NBINS; ++b) store_relaxed(&old->cnt[b], 0u);
-    store_relaxed(&old->nf, 0u);
-    store_relaxed(&old->mf, 0ull);
-    store_relaxed(&old->overflow, 0u);
-  }
+  bins_end(lds.bins, st, w.rec + (size_t)((j + 1) % 3) * kMaxGrid, vg.bid);
+  add_stats(w.ctrl, vg.bid, edges, vg.bid == 0 ? (unsigned long long)cs + cm + cl : 0ull, lds.red);
+}
+
+// The run state of a decomposition: level k, scans done s, peel steps done
+// j, and whether the lists of peel j come from a scan.
+struct KState {
+  int k, s, j;
+  bool from_scan;
+};
+
+// What to do after a scan: 1 peel, 0 scan again at a higher level (k
+// updated), -1 done.
+SX_DEV int after_scan(const VGrid &vg, const KArgs &a, KState &q, const Totals &T, LdsK &lds) {
+  if (T.nf > 0) return 1;
+  unsigned long long surv;
+  unsigned mind;
+  alive_totals(vg, a.w, q.s & 1, lds, surv, mind);
+  if (surv == 0) return -1;
+  // empty level: jump to the smallest surviving degree
+  q.k = (int)mind > q.k + 1 ? (int)mind : q.k + 1;
+  return 0;
 }
 
 // Persistent kernel: the whole decomposition in one launch.
+// Ctrl::aux: [10] k [11] scans [12] peel steps [13] lists of the next peel
+// come from a scan [14] next step kind (0 scan, 1 peel)
+enum { AUX_K = 10, AUX_SCAN = 11, AUX_STEP = 12, AUX_FROM = 13, AUX_KIND = 14 };
+
 __global__ void __launch_bounds__(kBlock) k_kcore_fused(KArgs a) {
   __shared__ LdsK lds;
   Ctrl *C = a.w.ctrl;
+  const VGrid vg = hw_grid();
   GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]));
-  int k = (int)load_relaxed(&C->aux.v[AUX_K]);
-  int scan_no = (int)load_relaxed(&C->aux.v[AUX_SCAN]);
+  KState q;
+  q.k = (int)load_relaxed(&C->aux.v[AUX_K]);
+  q.s = (int)load_relaxed(&C->aux.v[AUX_SCAN]);
+  q.j = (int)load_relaxed(&C->aux.v[AUX_STEP]);
+  q.from_scan = load_relaxed(&C->aux.v[AUX_FROM]) != 0;
   int kind = (int)load_relaxed(&C->aux.v[AUX_KIND]);
-  int step = (int)load_relaxed(&C->aux.v[AUX_STEP]);
   auto save = [&](int reason) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (vg.bid == 0 && threadIdx.x == 0) {
       store_relaxed(&C->state.v[0], (unsigned)reason);
-      store_relaxed(&C->aux.v[AUX_K], (unsigned)k);
-      store_relaxed(&C->aux.v[AUX_SCAN], (unsigned)scan_no);
+      store_relaxed(&C->aux.v[AUX_K], (unsigned)q.k);
+      store_relaxed(&C->aux.v[AUX_SCAN], (unsigned)q.s);
+      store_relaxed(&C->aux.v[AUX_STEP], (unsigned)q.j);
+      store_relaxed(&C->aux.v[AUX_FROM], q.from_scan ? 1u : 0u);
       store_relaxed(&C->aux.v[AUX_KIND], (unsigned)kind);
-      store_relaxed(&C->aux.v[AUX_STEP], (unsigned)step);
     }
   };
   if (load_relaxed(&C->state.v[0]) != EXIT_NONE || bar.failed()) return;
-  // every step removes at least one vertex or advances k; bound the loop
+  // every step deletes at least one vertex or raises k: bound the loop
   const long long limit = 4ll * a.g.n + 64;
+  ViewRef ref;
   for (long long guard = 0;; ++guard) {
     if (guard > limit) { save(EXIT_LIMIT); return; }
-    const int slot = (step + 1) % 3, qp = (step + 1) & 1;
     if (kind == 0) {
-      // scan: frontier of the level into (slot, qp), survivors into the
-      // other alive list
-      kscan_pass1(a, k, scan_no, lds);
+      kscan(vg, a, q.k, q.s, q.j & 1, lds);
       if (!bar.sync()) { save(EXIT_ERROR); return; }
-      const unsigned nfr = kscan_pass2(a, qp, slot, scan_no, lds);
-      if (!bar.sync()) { save(EXIT_ERROR); return; }
-      const unsigned survivors = load_relaxed(&C->aux.v[(scan_no + 1) % 3]);
-      const unsigned mind = load_relaxed(&C->aux.v[3 + scan_no % 3]);
-      ++scan_no;
-      if (nfr == 0) {
-        if (survivors == 0) { save(EXIT_DONE); return; }
-        // empty level: jump to the smallest surviving degree
-        k = (int)mind > k + 1 ? (int)mind : k + 1;
-        continue;
+      ++q.s;
+      const Totals T = kview(vg, a, SLOT_SCAN, q.j & 1, lds, ref);
+      if (T.ovf) {
+        if (threadIdx.x == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
+        save(EXIT_ERROR);
+        return;
       }
+      const int r = after_scan(vg, a, q, T, lds);
+      if (r < 0) { save(EXIT_DONE); return; }
+      if (r == 0) continue;
       kind = 1;
-      ++step;
+      q.from_scan = true;
     } else {
-      // peel the frontier of step-1's output
-      const int cslot = step % 3, cqp = step & 1;
-      kpeel(a, k, cqp, cslot, lds);
+      const Totals T = kview(vg, a, q.from_scan ? SLOT_SCAN : q.j % 3, q.j & 1, lds, ref);
+      kpeel(vg, a, q.k, q.j, ref, T, lds);
       if (!bar.sync()) { save(EXIT_ERROR); return; }
-      if (blockIdx.x == 0 && threadIdx.x == 0) atomic_add_u32(&C->stats.v[6], 1u);
-      Counters *nx = &C->q[(cslot + 1) % 3];
-      const unsigned nf = load_relaxed(&nx->nf);
-      const unsigned ovf = load_relaxed(&nx->overflow);
-      if (nf == 0) { ++k; kind = 0; continue; }
-      if (ovf || a.P.filter == 2) { kind = 0; continue; }   // rebuild by a scan at the same k
-      ++step;
+      if (vg.bid == 0 && threadIdx.x == 0) atomic_add_u32(&C->stats.v[6], 1u);
+      ++q.j;
+      const Totals N = kview(vg, a, q.j % 3, q.j & 1, lds, ref);
+      q.from_scan = false;
+      if (N.nf == 0) { ++q.k; kind = 0; continue; }
+      if (N.ovf || a.P.filter == 2) { kind = 0; continue; }   // rebuild by a scan at the same k
     }
-    (void)slot;
   }
 }
 
-// Sequenced form of the same loop: one launch per phase (scan pass 1, scan
-// pass 2, peel), the decision taken at the start of the launch after a
-// scan or a peel; launch L reads Ctrl::seq[L & 1] and writes seq[(L+1) & 1]:
-// [0] phase [1] k [2] scan number [3] step [4] decision due (1 after a scan,
-// 2 after a peel).
-enum : unsigned { KP_SCAN1 = 0, KP_SCAN2 = 1, KP_PEEL = 2, KP_DONE = 6, KP_ERROR = 7, KP_LIMIT = 8 };
+// Sequenced form of the same loop: one launch per phase (scan, peel), the
+// decision taken at the start of the launch after it; launch L reads
+// Ctrl::seq[L & 1] and writes seq[(L+1) & 1]: [0] phase [1] k [2] scans [3]
+// peel steps [4] decision due (1 after a scan, 2 after a peel) [5] the lists
+// of the next peel come from a scan.
+enum : unsigned { KP_SCAN = 0, KP_PEEL = 1, KP_DONE = 6, KP_ERROR = 7, KP_LIMIT = 8 };
 
 __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
   __shared__ LdsK lds;
   Ctrl *C = a.w.ctrl;
+  const VGrid vg = hw_grid();
   const Line &in = C->seq[L & 1];
   Line &out = C->seq[(L + 1) & 1];
   unsigned phase = load_relaxed(&in.v[0]);
-  int k = (int)load_relaxed(&in.v[1]);
-  int scan_no = (int)load_relaxed(&in.v[2]);
-  int step = (int)load_relaxed(&in.v[3]);
+  KState q;
+  q.k = (int)load_relaxed(&in.v[1]);
+  q.s = (int)load_relaxed(&in.v[2]);
+  q.j = (int)load_relaxed(&in.v[3]);
   unsigned due = load_relaxed(&in.v[4]);
-  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  q.from_scan = load_relaxed(&in.v[5]) != 0;
+  const bool lead = vg.bid == 0 && threadIdx.x == 0;
   auto save = [&](unsigned ph) {
     if (lead) {
       store_relaxed(&out.v[0], ph);
-      store_relaxed(&out.v[1], (unsigned)k);
-      store_relaxed(&out.v[2], (unsigned)scan_no);
-      store_relaxed(&out.v[3], (unsigned)step);
+      store_relaxed(&out.v[1], (unsigned)q.k);
+      store_relaxed(&out.v[2], (unsigned)q.s);
+      store_relaxed(&out.v[3], (unsigned)q.j);
       store_relaxed(&out.v[4], due);
+      store_relaxed(&out.v[5], q.from_scan ? 1u : 0u);
     }
   };
   if (phase >= KP_DONE) { save(phase); return; }
   if (load_relaxed(&C->error.v[0])) { due = 0; save(KP_ERROR); return; }
-  if (step > 4 * a.g.n + 64) { due = 0; save(KP_LIMIT); return; }
+  if ((long long)q.s + q.j > 4ll * a.g.n + 64) { due = 0; save(KP_LIMIT); return; }
+  ViewRef ref;
   if (due == 1) {
-    // after a scan (scan_no already advanced): frontier of the level or a jump
-    const int s_prev = scan_no - 1;
-    Counters *q = &C->q[(step + 1) % 3];
-    const unsigned nfr = load_relaxed(&q->nf);
-    const unsigned survivors = load_relaxed(&C->aux.v[(s_prev + 1) % 3]);
-    const unsigned mind = load_relaxed(&C->aux.v[3 + s_prev % 3]);
-    if (nfr == 0) {
-      if (survivors == 0) { due = 0; save(KP_DONE); return; }
-      k = (int)mind > k + 1 ? (int)mind : k + 1;
-      phase = KP_SCAN1;
-    } else {
-      phase = KP_PEEL;
-      ++step;
+    const Totals T = kview(vg, a, SLOT_SCAN, q.j & 1, lds, ref);
+    if (T.ovf) {
+      if (lead) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
+      due = 0;
+      save(KP_ERROR);
+      return;
     }
+    const int r = after_scan(vg, a, q, T, lds);
     due = 0;
+    if (r < 0) { save(KP_DONE); return; }
+    if (r == 0) phase = KP_SCAN;
+    else { phase = KP_PEEL; q.from_scan = true; }
   } else if (due == 2) {
-    Counters *nx = &C->q[(step % 3 + 1) % 3];
-    const unsigned nf = load_relaxed(&nx->nf);
-    const unsigned ovf = load_relaxed(&nx->overflow);
-    if (nf == 0) { ++k; phase = KP_SCAN1; }
-    else if (ovf || a.P.filter == 2) phase = KP_SCAN1;
-    else { phase = KP_PEEL; ++step; }
+    const Totals N = kview(vg, a, q.j % 3, q.j & 1, lds, ref);
+    q.from_scan = false;
     due = 0;
+    if (N.nf == 0) { ++q.k; phase = KP_SCAN; }
+    else if (N.ovf || a.P.filter == 2) phase = KP_SCAN;
+    else phase = KP_PEEL;
   }
-  switch (phase) {
-    case KP_SCAN1:
-      kscan_pass1(a, k, scan_no, lds);
-      save(KP_SCAN2);
-      return;
-    case KP_SCAN2:
-      kscan_pass2(a, (step + 1) & 1, (step + 1) % 3, scan_no, lds);
-      ++scan_no;
-      due = 1;
-      save(KP_SCAN2);
-      return;
-    case KP_PEEL:
-      kpeel(a, k, step & 1, step % 3, lds);
-      if (lead) atomic_add_u32(&C->stats.v[6], 1u);
-      due = 2;
-      save(KP_PEEL);
-      return;
+  if (phase == KP_SCAN) {
+    kscan(vg, a, q.k, q.s, q.j & 1, lds);
+    ++q.s;
+    due = 1;
+    save(KP_SCAN);
+  } else {
+    const Totals T = kview(vg, a, q.from_scan ? SLOT_SCAN : q.j % 3, q.j & 1, lds, ref);
+    kpeel(vg, a, q.k, q.j, ref, T, lds);
+    if (lead) atomic_add_u32(&C->stats.v[6], 1u);
+    ++q.j;
+    due = 2;
+    save(KP_PEEL);
   }
 }
 
 __global__ void k_kcore_seq_start(Ctrl *C) {
-  if (threadIdx.x < 32) C->seq[0].v[threadIdx.x] = 0u;   // scan 1 of level 0
+  if (threadIdx.x < 32) C->seq[0].v[threadIdx.x] = 0u;   // first scan of level 0
 }
 
 hipError_t kcore_seq_launch(const KArgs &a, unsigned L, int grid, hipStream_t s, bool start) {
@@ -345,37 +350,41 @@ hipError_t kcore_seq_launch(const KArgs &a, unsigned L, int grid, hipStream_t s,
 
 const void *kcore_seq_kernel() { return (const void *)k_kcore_seq; }
 
-__global__ void k_kcore_init(KArgs a) {
+// Set-up for a run on G workgroups: core -1, current degrees, alive list 0 =
+// every vertex, workgroup b holding a contiguous range of per = (n / G
+// rounded up to 64) vertices.
+__global__ void k_kcore_init(KArgs a, unsigned G) {
   const int n = a.g.n;
+  const unsigned cap = alive_cap(a.w, G);
+  const long long per = (((long long)n + G - 1) / G + 63) / 64 * 64;
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (long long)gridDim.x * blockDim.x) {
     a.core[v] = -1;
     a.w.deg[v] = total_degree(a.g, (int)v);
-    a.w.alive[0][v] = (int)v;
+    const long long b = v / per;
+    a.w.alive[0][b * cap + (v - b * per)] = (int)v;
   }
-  if (blockIdx.x == 0) reset_barrier(a.w.ctrl);
+  for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < G;
+       b += (long long)gridDim.x * blockDim.x) {
+    const long long lo = b * per;
+    const long long c = lo >= n ? 0 : (n - lo < per ? n - lo : per);
+    a.w.alive_cnt[b] = (unsigned)c;
+  }
+  Ctrl *C = a.w.ctrl;
+  if (blockIdx.x == 0) reset_barrier(C);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    Ctrl *C = a.w.ctrl;
-    for (int s = 0; s < 3; ++s) {
-      for (int b = 0; b < NBINS; ++b) C->q[s].cnt[b] = 0;
-      C->q[s].nf = 0;
-      C->q[s].mf = 0;
-      C->q[s].overflow = 0;
-    }
     for (int i = 0; i < 32; ++i) { C->state.v[i] = 0; C->stats.v[i] = 0; C->aux.v[i] = 0; }
     C->error.v[0] = 0;
-    C->aux.v[0] = (unsigned)n;       // alive list 0 = all vertices
-    C->aux.v[3] = 0xFFFFFFFFu;
-    C->aux.v[4] = 0xFFFFFFFFu;
-    C->aux.v[5] = 0xFFFFFFFFu;
   }
+  if (blockIdx.x == 1)
+    for (int i = threadIdx.x; i < kStatLines * 4; i += blockDim.x) C->statw[i / 4].v[i % 4] = 0u;
 }
 
 hipError_t kcore_launch(const KArgs &a, int grid, hipStream_t s, bool init) {
   if (init) {
     int g = (a.g.n + kBlock - 1) / kBlock;
-    g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
-    hipLaunchKernelGGL(k_kcore_init, dim3(g), dim3(kBlock), 0, s, a);
+    g = g < 2 ? 2 : (g > 4096 ? 4096 : g);
+    hipLaunchKernelGGL(k_kcore_init, dim3(g), dim3(kBlock), 0, s, a, (unsigned)grid);
   } else {
     hipLaunchKernelGGL(k_kcore_fused, dim3(grid), dim3(kBlock), 0, s, a);
   }

@@ -5,19 +5,18 @@
 
 namespace sx {
 
-enum TravKernel {
-  TK_PUSH_FUSED, TK_PULL_FUSED, TK_PUSH_STEP, TK_BALLOT1, TK_BALLOT2,
-  TK_PULL_SCAN, TK_PULL_LISTS, TK_PULL_STEP, TK_COUNT
-};
+// traversal kernels; trav_launch's `it` is the iteration (TK_SEQ: the launch
+// number) and `arg` the direction (TK_FUSED: 1 = pull) or whether the push
+// lists come from a ballot scan (TK_PUSH_STEP)
+enum TravKernel { TK_FUSED, TK_PUSH_STEP, TK_BALLOT, TK_PULL_SCAN, TK_PULL_STEP, TK_SEQ, TK_COUNT };
 
 const void *trav_kernel(int kind, int sssp);
-hipError_t trav_launch(int kind, int sssp, const TravArgs &a, int it, int grid, hipStream_t s);
-hipError_t trav_init(const TravArgs &a, int sssp, unsigned long long mu0, hipStream_t s);
-hipError_t reset_slot(Ctrl *c, int slot, hipStream_t s);
+hipError_t trav_launch(int kind, int sssp, const TravArgs &a, int it, int arg, int grid,
+                       hipStream_t s);
+hipError_t trav_init(const TravArgs &a, int sssp, unsigned long long mu0, int run_grid,
+                     hipStream_t s);
 hipError_t batch_launch(const BatchArgs &b, int grid, hipStream_t s);
 hipError_t seq_start(Ctrl *c, bool pull_first, hipStream_t s);
-hipError_t seq_launch(int sssp, const TravArgs &a, unsigned L, int grid, hipStream_t s);
-const void *seq_kernel(int sssp);
 // phases of the sequenced mode (Ctrl::seq[..].v[0])
 enum : unsigned { SEQ_DONE = 6, SEQ_ERROR = 7, SEQ_LIMIT = 8 };
 const void *batch_kernel();

@@ -64,7 +64,8 @@ SX_DEV CSum wg_merge(CSum a, float *lds /* 2*kWaves */) {
 }
 
 struct LdsPr {
-  unsigned cnt[kWaves * 8];
+  LdsView view;
+  LdsBallot ball;
   long long red[kWaves];
   float f[2 * kWaves];
 };
@@ -77,25 +78,16 @@ SX_DEV float dangling_total(const float *part, int nparts, float *lds) {
   return a.s + a.c;
 }
 
-// Binned vertex lists (by in-degree), built once.
-SX_DEV void pr_lists_pass1(const PrArgs &a, LdsPr &lds) {
-  Tiling T(a.g.n, gridDim.x * kWaves);
+// Binned vertex lists (by in-degree, one item per vertex), built once by the
+// ballot filter into slot SLOT_SCAN, parity 0.
+SX_DEV void pr_lists(const PrArgs &a, LdsPr &lds) {
   const int *io = a.g.in_off;
-  auto pred = [&](int v) { (void)v; return true; };
-  auto deg = [&](int v) { return io[v + 1] - io[v]; };
-  ballot_count(hw_grid(), a.g.n, T, pred, deg, a.P, 0x7fffffff, a.w.bits, a.w.wavecnt, a.w.wgc, lds.cnt);
-}
-SX_DEV void pr_lists_pass2(const PrArgs &a, LdsPr &lds, unsigned tot_out[3]) {
-  Tiling T(a.g.n, gridDim.x * kWaves);
-  const int *io = a.g.in_off;
+  auto pred = [](int v) { (void)v; return true; };
   auto deg = [&](int v) { return io[v + 1] - io[v]; };
   auto ident = [](int i) { return i; };
-  WgCount tot;
-  ballot_write(hw_grid(), a.g.n, T, deg, ident, 0x7fffffff, a.w.bits, a.w.wavecnt, a.w.wgc, a.w.q[0][0],
-               a.w.q[0][1], a.w.ql[0], tot, lds.cnt, lds.red);
-  tot_out[0] = min(tot.cnt[0], a.w.qcap_small);
-  tot_out[1] = min(tot.cnt[1], a.w.qcap_med);
-  tot_out[2] = min(tot.cnt[2], a.w.qcap_large);
+  const VGrid vg = hw_grid();
+  ballot_fill(vg, a.g.n, pred, deg, ident, a.P, 0x7fffffff, a.w.bits, regions(a.w, 0, vg.nb),
+              a.w.rec + (size_t)SLOT_SCAN * kMaxGrid, lds.ball);
 }
 
 // One vertex's new value from its in-arc sum; returns the dangling share.
@@ -109,7 +101,7 @@ SX_DEV void pr_finish_vertex(const PrArgs &a, int v, CSum s, float D, bool last,
   if (od == 0) cadd(dang, r);
 }
 
-SX_DEV void pr_iteration(const PrArgs &a, int t, const unsigned cnt[3], LdsPr &lds) {
+SX_DEV void pr_iteration(const PrArgs &a, int t, const ViewRef &L, const Totals &T, LdsPr &lds) {
   const Work &w = a.w;
   const float *src = w.contrib[t & 1];
   float *dst = w.contrib[(t + 1) & 1];
@@ -120,8 +112,8 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const unsigned cnt[3], LdsPr &l
   CSum dang{0.f, 0.f};
   long long edges = 0;
   // one workgroup per large vertex
-  for (unsigned i = blockIdx.x; i < cnt[2]; i += gridDim.x) {
-    const int v = (int)(w.ql[0][i] & 0xffffffffu);
+  for (unsigned i = blockIdx.x; i < T.cnt[BIN_LARGE]; i += gridDim.x) {
+    const int v = (int)(L.large(i) & 0xffffffffu);
     if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
@@ -132,8 +124,8 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const unsigned cnt[3], LdsPr &l
   const unsigned gw = blockIdx.x * kWaves + wave_in_wg();
   const unsigned nw = gridDim.x * kWaves;
   // one wavefront per medium vertex
-  for (unsigned i = gw; i < cnt[1]; i += nw) {
-    const int v = w.q[0][1][i];
+  for (unsigned i = gw; i < T.cnt[BIN_MED]; i += nw) {
+    const int v = L.med(i);
     if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
@@ -142,8 +134,8 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const unsigned cnt[3], LdsPr &l
     if (lane == 0) pr_finish_vertex(a, v, s, D, last, dst, dang);
   }
   // one lane per small vertex
-  for (unsigned i = gw * 64u + lane; i < cnt[0] + 0u; i += nw * 64u) {
-    const int v = w.q[0][0][i];
+  for (unsigned i = gw * 64u + lane; i < T.cnt[BIN_SMALL]; i += nw * 64u) {
+    const int v = L.small(i);
     if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
@@ -157,27 +149,35 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const unsigned cnt[3], LdsPr &l
     part[2 * blockIdx.x] = dang.s;
     part[2 * blockIdx.x + 1] = dang.c;
   }
-  const long long e = wave_sum_ll(edges);
-  if (lane == 0 && e) atomic_add_u64((unsigned long long *)&w.ctrl->stats.v[0], (unsigned long long)e);
+  add_stats(w.ctrl, blockIdx.x, edges, 0ull, lds.red);
 }
 
 __global__ void __launch_bounds__(kBlock) k_pr_fused(PrArgs a) {
   __shared__ LdsPr lds;
   Ctrl *C = a.w.ctrl;
+  const VGrid vg = hw_grid();
   GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]));
-  pr_lists_pass1(a, lds);
+  pr_lists(a, lds);
   if (!bar.sync()) return;
-  unsigned cnt[3];
-  pr_lists_pass2(a, lds, cnt);
-  if (!bar.sync()) return;
+  ViewRef L;
+  L.V = &lds.view;
+  L.R = regions(a.w, 0, vg.nb);
+  L.G = vg.nb;
+  const Totals T = view_build(a.w.rec + (size_t)SLOT_SCAN * kMaxGrid, vg.nb, L.R, lds.view, lds.red);
+  if (T.ovf) {
+    if (threadIdx.x == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
+    return;
+  }
   for (int t = 0; t < a.iters; ++t) {
-    pr_iteration(a, t, cnt, lds);
+    pr_iteration(a, t, L, T, lds);
     if (!bar.sync()) return;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (vg.bid == 0 && threadIdx.x == 0) {
     store_relaxed(&C->state.v[0], (unsigned)EXIT_DONE);
     store_relaxed(&C->stats.v[6], (unsigned)a.iters);
     store_relaxed(&C->stats.v[4], 1u);
+    atomic_add_u64((unsigned long long *)&C->statw[0].v[2],
+                   (unsigned long long)a.iters * ((unsigned long long)T.cnt[0] + T.cnt[1] + T.cnt[2]));
   }
 }
 
@@ -204,6 +204,8 @@ __global__ void __launch_bounds__(kBlock) k_pr_init(PrArgs a) {
     for (int i = 0; i < 32; ++i) { C->state.v[i] = 0; C->stats.v[i] = 0; }
     C->error.v[0] = 0;
   }
+  if (blockIdx.x == 1 || gridDim.x == 1)
+    for (int i = threadIdx.x; i < kStatLines * 4; i += blockDim.x) a.w.ctrl->statw[i / 4].v[i % 4] = 0u;
 }
 
 hipError_t pagerank_launch(const PrArgs &a, int grid, hipStream_t s) {

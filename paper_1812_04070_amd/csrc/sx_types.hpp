@@ -9,10 +9,13 @@ namespace sx {
 
 constexpr int kBlock = 512;              // threads per workgroup (8 wavefronts)
 constexpr int kWaves = kBlock / 64;
-constexpr int kMaxGrid = 2048;           // upper bound on persistent workgroups
+constexpr int kMaxGrid = 1024;           // upper bound on workgroups per grid
 constexpr unsigned kSpinLimit = 1u << 22; // watchdog: polls of ~128 cycles each
+constexpr int kStatLines = 64;           // statistics spread over 64 lines
 
-enum : unsigned { SX_ERR_NONE = 0, SX_ERR_DEADLOCK = 1, SX_ERR_OVERFLOW = 2 };
+// SX_ERR_CAPACITY: a list built by a ballot scan did not fit its regions
+// (the host sizes them so that this cannot happen)
+enum : unsigned { SX_ERR_NONE = 0, SX_ERR_DEADLOCK = 1, SX_ERR_OVERFLOW = 2, SX_ERR_CAPACITY = 3 };
 
 // kernel exit reasons written to Ctrl::state
 enum : int { EXIT_NONE = 0, EXIT_DONE = 1, EXIT_SWITCH = 2, EXIT_ERROR = 3, EXIT_LIMIT = 4 };
@@ -20,32 +23,37 @@ enum : int { EXIT_NONE = 0, EXIT_DONE = 1, EXIT_SWITCH = 2, EXIT_ERROR = 3, EXIT
 // worklist bins (Section 4 step I: small / medium / large lists)
 enum : int { BIN_SMALL = 0, BIN_MED = 1, BIN_LARGE = 2, NBINS = 3 };
 
+// record slots: 0..2 rotate with the iteration (the lists a compute phase
+// appends for the next iteration); 3 holds lists built by a ballot scan
+enum : int { NSLOTS = 4, SLOT_SCAN = 3 };
+
 struct alignas(128) Line {
   unsigned v[32];
 };
 
-// Per-iteration counters, triple buffered by iteration (it % 3): slot it is
-// read during iteration it, slot it+1 is appended to, slot it+2 is reset.
-struct alignas(128) Counters {
-  unsigned cnt[NBINS];          // entries per bin (large: chunk items)
-  unsigned nf;                  // vertices in the frontier
-  unsigned long long mf;        // sum of their degrees
-  unsigned overflow;            // online filter overflowed
-  unsigned pad[25];
+// What one workgroup appended to its bins in one phase (its "thread bins" in
+// the paper's terms, Section 3.3): items per bin, vertices and their arcs,
+// and whether a bin overflowed its capacity.
+struct alignas(64) WgRec {
+  unsigned cnt[NBINS];
+  unsigned nf;
+  unsigned long long mf;
+  unsigned ovf;
+  unsigned pad[9];
 };
 
 // Control block: one per graph workspace, in device memory.
 struct Ctrl {
   Line bar_gen;                 // barrier generation
   Line error;                   // SX_ERR_*
-  Line state;                   // [0] exit reason [1] iteration [2] level/k
-                                // [3] direction [4] launches-in-kernel
-  Line stats;                   // u64 [0] edges, [1] expansions; u32 [4]
-                                // ballot iters, [5] pull iters, [6] iterations
-  Counters q[3];
-  Line aux;                     // algorithm scratch (k-core: min alive degree)
+  Line state;                   // run state of the fused kernels
+  Line stats;                   // u32 [4] ballot scans, [5] pull iterations,
+                                // [6] iterations
+  Line aux;                     // algorithm scratch
   Line seq[2];                  // sequenced mode: run state handed from launch
                                 // L (reads seq[L&1]) to launch L+1
+  Line statw[kStatLines];       // u64 [0] arcs inspected, [2] worklist entries
+                                // processed; workgroup b adds into line b % 64
   Line flags[kMaxGrid];         // barrier arrival words, one line per workgroup
 };
 
@@ -62,27 +70,24 @@ struct DevGraph {
   int directed;
 };
 
-// Per-workgroup ballot-filter totals, written in pass 1, read in pass 2.
-struct WgCount {
-  unsigned cnt[NBINS];
-  unsigned nf;
-  unsigned long long mf;
-};
-
+// Worklists are kept in per-workgroup regions: workgroup b owns entries
+// [b * cap, (b+1) * cap) of each bin array, with cap = total / (workgroups).
 struct Work {
-  int *q[2][2];                 // [parity][small, med] vertex queues
-  unsigned long long *ql[2];    // [parity] large items: chunk << 32 | vertex
-  unsigned long long *bits[NBINS]; // ballot words per bin, n/64 each
-  unsigned long long *fbits;    // frontier bitmap (pull)
-  unsigned *wavecnt;            // per-wavefront ballot counts [kMaxGrid*kWaves][NBINS]
-  WgCount *wgc;                 // per-workgroup ballot totals [kMaxGrid]
-  int *stamp;                   // per-vertex int: SSSP/k-core iteration stamps
-  int *deg;                     // k-core current degree
-  float *contrib[2];            // PageRank contributions (double buffered)
-  float *dang;                  // PageRank dangling partials [2][kMaxGrid][2]
-  int *alive[2];                // k-core alive lists
+  int *reg_s[2], *reg_m[2];        // [parity] small / medium bin regions
+  unsigned long long *reg_l[2];    // [parity] large items: chunk << 32 | vertex
+  unsigned tot_s, tot_m, tot_l;    // entries per bin array (all regions)
+  WgRec *rec;                      // [NSLOTS][kMaxGrid]
+  unsigned long long *bits[NBINS]; // ballot words, one per 64 scan positions
+  unsigned long long *fbits;       // frontier bitmap (pull)
+  int *stamp;                      // per-vertex int: SSSP iteration stamps
+  int *deg;                        // k-core current degree
+  int *alive[2];                   // k-core per-workgroup alive lists
+  unsigned tot_a;                  // entries per alive array
+  unsigned *alive_cnt;             // [2][kMaxGrid] alive list lengths
+  unsigned *alive_min;             // [2][kMaxGrid] minimum survivor degree
+  float *contrib[2];               // PageRank contributions (double buffered)
+  float *dang;                     // PageRank dangling partials [2][kMaxGrid][2]
   Ctrl *ctrl;
-  unsigned qcap_small, qcap_med, qcap_large;
 };
 
 // Uniform per-run parameters.
@@ -90,7 +95,8 @@ struct Params {
   int t1;                       // degree < t1 -> small bin (lane)
   int t2;                       // degree >= t2 -> large bin (workgroup chunks)
   int chunk;                    // arcs per large-bin item
-  unsigned online_cap;          // online filter capacity (entries, all bins)
+  unsigned online_cap;          // online filter: entries per workgroup and bin
+                                // before overflow (0: the whole region)
   int filter;                   // 0 JIT, 1 online, 2 ballot
   int direction;                // 0 auto, 1 push, 2 pull
   float alpha, beta;            // direction heuristic
