@@ -138,14 +138,20 @@ struct GridBarrier {
 
   SX_DEV bool failed() const { return load_relaxed(&c->error.v[0]) != 0u; }
 
-  // returns false when the watchdog fired (this or another workgroup)
+  // Returns false when the watchdog fired or an error was raised (by any
+  // workgroup).  The error word is read by one thread and shared through
+  // LDS: hundreds of workgroups x 8 wavefronts loading one address would
+  // queue on a single L2 channel.
   SX_DEV bool sync() {
+    __shared__ unsigned s_err;
     const unsigned target = gen + 1;
     if (nblk == 1) {
       // a single workgroup: the workgroup barrier orders its global memory
       __syncthreads();
+      if (threadIdx.x == 0) s_err = load_relaxed(&c->error.v[0]);
+      __syncthreads();
       gen = target;
-      return !failed();
+      return s_err == 0u;
     }
     __syncthreads();
     bool ok = true;
@@ -179,11 +185,21 @@ struct GridBarrier {
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
+    if (threadIdx.x == 0) s_err = load_relaxed(&c->error.v[0]) | (ok ? 0u : 1u);
     gen = target;
     __syncthreads();
-    return ok && !failed();
+    return ok && s_err == 0u;
   }
 };
+
+// Words of the control block that every workgroup reads at the start of a
+// launch: one wavefront loads the 128-byte line (and the error word) and
+// shares them through LDS, for the same reason as in GridBarrier::sync.
+SX_DEV void fetch_line(const Line &l, const Ctrl *c, unsigned *dst /* 33 words of LDS */) {
+  if (threadIdx.x < 32) dst[threadIdx.x] = load_relaxed(&l.v[threadIdx.x]);
+  else if (threadIdx.x == 32) dst[32] = load_relaxed(&c->error.v[0]);
+  __syncthreads();
+}
 
 // Start every run from barrier generation 0 (called by one workgroup of the
 // run's initialisation kernel, which completes before the persistent kernel

@@ -132,9 +132,17 @@ SX_DEV void bins_append(bool valid, int v, int deg, const Regions &R, unsigned b
   }
 }
 
+// Publish workgroup `bid`'s record in slot `rs` (one thread).
+SX_DEV void rec_write(RecSlot *rs, unsigned bid, const unsigned cnt[NBINS], unsigned nf,
+                      unsigned long long mf, bool ovf) {
+  for (int i = 0; i < NBINS; ++i) rs->cnt[i][bid] = cnt[i];
+  rs->nf[bid] = (nf & ~kRecOvf) | (ovf ? kRecOvf : 0u);
+  rs->mf[bid] = mf;
+}
+
 // End of a producing phase (all threads): publish this workgroup's record.
 // Counts past the limit mark overflow; entries beyond it were not written.
-SX_DEV void bins_end(LdsBins &b, WaveStats &st, WgRec *rec_slot, unsigned bid) {
+SX_DEV void bins_end(LdsBins &b, WaveStats &st, RecSlot *rs, unsigned bid) {
   const int nf = wave_sum_i((int)st.nf);
   const long long mf = wave_sum_ll((long long)st.mf);
   if (lane_id() == 0) {
@@ -145,20 +153,16 @@ SX_DEV void bins_end(LdsBins &b, WaveStats &st, WgRec *rec_slot, unsigned bid) {
   st.mf = 0;
   __syncthreads();
   if (threadIdx.x == 0) {
-    WgRec r;
     unsigned tnf = 0;
     unsigned long long tmf = 0;
     for (int w = 0; w < kWaves; ++w) { tnf += b.nf[w]; tmf += b.mf[w]; }
-    unsigned ovf = b.ovf;
+    bool ovf = b.ovf != 0;
+    unsigned c[NBINS];
     for (int i = 0; i < NBINS; ++i) {
-      r.cnt[i] = b.cnt[i] < b.lim[i] ? b.cnt[i] : b.lim[i];
-      if (b.cnt[i] > b.lim[i]) ovf = 1;
+      c[i] = b.cnt[i] < b.lim[i] ? b.cnt[i] : b.lim[i];
+      if (b.cnt[i] > b.lim[i]) ovf = true;
     }
-    r.nf = tnf;
-    r.mf = tmf;
-    r.ovf = ovf;
-    for (int i = 0; i < 9; ++i) r.pad[i] = 0;
-    rec_slot[bid] = r;
+    rec_write(rs, bid, c, tnf, tmf, ovf);
   }
   __syncthreads();
 }
@@ -167,6 +171,7 @@ SX_DEV void bins_end(LdsBins &b, WaveStats &st, WgRec *rec_slot, unsigned bid) {
 struct LdsView {
   unsigned pre[NBINS][kMaxGrid + 1];
   unsigned tmp[kWaves * 4];
+  long long wnf[kWaves], wmf[kWaves];
 };
 
 struct Totals {
@@ -177,55 +182,75 @@ struct Totals {
 };
 
 // Prefix of the records of one slot (all threads); the totals are identical
-// in every workgroup.
-SX_DEV Totals view_build(const WgRec *rec, unsigned G, const Regions &R, LdsView &V,
+// in every workgroup.  Thread t owns records 2t and 2t+1 and reads them with
+// one 8-byte load per field.
+SX_DEV uint2 rec_pair(const unsigned *a, unsigned w0, unsigned G) {
+  if (w0 + 1 < G) return *(const uint2 *)(a + w0);
+  return make_uint2(w0 < G ? a[w0] : 0u, 0u);
+}
+
+SX_DEV Totals view_build(const RecSlot *rs, unsigned G, const Regions &R, LdsView &V,
                          long long *red /* kWaves */) {
-  const unsigned t = threadIdx.x;  // owns records 2t and 2t+1
-  unsigned c[2][NBINS] = {{0, 0, 0}, {0, 0, 0}};
-  unsigned long long mf = 0;
-  unsigned nf = 0, ovf = 0;
+  (void)red;
+  const unsigned t = threadIdx.x;
+  const unsigned w0 = 2 * t;
   const unsigned caps[NBINS] = {R.cap_s, R.cap_m, R.cap_l};
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const unsigned w = 2 * t + k;
-    if (w < G) {
-      const WgRec r = rec[w];
-#pragma unroll
-      for (int b = 0; b < NBINS; ++b) {
-        c[k][b] = r.cnt[b] < caps[b] ? r.cnt[b] : caps[b];
-        ovf |= r.cnt[b] > caps[b] ? 1u : 0u;
-      }
-      nf += r.nf;
-      mf += r.mf;
-      ovf |= r.ovf;
-    }
-  }
-  unsigned tot[NBINS];
+  unsigned ovf = 0;
+  unsigned c0[NBINS], c1[NBINS];
+  int incl[NBINS];
 #pragma unroll
   for (int b = 0; b < NBINS; ++b) {
-    const int s = (int)(c[0][b] + c[1][b]);
-    const int incl = wave_incl_scan(s);
-    if (lane_id() == 63) V.tmp[wave_in_wg() * 4 + b] = (unsigned)incl;
-    __syncthreads();
-    unsigned base = 0, all = 0;
-    for (int w = 0; w < kWaves; ++w) {
-      const unsigned x = V.tmp[w * 4 + b];
-      if (w < wave_in_wg()) base += x;
-      all += x;
-    }
-    const unsigned ex = base + (unsigned)(incl - s);
-    if (2 * t < G) V.pre[b][2 * t] = ex;
-    if (2 * t + 1 < G) V.pre[b][2 * t + 1] = ex + c[0][b];
-    if (t == 0) V.pre[b][G] = all;
-    tot[b] = all;
-    __syncthreads();
+    const uint2 p = rec_pair(rs->cnt[b], w0, G);
+    c0[b] = p.x < caps[b] ? p.x : caps[b];
+    c1[b] = p.y < caps[b] ? p.y : caps[b];
+    ovf |= (p.x > caps[b] || p.y > caps[b]) ? 1u : 0u;
   }
-  Totals T;
+  const uint2 nfp = rec_pair(rs->nf, w0, G);
+  unsigned long long mf = 0;
+  if (w0 < G) mf += rs->mf[w0];
+  if (w0 + 1 < G) mf += rs->mf[w0 + 1];
+  ovf |= ((nfp.x | nfp.y) & kRecOvf) ? 1u : 0u;
+  // one exchange through LDS for the three bin scans and the totals
 #pragma unroll
-  for (int b = 0; b < NBINS; ++b) T.cnt[b] = tot[b];
-  T.nf = (unsigned)wg_sum_ll<kBlock>((long long)nf, red);
-  T.mf = (unsigned long long)wg_sum_ll<kBlock>((long long)mf, red);
-  T.ovf = wg_sum_ll<kBlock>((long long)ovf, red) ? 1u : 0u;
+  for (int b = 0; b < NBINS; ++b) incl[b] = wave_incl_scan((int)(c0[b] + c1[b]));
+  const long long nf = wave_sum_ll((long long)(nfp.x & ~kRecOvf) + (long long)(nfp.y & ~kRecOvf));
+  const long long mfw = wave_sum_ll((long long)mf);
+  const unsigned ovw = ballot(ovf != 0) ? 1u : 0u;
+  const int wv = wave_in_wg();
+  if (lane_id() == 63) {
+#pragma unroll
+    for (int b = 0; b < NBINS; ++b) V.tmp[wv * 4 + b] = (unsigned)incl[b];
+    V.tmp[wv * 4 + 3] = ovw;
+    V.wnf[wv] = nf;
+    V.wmf[wv] = mfw;
+  }
+  __syncthreads();
+  Totals T;
+  T.nf = 0;
+  T.mf = 0;
+  T.ovf = 0;
+#pragma unroll
+  for (int b = 0; b < NBINS; ++b) T.cnt[b] = 0;
+  unsigned base[NBINS] = {0, 0, 0};
+  for (int w = 0; w < kWaves; ++w) {
+#pragma unroll
+    for (int b = 0; b < NBINS; ++b) {
+      const unsigned x = V.tmp[w * 4 + b];
+      if (w < wv) base[b] += x;
+      T.cnt[b] += x;
+    }
+    T.ovf |= V.tmp[w * 4 + 3];
+    T.nf += (unsigned)V.wnf[w];
+    T.mf += (unsigned long long)V.wmf[w];
+  }
+#pragma unroll
+  for (int b = 0; b < NBINS; ++b) {
+    const unsigned ex = base[b] + (unsigned)(incl[b] - (int)(c0[b] + c1[b]));
+    if (w0 < G) V.pre[b][w0] = ex;
+    if (w0 + 1 < G) V.pre[b][w0 + 1] = ex + c0[b];
+    if (t == 0) V.pre[b][G] = T.cnt[b];
+  }
+  __syncthreads();
   return T;
 }
 
@@ -280,7 +305,7 @@ template <class Probe, class Deg, class VertexOf>
 SX_DEV void ballot_fill_range(long long lo, long long hi, unsigned bid, Probe probe, Deg degree,
                               VertexOf vertex_of, const Params &P, int chunk,
                               unsigned long long *const bits[NBINS], const Regions &R,
-                              WgRec *rec_slot, LdsBallot &lb) {
+                              RecSlot *rec_slot, LdsBallot &lb) {
   const long long len = hi > lo ? hi - lo : 0;
   const long long per_wave = ((len + kWaves - 1) / kWaves + 63) / 64 * 64;
   const int lane = lane_id(), wv = wave_in_wg();
@@ -356,19 +381,14 @@ SX_DEV void ballot_fill_range(long long lo, long long hi, unsigned bid, Probe pr
   if (lane == 0) lb.wovf[wv] = any_ovf ? 1u : 0u;
   __syncthreads();
   if (threadIdx.x == 0) {
-    WgRec r;
     unsigned long long tmf = 0;
-    unsigned tnf = 0, o = 0;
+    unsigned tnf = 0, o = 0, c[NBINS];
     for (int w = 0; w < kWaves; ++w) { tmf += lb.wmf[w]; tnf += lb.wnf[w]; o |= lb.wovf[w]; }
     for (int bin = 0; bin < NBINS; ++bin) {
-      r.cnt[bin] = tot[bin] < caps[bin] ? tot[bin] : caps[bin];
+      c[bin] = tot[bin] < caps[bin] ? tot[bin] : caps[bin];
       if (tot[bin] > caps[bin]) o = 1;
     }
-    r.nf = tnf;
-    r.mf = tmf;
-    r.ovf = o;
-    for (int i = 0; i < 9; ++i) r.pad[i] = 0;
-    rec_slot[bid] = r;
+    rec_write(rec_slot, bid, c, tnf, tmf, o != 0);
   }
   __syncthreads();
 }
@@ -379,7 +399,7 @@ SX_DEV void ballot_fill_range(long long lo, long long hi, unsigned bid, Probe pr
 template <class Pred, class Deg, class VertexOf>
 SX_DEV void ballot_fill(const VGrid &vg, int count, Pred pred, Deg degree, VertexOf vertex_of,
                         const Params &P, int chunk, unsigned long long *const bits[NBINS],
-                        const Regions &R, WgRec *rec_slot, LdsBallot &lb) {
+                        const Regions &R, RecSlot *rec_slot, LdsBallot &lb) {
   const long long unit = 64 * kWaves;
   const long long per_wg = (((long long)count + vg.nb - 1) / vg.nb + unit - 1) / unit * unit;
   const long long lo = (long long)vg.bid * per_wg;
@@ -399,8 +419,19 @@ SX_DEV void ballot_fill(const VGrid &vg, int count, Pred pred, Deg degree, Verte
 // prefix sum of their degrees in LDS, then walks the concatenated arcs 64 at
 // a time (one arc per lane), so lanes stay busy however degrees vary.
 template <class Acc, class Op>
+SX_DEV void visit_med(int n, Acc item, unsigned cnt, const int *off, const int *idx, Op &op,
+                      unsigned gw, unsigned nwaves);
+
+template <class Acc, class Op>
 SX_DEV void visit_small(int n, Acc item, unsigned cnt, const int *off, const int *idx, Op &op,
                         unsigned gw, unsigned nwaves, int *lds /* 3*64 per wave */) {
+  // a short list would leave most wavefronts idle while a few walk 64 rows
+  // each: give every vertex a wavefront of its own instead (its row is
+  // shorter than 64 arcs, so one round)
+  if (cnt <= nwaves / 4) {
+    visit_med(n, item, cnt, off, idx, op, gw, nwaves);
+    return;
+  }
   const int lane = lane_id();
   int *l_v = lds, *l_beg = lds + 64, *l_ex = lds + 128;
   for (unsigned c = gw; c * 64u < cnt; c += nwaves) {

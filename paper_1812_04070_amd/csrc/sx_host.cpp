@@ -264,7 +264,7 @@ static sx_status work_alloc(Alloc al, long long n, long long m, bool directed, i
   w.tot_s = (unsigned)z.tot_s;
   w.tot_m = (unsigned)z.tot_s;
   w.tot_l = (unsigned)z.tot_l;
-  ALLOC(w.rec, sizeof(WgRec) * NSLOTS * kMaxGrid);
+  ALLOC(w.rec, sizeof(RecSlot) * NSLOTS);
   for (int b = 0; b < NBINS; ++b) ALLOC(w.bits[b], 8 * z.words);
   ALLOC(w.fbits, 8 * z.fwords);
   ALLOC(w.stamp, 4 * nn);
@@ -520,17 +520,17 @@ struct HostTotals {
   unsigned nf, ovf;
 };
 static sx_status read_totals(const Work &w, int slot, int grid, hipStream_t st,
-                             std::vector<WgRec> &buf, HostTotals &T) {
-  buf.resize((size_t)grid);
-  HIP_TRY(hipMemcpyAsync(buf.data(), w.rec + (size_t)slot * kMaxGrid, sizeof(WgRec) * grid,
-                         hipMemcpyDeviceToHost, st));
+                             std::vector<RecSlot> &buf, HostTotals &T) {
+  buf.resize(1);
+  HIP_TRY(hipMemcpyAsync(buf.data(), w.rec + slot, sizeof(RecSlot), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   memset(&T, 0, sizeof T);
-  for (const WgRec &r : buf) {
-    for (int b = 0; b < NBINS; ++b) T.cnt[b] += r.cnt[b];
-    T.nf += r.nf;
-    T.mf += r.mf;
-    T.ovf |= r.ovf;
+  const RecSlot &r = buf[0];
+  for (int b = 0; b < grid; ++b) {
+    for (int i = 0; i < NBINS; ++i) T.cnt[i] += r.cnt[i][b];
+    T.nf += r.nf[b] & ~kRecOvf;
+    T.ovf |= (r.nf[b] & kRecOvf) ? 1u : 0u;
+    T.mf += r.mf[b];
   }
   return SX_OK;
 }
@@ -642,7 +642,7 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
     sx_status s0 = read_ctrl(G, st);
     if (s0 != SX_OK) return s0;
     unsigned long long mu = *(const unsigned long long *)&G->h_ctrl->state.v[6];
-    std::vector<WgRec> buf;
+    std::vector<RecSlot> buf;
     for (int it = 0;; ++it) {
       if (!pulling) {
         HIP_TRY(trav_launch(TK_PUSH_STEP, sssp, a, it, rebuilt ? 1 : 0, grid, st));
@@ -840,7 +840,7 @@ extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_
     snap.items.push_back({w.reg_m[par], sizeof(int) * (size_t)w.tot_m});
     snap.items.push_back({w.reg_l[par], sizeof(unsigned long long) * (size_t)w.tot_l});
   }
-  snap.items.push_back({w.rec, sizeof(WgRec) * NSLOTS * kMaxGrid});
+  snap.items.push_back({w.rec, sizeof(RecSlot) * NSLOTS});
   snap.items.push_back({d_out, sizeof(int) * (size_t)n});
   snap.items.push_back({w.stamp, sizeof(int) * (size_t)n});
   snap.items.push_back({w.ctrl, sizeof(Ctrl)});
@@ -866,7 +866,7 @@ extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_
   bool last_ovf = false, pulling = false, rebuilt = false;
   int rec = 0;
   hipEvent_t e0 = G->ev0, e1 = G->ev1;
-  std::vector<WgRec> buf;
+  std::vector<RecSlot> buf;
   for (int it = 0;; ++it) {
     if (rec < max_records && it % stride == 0) {
       float *x = features + (size_t)rec * 8;

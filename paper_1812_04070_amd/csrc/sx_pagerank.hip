@@ -87,7 +87,7 @@ SX_DEV void pr_lists(const PrArgs &a, LdsPr &lds) {
   auto ident = [](int i) { return i; };
   const VGrid vg = hw_grid();
   ballot_fill(vg, a.g.n, pred, deg, ident, a.P, 0x7fffffff, a.w.bits, regions(a.w, 0, vg.nb),
-              a.w.rec + (size_t)SLOT_SCAN * kMaxGrid, lds.ball);
+              a.w.rec + SLOT_SCAN, lds.ball);
 }
 
 // One vertex's new value from its in-arc sum; returns the dangling share.
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(kBlock) k_pr_fused(PrArgs a) {
   L.V = &lds.view;
   L.R = regions(a.w, 0, vg.nb);
   L.G = vg.nb;
-  const Totals T = view_build(a.w.rec + (size_t)SLOT_SCAN * kMaxGrid, vg.nb, L.R, lds.view, lds.red);
+  const Totals T = view_build(a.w.rec + SLOT_SCAN, vg.nb, L.R, lds.view, lds.red);
   if (T.ovf) {
     if (threadIdx.x == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
     return;

@@ -45,11 +45,11 @@ struct BfsOps {
   // push Compute + Combine for arc v->u; true when u becomes active
   SX_DEV bool push(int v, int u, int arc, const DevGraph &g, unsigned &err) const {
     (void)v; (void)arc; (void)g; (void)err;
-    return load_relaxed(&depth[u]) == -1 && atomic_cas_i32(&depth[u], -1, it + 1);
+    return depth[u] == -1 && atomic_cas_i32(&depth[u], -1, it + 1);
   }
-  SX_DEV bool next_active(int v) const { return load_relaxed(&depth[v]) == it + 1; }
-  SX_DEV bool in_frontier(int v) const { return load_relaxed(&depth[v]) == it; }
-  SX_DEV bool pull_candidate(int v) const { return load_relaxed(&depth[v]) == -1; }
+  SX_DEV bool next_active(int v) const { return depth[v] == it + 1; }
+  SX_DEV bool in_frontier(int v) const { return depth[v] == it; }
+  SX_DEV bool pull_candidate(int v) const { return depth[v] == -1; }
 };
 
 struct SsspOps {
@@ -58,16 +58,16 @@ struct SsspOps {
   int *stamp;
   int it;
   SX_DEV bool push(int v, int u, int arc, const DevGraph &g, unsigned &err) const {
-    const unsigned dv = load_relaxed(&dist[v]);
+    const unsigned dv = dist[v];
     const unsigned nd = dv + g.w[arc];
     if (nd < dv || nd == 0xFFFFFFFFu) { err = SX_ERR_OVERFLOW; return false; }
-    if (nd >= load_relaxed(&dist[u])) return false;
+    if (nd >= dist[u]) return false;
     const unsigned old = atomic_min_u32(&dist[u], nd);
     if (nd >= old) return false;
     return atomic_exch_i32(&stamp[u], it + 1) != it + 1;
   }
-  SX_DEV bool next_active(int v) const { return load_relaxed(&stamp[v]) == it + 1; }
-  SX_DEV bool in_frontier(int v) const { return load_relaxed(&stamp[v]) == it; }
+  SX_DEV bool next_active(int v) const { return stamp[v] == it + 1; }
+  SX_DEV bool in_frontier(int v) const { return stamp[v] == it; }
   SX_DEV bool pull_candidate(int v) const { (void)v; return true; }
 };
 
@@ -80,6 +80,7 @@ struct LdsTrav {
   LdsBallot ball;
   long long red[kWaves];
   unsigned cnt[kWaves];
+  unsigned sq[33];                 // the run-state line and the error word
 };
 
 SX_DEV void raise_error(Ctrl *C, unsigned e) { store_relaxed(&C->error.v[0], e); }
@@ -112,7 +113,7 @@ SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   visit_med(g.n, [&](unsigned i) { return cur.med(i); }, T.cnt[BIN_MED], g.off, g.idx, op, gw, nw);
   visit_small(g.n, [&](unsigned i) { return cur.small(i); }, T.cnt[BIN_SMALL], g.off, g.idx, op, gw,
               nw, lds.small[wave_in_wg()]);
-  bins_end(lds.bins, st, a.w.rec + (size_t)((it + 1) % 3) * kMaxGrid, vg.bid);
+  bins_end(lds.bins, st, a.w.rec + ((it + 1) % 3), vg.bid);
   if (err) raise_error(a.w.ctrl, err);
   add_stats(a.w.ctrl, vg.bid, edges,
             vg.bid == 0 ? (unsigned long long)T.cnt[0] + T.cnt[1] + T.cnt[2] : 0ull, lds.red);
@@ -131,7 +132,7 @@ SX_PHASE void ballot_next(const VGrid &vg, const TravArgs &a, const Params &P, c
   auto ident = [](int i) { return i; };
   const Regions R = regions(w, (it + 1) & 1, vg.nb);
   ballot_fill(vg, a.g.n, pred, deg, ident, P, P.chunk, w.bits, R,
-              w.rec + (size_t)SLOT_SCAN * kMaxGrid, lds.ball);
+              w.rec + SLOT_SCAN, lds.ball);
   if (vg.bid == 0 && threadIdx.x == 0) atomic_add_u32(&w.ctrl->stats.v[4], 1u);
 }
 
@@ -160,7 +161,7 @@ SX_PHASE void pull_scan(const VGrid &vg, const TravArgs &a, const Params &P, con
   auto ident = [](int i) { return i; };
   const Regions R = regions(w, it & 1, vg.nb);
   ballot_fill(vg, n, pred, deg, ident, P, 0x7fffffff, w.bits, R,
-              w.rec + (size_t)SLOT_SCAN * kMaxGrid, lds.ball);
+              w.rec + SLOT_SCAN, lds.ball);
 }
 
 SX_DEV bool fbit(const unsigned long long *fb, int u) { return (fb[u >> 6] >> (u & 63)) & 1ull; }
@@ -189,7 +190,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
     if ((unsigned)v >= (unsigned)g.n) continue;
     const int beg = g.in_off[v], end = g.in_off[v + 1];
     unsigned best = 0xFFFFFFFFu;
-    if (!Ops::kVote) best = load_relaxed(&dist[v]);
+    if (!Ops::kVote) best = dist[v];
     bool found = false;
     for (int b = beg; b < end; b += kBlock) {
       const int arc = b + (int)threadIdx.x;
@@ -200,7 +201,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
         if (fbit(fb, u)) {
           hit = true;
           if (!Ops::kVote) {
-            const unsigned c = load_relaxed(&dist[u]) + g.in_w[arc];
+            const unsigned c = dist[u] + g.in_w[arc];
             best = c < best ? c : best;
           }
         }
@@ -219,7 +220,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
       __syncthreads();
       if (threadIdx.x == 0) {
         for (int w2 = 0; w2 < kWaves; ++w2) best = lds.cnt[w2] < best ? lds.cnt[w2] : best;
-        if (best < load_relaxed(&dist[v])) {
+        if (best < dist[v]) {
           store_relaxed(&dist[v], best);
           store_relaxed(&a.w.stamp[v], it + 1);
           act = true;
@@ -246,7 +247,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
         if (fbit(fb, u)) {
           hit = true;
           if (!Ops::kVote) {
-            const unsigned c = load_relaxed(&dist[u]) + g.in_w[arc];
+            const unsigned c = dist[u] + g.in_w[arc];
             best = c < best ? c : best;
           }
         }
@@ -258,7 +259,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
       if (found && lane == 0) { store_relaxed(&a.state_i[v], it + 1); act = true; }
     } else {
       best = wave_min_u(best);
-      if (lane == 0 && best < load_relaxed(&dist[v])) {
+      if (lane == 0 && best < dist[v]) {
         store_relaxed(&dist[v], best);
         store_relaxed(&a.w.stamp[v], it + 1);
         act = true;
@@ -292,7 +293,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
           }
           if (act) store_relaxed(&a.state_i[v], it + 1);
         } else {
-          unsigned best = load_relaxed(&dist[v]);
+          unsigned best = dist[v];
           const unsigned old = best;
           for (; arc + 4 <= end; arc += 4) {
             int u[4];
@@ -304,7 +305,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
 #pragma unroll
             for (int j = 0; j < 4; ++j)
               if (h[j]) {
-                const unsigned cc = load_relaxed(&dist[u[j]]) + g.in_w[arc + j];
+                const unsigned cc = dist[u[j]] + g.in_w[arc + j];
                 best = cc < best ? cc : best;
               }
             edges += 4;
@@ -313,7 +314,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
             ++edges;
             const int u1 = g.in_idx[arc];
             if (fbit(fb, u1)) {
-              const unsigned cc = load_relaxed(&dist[u1]) + g.in_w[arc];
+              const unsigned cc = dist[u1] + g.in_w[arc];
               best = cc < best ? cc : best;
             }
           }
@@ -327,7 +328,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
     }
     bins_append(act, v, act ? out_deg(v, d) : 0, NR, vg.bid, P, P.chunk, lds.bins, st);
   }
-  bins_end(lds.bins, st, a.w.rec + (size_t)((it + 1) % 3) * kMaxGrid, vg.bid);
+  bins_end(lds.bins, st, a.w.rec + ((it + 1) % 3), vg.bid);
   add_stats(a.w.ctrl, vg.bid, edges, vg.bid == 0 ? (unsigned long long)cs + cm + cl : 0ull, lds.red);
   if (vg.bid == 0 && threadIdx.x == 0) atomic_add_u32(&a.w.ctrl->stats.v[5], 1u);
 }
@@ -338,7 +339,7 @@ SX_DEV Totals make_view(const VGrid &vg, const TravArgs &a, int slot, int parity
   ref.V = &lds.view;
   ref.R = regions(a.w, parity, vg.nb);
   ref.G = vg.nb;
-  return view_build(a.w.rec + (size_t)slot * kMaxGrid, vg.nb, ref.R, lds.view, lds.red);
+  return view_build(a.w.rec + slot, vg.nb, ref.R, lds.view, lds.red);
 }
 
 // A list built by a ballot scan never exceeds its regions (the host sizes
@@ -492,7 +493,6 @@ SX_DEV int run_loop(const VGrid &vg, const TravArgs &a, GridBarrier &bar, LdsTra
       Ops ops = make_ops<Ops>(a, s.it);
       push_phase(vg, a, s.P, ops, s.it, ref, T, lds);
       if (!bar.sync()) return EXIT_ERROR;
-      if (load_relaxed(&C->error.v[0])) return EXIT_ERROR;
       T = make_view(vg, a, (s.it + 1) % 3, (s.it + 1) & 1, lds, ref);
       Decision d = decide<Ops>(a, s, false, T, &pol);
       rebuilt = false;
@@ -520,7 +520,6 @@ SX_DEV int run_loop(const VGrid &vg, const TravArgs &a, GridBarrier &bar, LdsTra
       if (!scan_fits(a, T)) return EXIT_ERROR;
       pull_phase<Ops>(vg, a, s.P, s.it, ref, T, lds);
       if (!bar.sync()) return EXIT_ERROR;
-      if (load_relaxed(&C->error.v[0])) return EXIT_ERROR;
       T = make_view(vg, a, (s.it + 1) % 3, (s.it + 1) & 1, lds, ref);
       Decision d = decide<Ops>(a, s, true, T, &pol);
       if (d.done) { ++s.it; return s.it >= a.P.max_iters ? EXIT_LIMIT : EXIT_DONE; }
@@ -635,28 +634,26 @@ __global__ void __launch_bounds__(kBlock) k_seq(TravArgs a, unsigned L) {
   __shared__ LdsPolicy pol;
   Ctrl *C = a.w.ctrl;
   const VGrid vg = hw_grid();
-  const Line &in = C->seq[L & 1];
   Line &out = C->seq[(L + 1) & 1];
   const bool lead = vg.bid == 0 && threadIdx.x == 0;
-  unsigned phase = load_relaxed(&in.v[0]);
+  fetch_line(C->seq[L & 1], C, lds.sq);
+  const unsigned *in = lds.sq;
+  unsigned phase = in[0];
   RunState s;
-  s.it = (int)load_relaxed(&in.v[1]);
-  s.mu = load_relaxed((const unsigned long long *)&in.v[2]);
-  s.ps.nf_prev = load_relaxed(&in.v[4]);
-  s.ps.reached = load_relaxed((const unsigned long long *)&in.v[6]);
+  s.it = (int)in[1];
+  s.mu = (unsigned long long)in[2] | ((unsigned long long)in[3] << 32);
+  s.ps.nf_prev = in[4];
+  s.ps.reached = (unsigned long long)in[6] | ((unsigned long long)in[7] << 32);
   s.P = a.P;
-  {
-    const unsigned t1 = load_relaxed(&in.v[8]), t2 = load_relaxed(&in.v[9]);
-    if (t1) { s.P.t1 = (int)t1; s.P.t2 = (int)t2; }
-  }
-  unsigned pulling = load_relaxed(&in.v[10]);
-  const unsigned due = load_relaxed(&in.v[11]);
-  unsigned rebuilt = load_relaxed(&in.v[12]);
+  if (in[8]) { s.P.t1 = (int)in[8]; s.P.t2 = (int)in[9]; }
+  unsigned pulling = in[10];
+  const unsigned due = in[11];
+  unsigned rebuilt = in[12];
   if (phase >= SEQ_DONE) {
     if (lead) seq_store(out, phase, s, pulling, 0, rebuilt);
     return;
   }
-  if (load_relaxed(&C->error.v[0])) {
+  if (in[32]) {
     if (lead) seq_store(out, SEQ_ERROR, s, pulling, 0, rebuilt);
     return;
   }
@@ -717,7 +714,7 @@ __global__ void __launch_bounds__(kBlock) k_seq(TravArgs a, unsigned L) {
       break;
   }
   // a capacity error leaves `out` unwritten: the next launch sees the error
-  if (load_relaxed(&C->error.v[0]) == SX_ERR_CAPACITY && lead)
+  if (lead && load_relaxed(&C->error.v[0]) == SX_ERR_CAPACITY)
     seq_store(out, SEQ_ERROR, s, pulling, 0, rebuilt);
 }
 
@@ -765,12 +762,10 @@ SX_DEV void init_source(const TravArgs &a, unsigned G) {
   for (long long c = lane; c < kk; c += 64)
     R.l[c] = ((unsigned long long)c << 32) | (unsigned)a.src;
   for (unsigned w = lane; w < G; w += 64) {
-    WgRec *r = a.w.rec + w;
     const bool me = w == 0;
-    for (int i = 0; i < NBINS; ++i) r->cnt[i] = me && i == b ? (b == BIN_LARGE ? (unsigned)kk : 1u) : 0u;
-    r->nf = me ? 1u : 0u;
-    r->mf = me ? (unsigned long long)d : 0ull;
-    r->ovf = me && kk < k ? 1u : 0u;
+    unsigned c[NBINS];
+    for (int i = 0; i < NBINS; ++i) c[i] = me && i == b ? (b == BIN_LARGE ? (unsigned)kk : 1u) : 0u;
+    rec_write(a.w.rec, w, c, me ? 1u : 0u, me ? (unsigned long long)d : 0ull, me && kk < k);
   }
 }
 

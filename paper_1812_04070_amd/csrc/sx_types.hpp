@@ -31,15 +31,15 @@ struct alignas(128) Line {
   unsigned v[32];
 };
 
-// What one workgroup appended to its bins in one phase (its "thread bins" in
-// the paper's terms, Section 3.3): items per bin, vertices and their arcs,
-// and whether a bin overflowed its capacity.
-struct alignas(64) WgRec {
-  unsigned cnt[NBINS];
-  unsigned nf;
-  unsigned long long mf;
-  unsigned ovf;
-  unsigned pad[9];
+// What the workgroups appended to their bins in one phase (their "thread
+// bins" in the paper's terms, Section 3.3), one slot per list, stored field
+// by field so that a consumer reads only the counts it needs: items per bin,
+// vertices (bit 31: a bin overflowed its capacity) and their arcs.
+constexpr unsigned kRecOvf = 0x80000000u;
+struct RecSlot {
+  unsigned cnt[NBINS][kMaxGrid];
+  unsigned nf[kMaxGrid];
+  unsigned long long mf[kMaxGrid];
 };
 
 // Control block: one per graph workspace, in device memory.
@@ -76,7 +76,7 @@ struct Work {
   int *reg_s[2], *reg_m[2];        // [parity] small / medium bin regions
   unsigned long long *reg_l[2];    // [parity] large items: chunk << 32 | vertex
   unsigned tot_s, tot_m, tot_l;    // entries per bin array (all regions)
-  WgRec *rec;                      // [NSLOTS][kMaxGrid]
+  RecSlot *rec;                    // [NSLOTS]
   unsigned long long *bits[NBINS]; // ballot words, one per 64 scan positions
   unsigned long long *fbits;       // frontier bitmap (pull)
   int *stamp;                      // per-vertex int: SSSP iteration stamps
