@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=int, default=22, help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--fused", type=int, default=0, help="0 auto, 1 fused, 2 unfused")
+    ap.add_argument("--fused", type=int, default=0, help="0 auto, 1 fused, 2 unfused, 3 sequenced")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched / learned-policy leg")
     return ap.parse_args()
 
@@ -52,8 +52,10 @@ def algo_bytes(kind: str, st: dict, n: int, reached: int) -> float:
       SSSP  8 B per expansion + 12 B per inspected arc (id, weight, distance)
             + 12 B per expansion (relaxation write, list write and read)
             + 4n B per metadata scan
-      k-core 8 B per inspected arc (id + degree decrement) + 8 B per removed
-            vertex + 4n B (x2: state and degree) per alive-list scan."""
+      k-core 8 B per inspected arc (id + degree decrement, or id + stamp in a
+            pull step) + 12 B per alive-list entry scanned (entry, core number,
+            degree) + 16 B per vertex (core number and stamp writes, list
+            write and read)."""
     e, x = st["edges_inspected"], st["vertex_expansions"]
     scans = st["ballot_iters"] + st["pull_iters"]
     if kind == "bfs":
@@ -61,7 +63,7 @@ def algo_bytes(kind: str, st: dict, n: int, reached: int) -> float:
     if kind == "sssp":
         return 8.0 * x + 12.0 * e + 12.0 * x + 4.0 * n * scans
     if kind == "kcore":
-        return 8.0 * e + 8.0 * n + 8.0 * n * st["ballot_iters"]
+        return 8.0 * e + 12.0 * st["scan_entries"] + 16.0 * n
     raise KeyError(kind)
 
 
@@ -227,12 +229,21 @@ def main():
 
     algo_ms = {k: float(np.median([s["device_ms"] for s in v])) for k, v in per.items()}
     last = {k: v[-1] for k, v in per.items()}
-    # dominant kernel: the algorithm with the largest device time
+    # dominant kernel: the kernel of the algorithm with the largest device
+    # time.  Each run is one init launch followed by its phase launches, all
+    # queued back to back on one stream, so the phase kernel's average launch
+    # duration is the run's event-timed device time over its launch count
+    # (rocprofv3 --kernel-trace --stats on the same command agrees, see
+    # profiles/).
     dom = max(algo_ms, key=algo_ms.get)
     nbytes = algo_bytes(dom, last[dom], g.n, reached)
-    achieved = nbytes / (algo_ms[dom] / 1e3) / 1e9
-    kname = {"bfs": "bfs fused push/pull kernels", "sssp": "sssp fused push/pull kernels",
-             "kcore": "k-core fused kernel"}[dom]
+    phase_launches = max(1, int(last[dom]["launches"]) - 1)
+    avg_launch_us = 1e3 * algo_ms[dom] / phase_launches
+    achieved = nbytes / phase_launches / (avg_launch_us / 1e6) / 1e9
+    seq = args.fused in (0, 3)
+    kname = {"bfs": "k_seq<BfsOps>" if seq else "k_fused<BfsOps>",
+             "sssp": "k_seq<SsspOps>" if seq else "k_fused<SsspOps>",
+             "kcore": "k_kcore_seq" if seq else "k_kcore_fused"}[dom]
 
     result = {
         "metric": "GTEPS BFS/SSSP R-MAT s22, bit-exact; learned-policy+batched vs heuristic speedup",
@@ -258,7 +269,9 @@ def main():
                          "vertex_expansions": last[k]["vertex_expansions"]} for k in per},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "algorithmic_bytes": nbytes, "traffic": None},
+                     "traffic": None, "launches": phase_launches,
+                     "avg_launch_us": round(avg_launch_us, 3),
+                     "algorithmic_bytes_per_launch": round(nbytes / phase_launches, 1)},
     }
     log = lambda s: print(s, file=sys.stderr, flush=True)
     if not args.no_batch:

@@ -169,6 +169,7 @@ typedef struct {
   int64_t edges_inspected;   /* arcs read by compute                          */
   int64_t vertex_expansions; /* worklist entries processed                    */
   double device_ms;          /* stream time of the run (HIP events)           */
+  int64_t scan_entries;      /* list entries read by k-core level scans       */
 } sx_run_stats;
 
 /* Run program p on graph g.  source: start vertex (BFS, SSSP), ignored (pass

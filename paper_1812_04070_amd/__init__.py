@@ -74,7 +74,7 @@ class sx_run_stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("launches", ctypes.c_int32),
                 ("pull_iters", ctypes.c_int32), ("ballot_iters", ctypes.c_int32),
                 ("edges_inspected", ctypes.c_int64), ("vertex_expansions", ctypes.c_int64),
-                ("device_ms", ctypes.c_double)]
+                ("device_ms", ctypes.c_double), ("scan_entries", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

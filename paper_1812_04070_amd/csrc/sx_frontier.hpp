@@ -140,6 +140,36 @@ SX_DEV void rec_write(RecSlot *rs, unsigned bid, const unsigned cnt[NBINS], unsi
   rs->mf[bid] = mf;
 }
 
+// Online filter for entries that are already binned (re-emitting a list):
+// lanes with `valid` append `item` (a vertex id, or a large item chunk << 32
+// | vertex) to bin `bin`; entries with `vertex` count as one vertex of `deg`
+// arcs in the statistics (small and medium entries, first chunks).
+SX_DEV void bins_put(bool valid, int bin, unsigned long long item, bool vertex, int deg,
+                     const Regions &R, unsigned bid, LdsBins &b, WaveStats &st) {
+  if (ballot(valid) == 0) return;
+  const int lane = lane_id();
+  if (valid && vertex) { st.nf += 1; st.mf += (unsigned long long)deg; }
+#pragma unroll
+  for (int bn = 0; bn < NBINS; ++bn) {
+    const uint64_t mk = ballot(valid && bin == bn);
+    if (mk == 0) continue;
+    const int leader = __ffsll((long long)mk) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(&b.cnt[bn], (unsigned)__popcll(mk));
+    base = __shfl(base, leader);
+    if (valid && bin == bn) {
+      const unsigned pos = base + lane_prefix(mk);
+      if (pos < b.lim[bn]) {
+        if (bn == BIN_SMALL) R.s[(size_t)bid * R.cap_s + pos] = (int)item;
+        else if (bn == BIN_MED) R.m[(size_t)bid * R.cap_m + pos] = (int)item;
+        else R.l[(size_t)bid * R.cap_l + pos] = item;
+      } else {
+        b.ovf = 1;
+      }
+    }
+  }
+}
+
 // End of a producing phase (all threads): publish this workgroup's record.
 // Counts past the limit mark overflow; entries beyond it were not written.
 SX_DEV void bins_end(LdsBins &b, WaveStats &st, RecSlot *rs, unsigned bid) {
@@ -251,6 +281,24 @@ SX_DEV Totals view_build(const RecSlot *rs, unsigned G, const Regions &R, LdsVie
     if (t == 0) V.pre[b][G] = T.cnt[b];
   }
   __syncthreads();
+  return T;
+}
+
+// Totals of one record slot without the prefix (all threads).
+SX_DEV Totals rec_totals(const RecSlot *rs, unsigned G, long long *red /* kWaves */) {
+  long long c[NBINS] = {0, 0, 0}, nf = 0, mf = 0, ovf = 0;
+  for (unsigned w = threadIdx.x; w < G; w += kBlock) {
+    for (int b = 0; b < NBINS; ++b) c[b] += rs->cnt[b][w];
+    const unsigned x = rs->nf[w];
+    nf += x & ~kRecOvf;
+    ovf |= (x & kRecOvf) ? 1 : 0;
+    mf += (long long)rs->mf[w];
+  }
+  Totals T;
+  for (int b = 0; b < NBINS; ++b) T.cnt[b] = (unsigned)wg_sum_ll<kBlock>(c[b], red);
+  T.nf = (unsigned)wg_sum_ll<kBlock>(nf, red);
+  T.mf = (unsigned long long)wg_sum_ll<kBlock>(mf, red);
+  T.ovf = wg_sum_ll<kBlock>(ovf, red) ? 1u : 0u;
   return T;
 }
 

@@ -224,19 +224,18 @@ static const int kChunk = 4 * kBlock;  // arcs per large-bin item
 //   range of r vertices adds at most r + arcs / chunk: the large array holds
 //   n + 1024 gmax + gmax (ceil(arcs / chunk) + 1) entries, with arcs the
 //   degree sum (2m for the k-core of a directed graph: in- plus out-arcs);
-//   the k-core alive arrays hold n + 256 gmax entries (regions multiples of
-//   64 holding a contiguous n / G range at the start).
+//   the k-core alive lists are binned like the worklists, with the same
+//   capacities (a scan re-emits at most the entries it reads).
 struct Sizing {
-  size_t tot_s, tot_l, tot_a, words, fwords;
+  size_t tot_s, tot_l, words, fwords;
 };
 static Sizing work_sizing(long long n, long long m, bool directed, int gmax) {
   Sizing z;
   const size_t nn = (size_t)std::max<long long>(n, 1);
   const size_t arcs = (size_t)(directed ? 2 * m : m);
   z.tot_s = 2 * nn + 1024 * (size_t)gmax;
-  z.tot_a = nn + 256 * (size_t)gmax;
-  z.tot_l = nn + 1024 * (size_t)gmax + (size_t)gmax * ((arcs + kChunk - 1) / kChunk + 1);
-  z.words = (std::max(z.tot_a, nn) + 63) / 64 + 1;
+  z.tot_l = nn + 1024 * (size_t)gmax + (size_t)(gmax + 1) * ((arcs + kChunk - 1) / kChunk + 1);
+  z.words = (nn + 63) / 64 + 1;
   z.fwords = (nn + 63) / 64 + 1;
   return z;
 }
@@ -271,11 +270,11 @@ static sx_status work_alloc(Alloc al, long long n, long long m, bool directed, i
   ALLOC(w.ctrl, sizeof(Ctrl));
   if (full) {
     for (int p = 0; p < 2; ++p) {
-      ALLOC(w.alive[p], 4 * z.tot_a);
+      ALLOC(w.al_s[p], 4 * z.tot_s);
+      ALLOC(w.al_m[p], 4 * z.tot_s);
+      ALLOC(w.al_l[p], 8 * z.tot_l);
       ALLOC(w.contrib[p], 4 * nn);
     }
-    w.tot_a = (unsigned)z.tot_a;
-    ALLOC(w.alive_cnt, 4 * 2 * kMaxGrid);
     ALLOC(w.alive_min, 4 * 2 * kMaxGrid);
     ALLOC(w.deg, 4 * nn);
     ALLOC(w.dang, 4 * 4 * kMaxGrid);
@@ -469,6 +468,8 @@ static Params make_params(const sx_program *p, const sx_graph *G, int grid) {
   P.direction = pol.direction;
   P.alpha = 14.0f;
   P.beta = 24.0f;
+  P.alpha_w = 1.25f;
+  P.beta_w = 4.0f;
   // a BFS level or a Bellman-Ford round adds at least one vertex to the set
   // of settled ones, so n + 2 iterations bound every correct run
   P.max_iters = G ? G->g.n + 2 : INT_MAX / 2;
@@ -511,6 +512,7 @@ static void fill_stats(const Ctrl *c, int launches, float ms, sx_run_stats *stat
   stats->iterations = (int32_t)c->stats.v[6];
   stats->launches = launches;
   stats->device_ms = ms;
+  stats->scan_entries = (int64_t)(*(const unsigned long long *)&c->stats.v[8]);
 }
 
 // ---------------------------------------------------- BFS / SSSP runs ---

@@ -6,48 +6,55 @@
 //
 //   Active   alive and degree <= k.
 //   Compute  deleting v lowers the degree of each neighbour by one.
-//   Combine  sum (aggregation), here as an atomic decrement.  Following the
-//            paper's k-core note, a neighbour whose degree is already <= k is
-//            not decremented any more: it is being deleted at this level
-//            anyway.  The decrement that takes a degree from k+1 to k is the
-//            only one that activates the neighbour, so every vertex enters a
-//            frontier exactly once.
+//   Combine  sum (aggregation).  Push: an atomic decrement per arc; following
+//            the paper's k-core note, a neighbour whose degree is already
+//            <= k is not decremented any more (it is deleted at this level
+//            anyway).  Pull: every alive vertex counts its neighbours deleted
+//            in this step and lowers its own degree once, without atomics.
+//            A vertex is activated by the update that takes its degree from
+//            above k to k or below, so it enters a frontier exactly once.
 //
-// Task management: a level starts with a ballot-filter scan of the vertices
-// still alive.  Every workgroup keeps its own alive list (a region of the
-// alive arrays) and scans only that: the frontier (degree <= k) goes
-// sorted and binned into its bin regions, the survivors (degree > k) are
-// compacted into its region of the other alive array, with their count and
-// minimum degree in per-workgroup words, so that empty levels are skipped
-// without a grid-wide atomic.  The deletions within a level are chained by
-// the online filter.  The JIT switch of Section 4 applies: an overflowing
-// online filter is replaced by a fresh scan.  A directed graph counts in- plus
-// out-arcs; deleting v decrements through both its CSR and CSC rows.
+// A vertex deleted in step j carries stamp j (set when it enters the list of
+// step j, together with its core number), so a pull step only needs
+// stamp[u] == j to recognise the vertices being deleted.
+//
+// Task management: a level starts with a scan of the alive list (binned like
+// the worklists, per-workgroup regions, one record slot per parity): entries
+// still alive with degree <= k form the level's frontier, the others are
+// re-emitted into the other alive list, with their minimum degree per
+// workgroup so that empty levels are skipped.  The deletions within a level
+// are chained by the online filter, with the JIT switch of Section 4 (an
+// overflowing online list is replaced by a fresh scan at the same level).
+// Direction (Section 5, switching to pull for large frontiers): a step pulls
+// when the frontier's arcs exceed the alive arcs / kPullAlpha.  In R-MAT
+// graphs the dense last levels delete thousands of high-degree vertices per
+// step; pushing them costs one device-scope atomic per arc (MI355X sustains
+// ~13 G/s of them over scattered addresses) while a pull step reads the
+// alive arcs at memory speed.  A directed graph counts in- plus out-arcs and
+// walks both its CSR and CSC rows.
 #include "sx_frontier.hpp"
 #include "sx_kernels.hpp"
 
 namespace sx {
 
-// Decrements of high-degree neighbours are summed per workgroup in a small
-// LDS table and applied with one atomic per (workgroup, vertex) at the end of
-// the peel step.  In R-MAT graphs most arcs of the low-degree vertices that a
-// level deletes lead to a few hubs; one device-scope atomic per arc on the
-// same address is serialised (about 11 ns each on MI355X), which made the
-// large peel steps ~20x slower than their memory traffic.  Summing is exact:
-// the activation test needs only the value before and after each atomic.
+// Decrements of high-degree neighbours in push steps are summed per
+// workgroup in a small LDS table and applied with one atomic per
+// (workgroup, vertex) at the end of the step: most arcs of the low-degree
+// vertices that a level deletes lead to a few hubs, and device-scope atomics
+// on one address are serialised (~11 ns each).  Summing is exact: the
+// activation test needs only the value before and after each atomic.
 constexpr int kHot = 256;          // table entries (power of two)
 constexpr int kHotDeg = 64;        // current degree from which a target is summed
+constexpr float kPullAlpha = 16.f; // pull when frontier arcs > alive arcs / alpha
 
 struct LdsK {
   int hkey[kHot];
   int hcnt[kHot];
   int small[kWaves][192];
-  LdsBins bins;
+  LdsBins bins, bins2;
   LdsView view;
-  LdsBallot ball;
   long long red[kWaves];
   unsigned wmin[kWaves];
-  unsigned surv;
   unsigned sq[33];                 // the run-state line and the error word
 };
 
@@ -57,116 +64,120 @@ SX_DEV int total_degree(const DevGraph &g, int v) {
   return d;
 }
 
-// Alive regions: workgroup b of G owns entries [b * cap, b * cap + cnt) of
-// each alive array, cap a multiple of 64 (scan positions align with the
-// ballot words).
-SX_DEV unsigned alive_cap(const Work &w, unsigned G) { return (w.tot_a / G) & ~63u; }
+// The alive list of parity p as regions of a grid of G workgroups.
+SX_DEV Regions alive_regions(const Work &w, int p, unsigned G) {
+  Regions r;
+  r.s = w.al_s[p];
+  r.m = w.al_m[p];
+  r.l = w.al_l[p];
+  r.cap_s = w.tot_s / G;
+  r.cap_m = w.tot_m / G;
+  r.cap_l = w.tot_l / G;
+  return r;
+}
 
-// Level scan number s at level k: reads this workgroup's alive list in
-// alive[s & 1], writes the frontier into parity `fp`, slot SLOT_SCAN, and the
-// survivors into alive[(s + 1) & 1] with their count / minimum degree.
-SX_DEV void kscan(const VGrid &vg, const KArgs &a, int k, int s, int fp, LdsK &lds) {
+// The view of a list: record slot `slot`, regions R.
+SX_DEV Totals kview(const VGrid &vg, const Work &w, int slot, const Regions &R, LdsK &lds,
+                    ViewRef &ref) {
+  ref.V = &lds.view;
+  ref.R = R;
+  ref.G = vg.nb;
+  return view_build(w.rec + slot, vg.nb, R, lds.view, lds.red);
+}
+
+// A vertex enters the list of step `step` at level k: its core number and
+// deletion stamp are set now (single writer: the update that activated it).
+SX_DEV void mark_deleted(const KArgs &a, int v, int k, int step) {
+  a.core[v] = k;
+  a.w.stamp[v] = step;
+}
+
+// Level scan number s at level k, building the list of peel step j.  Every
+// entry of the alive list (view `A`, parity s & 1) is tested once per lane:
+// alive with degree > k -> re-emitted into alive parity (s + 1) & 1; alive
+// with degree <= k, or activated for step j by an online list that
+// overflowed -> the frontier (parity j & 1, slot SLOT_SCAN).
+SX_DEV void kscan(const VGrid &vg, const KArgs &a, int k, int s, int j, const ViewRef &A,
+                  const Totals &TA, LdsK &lds) {
   const Work &w = a.w;
   const DevGraph &g = a.g;
-  const unsigned G = vg.nb, bid = vg.bid;
-  const unsigned cap = alive_cap(w, G);
-  const long long lo = (long long)bid * cap;
-  const unsigned cnt = w.alive_cnt[(size_t)(s & 1) * kMaxGrid + bid];
-  const long long hi = lo + (cnt < cap ? cnt : cap);
-  const int *A = w.alive[s & 1];
-  int *B = w.alive[(s + 1) & 1] + lo;
-  if (threadIdx.x == 0) lds.surv = 0;
-  __syncthreads();
+  const Regions SR = alive_regions(w, (s + 1) & 1, vg.nb);
+  const Regions FR = regions(w, j & 1, vg.nb);
+  bins_begin(lds.bins, SR, 0);
+  bins_begin(lds.bins2, FR, 0);
+  WaveStats ss, fs;
   unsigned mind = 0xFFFFFFFFu;
-  auto probe = [&](long long i, bool ok) {
-    int v = 0, d = 0;
-    bool alive = false;
+  const unsigned tid = vg.bid * kBlock + threadIdx.x, nt = vg.nb * kBlock;
+  const unsigned cs = TA.cnt[BIN_SMALL], cm = TA.cnt[BIN_MED], cl = TA.cnt[BIN_LARGE];
+  const unsigned total = cs + cm + cl;
+  // wave-uniform trip count: all lanes take part in the appends
+  for (unsigned base = tid - lane_id(); base < total; base += nt) {
+    const unsigned i = base + lane_id();
+    bool ok = i < total;
+    int bin = BIN_SMALL;
+    unsigned long long item = 0;
     if (ok) {
-      v = A[i];
-      alive = (unsigned)v < (unsigned)g.n && a.core[v] == -1;
-      if (alive) d = w.deg[v];
+      if (i < cs) item = (unsigned)A.small(i);
+      else if (i < cs + cm) { bin = BIN_MED; item = (unsigned)A.med(i - cs); }
+      else { bin = BIN_LARGE; item = A.large(i - cs - cm); }
     }
-    const bool keep = alive && d > k;
-    const uint64_t mk = ballot(keep);
-    if (mk) {
-      const int leader = __ffsll((long long)mk) - 1;
-      unsigned base = 0;
-      if (lane_id() == leader) base = atomicAdd(&lds.surv, (unsigned)__popcll(mk));
-      base = __shfl(base, leader);
-      if (keep) {
-        B[base + lane_prefix(mk)] = v;
-        mind = (unsigned)d < mind ? (unsigned)d : mind;
-      }
+    const int v = (int)(item & 0xffffffffu);
+    const bool first = bin != BIN_LARGE || (item >> 32) == 0;
+    ok = ok && (unsigned)v < (unsigned)g.n;
+    bool keep = false, front = false;
+    int d = 0, td = 0;
+    if (ok) {
+      const int c = a.core[v];
+      d = w.deg[v];
+      keep = c == -1 && d > k;
+      front = first && ((c == -1 && d <= k) || (c == k && w.stamp[v] == j));
+      if (keep || front) td = total_degree(g, v);
+      if (keep) mind = (unsigned)d < mind ? (unsigned)d : mind;
     }
-    return alive && d <= k;
-  };
-  auto degree = [&](int v) { return total_degree(g, v); };
-  auto vof = [&](long long i) { return A[i]; };
-  ballot_fill_range(lo, hi, bid, probe, degree, vof, a.P, a.P.chunk, w.bits, regions(w, fp, G),
-                    w.rec + SLOT_SCAN, lds.ball);
+    bins_put(keep, bin, item, first, td, SR, vg.bid, lds.bins, ss);
+    if (front) mark_deleted(a, v, k, j);
+    bins_append(front, v, td, FR, vg.bid, a.P, a.P.chunk, lds.bins2, fs);
+  }
+  bins_end(lds.bins, ss, w.rec + SLOT_ALIVE + ((s + 1) & 1), vg.bid);
+  bins_end(lds.bins2, fs, w.rec + SLOT_SCAN, vg.bid);
   mind = wave_min_u(mind);
   if (lane_id() == 0) lds.wmin[wave_in_wg()] = mind;
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = 0; i < kWaves; ++i) mind = lds.wmin[i] < mind ? lds.wmin[i] : mind;
-    w.alive_cnt[(size_t)((s + 1) & 1) * kMaxGrid + bid] = lds.surv;
-    w.alive_min[(size_t)((s + 1) & 1) * kMaxGrid + bid] = mind;
-    if (bid == 0) atomic_add_u32(&w.ctrl->stats.v[4], 1u);
+    w.alive_min[(size_t)((s + 1) & 1) * kMaxGrid + vg.bid] = mind;
+    if (vg.bid == 0) {
+      atomic_add_u32(&w.ctrl->stats.v[4], 1u);
+      atomic_add_u64((unsigned long long *)&w.ctrl->stats.v[8], (unsigned long long)total);
+    }
   }
+  __syncthreads();
 }
 
-// Survivors of the last scan (alive parity p): total count and minimum
-// degree over all workgroups (all threads get both).
-SX_DEV void alive_totals(const VGrid &vg, const Work &w, int p, LdsK &lds, unsigned long long &cnt,
-                         unsigned &mind) {
-  long long c = 0;
+// Minimum survivor degree of the last scan (alive parity p), all threads.
+SX_DEV unsigned alive_min_degree(const VGrid &vg, const Work &w, int p, LdsK &lds) {
   unsigned m = 0xFFFFFFFFu;
   for (unsigned b = threadIdx.x; b < vg.nb; b += kBlock) {
-    c += w.alive_cnt[(size_t)p * kMaxGrid + b];
     const unsigned x = w.alive_min[(size_t)p * kMaxGrid + b];
     m = x < m ? x : m;
   }
-  cnt = (unsigned long long)wg_sum_ll<kBlock>(c, lds.red);
   m = wave_min_u(m);
   if (lane_id() == 0) lds.wmin[wave_in_wg()] = m;
   __syncthreads();
-  mind = 0xFFFFFFFFu;
+  unsigned mind = 0xFFFFFFFFu;
   for (int i = 0; i < kWaves; ++i) mind = lds.wmin[i] < mind ? lds.wmin[i] : mind;
   __syncthreads();
+  return mind;
 }
 
-SX_DEV Totals kview(const VGrid &vg, const KArgs &a, int slot, int parity, LdsK &lds, ViewRef &ref) {
-  ref.V = &lds.view;
-  ref.R = regions(a.w, parity, vg.nb);
-  ref.G = vg.nb;
-  return view_build(a.w.rec + slot, vg.nb, ref.R, lds.view, lds.red);
-}
-
-// Peel step j: delete the frontier (view `cur`), decrement the neighbours,
-// online filter into slot (j + 1) % 3, parity (j + 1) & 1.
-SX_DEV void kpeel(const VGrid &vg, const KArgs &a, int k, int j, const ViewRef &cur, const Totals &T,
-                  LdsK &lds) {
+// Push step j: the vertices of the list (view `cur`) lower the degrees of
+// their neighbours; activated neighbours form the list of step j + 1 (online
+// filter into slot (j + 1) % 3, parity (j + 1) & 1).
+SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const ViewRef &cur,
+                       const Totals &T, LdsK &lds) {
   const Work &w = a.w;
   const DevGraph &g = a.g;
   const unsigned cs = T.cnt[BIN_SMALL], cm = T.cnt[BIN_MED], cl = T.cnt[BIN_LARGE];
-  // mark the frontier deleted with core number k
-  {
-    const unsigned tid = vg.bid * kBlock + threadIdx.x, nt = vg.nb * kBlock;
-    const unsigned un = (unsigned)g.n;
-    for (unsigned i = tid; i < cs; i += nt) {
-      const int v = cur.small(i);
-      if ((unsigned)v < un) a.core[v] = k;
-    }
-    for (unsigned i = tid; i < cm; i += nt) {
-      const int v = cur.med(i);
-      if ((unsigned)v < un) a.core[v] = k;
-    }
-    for (unsigned i = tid; i < cl; i += nt) {
-      const unsigned long long it = cur.large(i);
-      const unsigned v = (unsigned)(it & 0xffffffffu);
-      if ((it >> 32) == 0 && v < un) a.core[v] = k;
-    }
-  }
   for (int i = threadIdx.x; i < kHot; i += kBlock) {
     lds.hkey[i] = -1;
     lds.hcnt[i] = 0;
@@ -199,7 +210,11 @@ SX_DEV void kpeel(const VGrid &vg, const KArgs &a, int k, int j, const ViewRef &
       const int d = deg[u];   // a stale (higher) value only costs an atomic
       if (d > k && !(d >= kHotDeg && hot_add(u))) {
         const int old = atomic_sub_i32(&deg[u], 1);
-        if (old == k + 1) { act = true; du = total_degree(g, u); }
+        if (old == k + 1) {
+          act = true;
+          du = total_degree(g, u);
+          mark_deleted(a, u, k, j + 1);
+        }
       }
     }
     bins_append(act, u, du, NR, vg.bid, a.P, a.P.chunk, lds.bins, st);
@@ -215,7 +230,7 @@ SX_DEV void kpeel(const VGrid &vg, const KArgs &a, int k, int j, const ViewRef &
                 lds.small[wave_in_wg()]);
   }
   // apply the summed decrements: u is activated by the atomic whose range
-  // (old - c, old] holds k + 1 ... i.e. old > k >= old - c
+  // (old - c, old] holds k, i.e. old > k >= old - c
   __syncthreads();
   if (wave_in_wg() < kHot / 64) {
     const int u = lds.hkey[threadIdx.x];
@@ -224,7 +239,11 @@ SX_DEV void kpeel(const VGrid &vg, const KArgs &a, int k, int j, const ViewRef &
     int du = 0;
     if (u >= 0 && c > 0 && (unsigned)u < (unsigned)g.n) {
       const int old = atomic_sub_i32(&deg[u], c);
-      if (old > k && old - c <= k) { act = true; du = total_degree(g, u); }
+      if (old > k && old - c <= k) {
+        act = true;
+        du = total_degree(g, u);
+        mark_deleted(a, u, k, j + 1);
+      }
     }
     bins_append(act, u, du, NR, vg.bid, a.P, a.P.chunk, lds.bins, st);
   }
@@ -232,42 +251,191 @@ SX_DEV void kpeel(const VGrid &vg, const KArgs &a, int k, int j, const ViewRef &
   add_stats(w.ctrl, vg.bid, edges, vg.bid == 0 ? (unsigned long long)cs + cm + cl : 0ull, lds.red);
 }
 
-// The run state of a decomposition: level k, scans done s, peel steps done
-// j, and whether the lists of peel j come from a scan.
+// Pull step j: every alive vertex of the alive list (view `A`) counts its
+// neighbours with stamp j and lowers its own degree by that count (a large
+// vertex per chunk of arcs, one atomic per chunk); activated vertices form
+// the list of step j + 1.
+SX_DEV void kpeel_pull(const VGrid &vg, const KArgs &a, int k, int j, const ViewRef &A,
+                       const Totals &TA, LdsK &lds) {
+  const Work &w = a.w;
+  const DevGraph &g = a.g;
+  const int *stamp = w.stamp;
+  int *deg = w.deg;
+  const Regions NR = regions(w, (j + 1) & 1, vg.nb);
+  bins_begin(lds.bins, NR, a.P.online_cap);
+  WaveStats st;
+  long long edges = 0;
+  const int lane = lane_id();
+  const int passes = g.directed ? 2 : 1;
+  // small vertices: one lane each, four arcs per round
+  auto count_row = [&](const int *idx, int beg, int end) {
+    int c = 0;
+    int e = beg;
+    for (; e + 4 <= end; e += 4) {
+      const int u0 = idx[e], u1 = idx[e + 1], u2 = idx[e + 2], u3 = idx[e + 3];
+      c += (stamp[u0] == j) + (stamp[u1] == j) + (stamp[u2] == j) + (stamp[u3] == j);
+    }
+    for (; e < end; ++e) c += stamp[idx[e]] == j;
+    edges += end - beg;
+    return c;
+  };
+  auto settle = [&](int v, int c, bool &act, int &du) {
+    // single writer of deg[v]: no other update of v in a pull step
+    const int d = deg[v];
+    deg[v] = d - c;
+    if (d > k && d - c <= k) {
+      act = true;
+      du = total_degree(g, v);
+      mark_deleted(a, v, k, j + 1);
+    }
+  };
+  const unsigned gw = vg.bid * kWaves + wave_in_wg();
+  const unsigned nw = vg.nb * kWaves;
+  const unsigned cs = TA.cnt[BIN_SMALL], cm = TA.cnt[BIN_MED], cl = TA.cnt[BIN_LARGE];
+  for (unsigned c0 = gw * 64u; c0 < cs; c0 += nw * 64u) {
+    const unsigned i = c0 + lane;
+    bool act = false;
+    int v = 0, du = 0;
+    if (i < cs) {
+      const int x = A.small(i);
+      if ((unsigned)x < (unsigned)g.n && a.core[x] == -1) {
+        v = x;
+        int c = count_row(g.idx, g.off[v], g.off[v + 1]);
+        if (passes == 2) c += count_row(g.in_idx, g.in_off[v], g.in_off[v + 1]);
+        if (c) settle(v, c, act, du);
+      }
+    }
+    bins_append(act, v, du, NR, vg.bid, a.P, a.P.chunk, lds.bins, st);
+  }
+  // medium vertices: one wavefront each
+  for (unsigned i = gw; i < cm; i += nw) {
+    const int v = A.med(i);
+    if ((unsigned)v >= (unsigned)g.n || __shfl(a.core[v], 0) != -1) continue;
+    int c = 0;
+    for (int pass = 0; pass < passes; ++pass) {
+      const int *off = pass ? g.in_off : g.off;
+      const int *idx = pass ? g.in_idx : g.idx;
+      const int beg = off[v], end = off[v + 1];
+      for (int e = beg + lane; e < end; e += 64) {
+        c += stamp[idx[e]] == j;
+        ++edges;
+      }
+    }
+    c = wave_sum_i(c);
+    bool act = false;
+    int du = 0;
+    if (lane == 0 && c) settle(v, c, act, du);
+    bins_append(act, v, du, NR, vg.bid, a.P, a.P.chunk, lds.bins, st);
+  }
+  // large vertices: one workgroup per chunk of arcs, one atomic per chunk.
+  // The workgroup that settles another chunk of v may set core[v] while this
+  // one reads it, so the test is agreed on by a barrier: every wavefront must
+  // take the same branch around the reduction's barriers below.
+  for (unsigned i = vg.bid; i < cl; i += vg.nb) {
+    const unsigned long long it = A.large(i);
+    const int v = (int)(it & 0xffffffffu);
+    if ((unsigned)v >= (unsigned)g.n) continue;
+    if (!__syncthreads_and(a.core[v] == -1)) continue;
+    const long long ch = (long long)(it >> 32) * a.P.chunk;
+    int c = 0;
+    for (int pass = 0; pass < passes; ++pass) {
+      const int *off = pass ? g.in_off : g.off;
+      const int *idx = pass ? g.in_idx : g.idx;
+      const long long vb = off[v], ve = off[v + 1];
+      const long long b0 = vb + ch < ve ? vb + ch : ve;
+      const long long e0 = b0 + a.P.chunk < ve ? b0 + a.P.chunk : ve;
+      for (long long e = b0 + threadIdx.x; e < e0; e += kBlock) {
+        c += stamp[idx[e]] == j;
+        ++edges;
+      }
+    }
+    c = (int)wg_sum_ll<kBlock>(c, lds.red);
+    bool act = false;
+    int du = 0;
+    if (threadIdx.x == 0 && c) {
+      const int old = atomic_sub_i32(&deg[v], c);
+      if (old > k && old - c <= k) {
+        act = true;
+        du = total_degree(g, v);
+        mark_deleted(a, v, k, j + 1);
+      }
+    }
+    if (wave_in_wg() == 0) bins_append(act, v, du, NR, vg.bid, a.P, a.P.chunk, lds.bins, st);
+  }
+  bins_end(lds.bins, st, w.rec + ((j + 1) % 3), vg.bid);
+  add_stats(w.ctrl, vg.bid, edges, vg.bid == 0 ? (unsigned long long)cs + cm + cl : 0ull, lds.red);
+  if (vg.bid == 0 && threadIdx.x == 0) atomic_add_u32(&w.ctrl->stats.v[5], 1u);
+}
+
+// Run state: level k, scans done s, peel steps done j, the list of step j
+// comes from a scan, the arcs of the alive list of the last scan.
 struct KState {
   int k, s, j;
   bool from_scan;
+  unsigned long long alive_arcs;
 };
 
-// What to do after a scan: 1 peel, 0 scan again at a higher level (k
-// updated), -1 done.
-SX_DEV int after_scan(const VGrid &vg, const KArgs &a, KState &q, const Totals &T, LdsK &lds) {
+// What follows a scan: 1 peel, 0 scan again at a higher level (k updated),
+// -1 done.  T: the frontier, TA: the survivors.
+SX_DEV int after_scan(const VGrid &vg, const KArgs &a, KState &q, const Totals &T,
+                      const Totals &TA, LdsK &lds) {
+  q.alive_arcs = TA.mf;
   if (T.nf > 0) return 1;
-  unsigned long long surv;
-  unsigned mind;
-  alive_totals(vg, a.w, q.s & 1, lds, surv, mind);
-  if (surv == 0) return -1;
+  if (TA.nf == 0) return -1;
   // empty level: jump to the smallest surviving degree
+  const unsigned mind = alive_min_degree(vg, a.w, q.s & 1, lds);
   q.k = (int)mind > q.k + 1 ? (int)mind : q.k + 1;
   return 0;
 }
 
+// Direction of the next peel step: the policy's fixed direction, else pull
+// when the step's arcs exceed the alive arcs / kPullAlpha.
+SX_DEV bool pull_step(const KState &q, const Totals &T, const Params &P) {
+  if (P.direction == 1) return false;
+  if (P.direction == 2) return true;
+  return (double)T.mf * kPullAlpha > (double)q.alive_arcs;
+}
+
+// One peel step: pull over the alive list or push from the step's list.
+// `have` / `T` / `ref`: the view of the step's list, when already built.
+SX_DEV void kpeel(const VGrid &vg, const KArgs &a, const KState &q, bool pull, bool have,
+                  Totals &T, ViewRef &ref, LdsK &lds) {
+  if (pull) {
+    const Totals TA = kview(vg, a.w, SLOT_ALIVE + (q.s & 1), alive_regions(a.w, q.s & 1, vg.nb),
+                            lds, ref);
+    kpeel_pull(vg, a, q.k, q.j, ref, TA, lds);
+  } else {
+    if (!have)
+      T = kview(vg, a.w, q.from_scan ? SLOT_SCAN : q.j % 3, regions(a.w, q.j & 1, vg.nb), lds, ref);
+    kpeel_push(vg, a, q.k, q.j, ref, T, lds);
+  }
+}
+
+// A scan: the view of the alive list, then kscan.
+SX_DEV void kscan_phase(const VGrid &vg, const KArgs &a, const KState &q, LdsK &lds) {
+  ViewRef A;
+  const Totals TA = kview(vg, a.w, SLOT_ALIVE + (q.s & 1), alive_regions(a.w, q.s & 1, vg.nb), lds, A);
+  kscan(vg, a, q.k, q.s, q.j, A, TA, lds);
+}
+
 // Persistent kernel: the whole decomposition in one launch.
 // Ctrl::aux: [10] k [11] scans [12] peel steps [13] lists of the next peel
-// come from a scan [14] next step kind (0 scan, 1 peel)
-enum { AUX_K = 10, AUX_SCAN = 11, AUX_STEP = 12, AUX_FROM = 13, AUX_KIND = 14 };
+// come from a scan [14] next step kind (0 scan, 1 peel) [16,17] alive arcs
+enum { AUX_K = 10, AUX_SCAN = 11, AUX_STEP = 12, AUX_FROM = 13, AUX_KIND = 14, AUX_ARCS = 16 };
 
 __global__ void __launch_bounds__(kBlock) k_kcore_fused(KArgs a) {
   __shared__ LdsK lds;
   Ctrl *C = a.w.ctrl;
   const VGrid vg = hw_grid();
   GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]));
+  fetch_line(C->aux, C, lds.sq);
   KState q;
-  q.k = (int)load_relaxed(&C->aux.v[AUX_K]);
-  q.s = (int)load_relaxed(&C->aux.v[AUX_SCAN]);
-  q.j = (int)load_relaxed(&C->aux.v[AUX_STEP]);
-  q.from_scan = load_relaxed(&C->aux.v[AUX_FROM]) != 0;
-  int kind = (int)load_relaxed(&C->aux.v[AUX_KIND]);
+  q.k = (int)lds.sq[AUX_K];
+  q.s = (int)lds.sq[AUX_SCAN];
+  q.j = (int)lds.sq[AUX_STEP];
+  q.from_scan = lds.sq[AUX_FROM] != 0;
+  q.alive_arcs = (unsigned long long)lds.sq[AUX_ARCS] | ((unsigned long long)lds.sq[AUX_ARCS + 1] << 32);
+  int kind = (int)lds.sq[AUX_KIND];
   auto save = [&](int reason) {
     if (vg.bid == 0 && threadIdx.x == 0) {
       store_relaxed(&C->state.v[0], (unsigned)reason);
@@ -276,46 +444,46 @@ __global__ void __launch_bounds__(kBlock) k_kcore_fused(KArgs a) {
       store_relaxed(&C->aux.v[AUX_STEP], (unsigned)q.j);
       store_relaxed(&C->aux.v[AUX_FROM], q.from_scan ? 1u : 0u);
       store_relaxed(&C->aux.v[AUX_KIND], (unsigned)kind);
+      store_relaxed((unsigned long long *)&C->aux.v[AUX_ARCS], q.alive_arcs);
     }
   };
-  if (load_relaxed(&C->state.v[0]) != EXIT_NONE || bar.failed()) return;
+  if (load_relaxed(&C->state.v[0]) != EXIT_NONE || lds.sq[32]) return;
   // every step deletes at least one vertex or raises k: bound the loop
   const long long limit = 4ll * a.g.n + 64;
   ViewRef ref;
   Totals V;
-  bool have = false;
+  bool have = false, pull = false;
   for (long long guard = 0;; ++guard) {
     if (guard > limit) { save(EXIT_LIMIT); return; }
     if (kind == 0) {
-      kscan(vg, a, q.k, q.s, q.j & 1, lds);
+      kscan_phase(vg, a, q, lds);
       if (!bar.sync()) { save(EXIT_ERROR); return; }
       ++q.s;
-      const Totals T = kview(vg, a, SLOT_SCAN, q.j & 1, lds, ref);
-      if (T.ovf) {
+      V = kview(vg, a.w, SLOT_SCAN, regions(a.w, q.j & 1, vg.nb), lds, ref);
+      const Totals TA = rec_totals(a.w.rec + SLOT_ALIVE + (q.s & 1), vg.nb, lds.red);
+      if (V.ovf || TA.ovf) {
         if (threadIdx.x == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
         save(EXIT_ERROR);
         return;
       }
-      const int r = after_scan(vg, a, q, T, lds);
+      const int r = after_scan(vg, a, q, V, TA, lds);
       if (r < 0) { save(EXIT_DONE); return; }
       if (r == 0) continue;
       kind = 1;
       q.from_scan = true;
-      V = T;
       have = true;
+      pull = pull_step(q, V, a.P);
     } else {
-      // the view of the peel's lists was built by the decision before it,
-      // except when the kernel starts here
-      if (!have) V = kview(vg, a, q.from_scan ? SLOT_SCAN : q.j % 3, q.j & 1, lds, ref);
-      kpeel(vg, a, q.k, q.j, ref, V, lds);
+      kpeel(vg, a, q, pull, have, V, ref, lds);
       if (!bar.sync()) { save(EXIT_ERROR); return; }
       if (vg.bid == 0 && threadIdx.x == 0) atomic_add_u32(&C->stats.v[6], 1u);
       ++q.j;
-      V = kview(vg, a, q.j % 3, q.j & 1, lds, ref);
+      V = kview(vg, a.w, q.j % 3, regions(a.w, q.j & 1, vg.nb), lds, ref);
       have = true;
       q.from_scan = false;
       if (V.nf == 0) { ++q.k; kind = 0; continue; }
       if (V.ovf || a.P.filter == 2) { kind = 0; continue; }   // rebuild by a scan at the same k
+      pull = pull_step(q, V, a.P);
     }
   }
 }
@@ -323,8 +491,8 @@ __global__ void __launch_bounds__(kBlock) k_kcore_fused(KArgs a) {
 // Sequenced form of the same loop: one launch per phase (scan, peel), the
 // decision taken at the start of the launch after it; launch L reads
 // Ctrl::seq[L & 1] and writes seq[(L+1) & 1]: [0] phase [1] k [2] scans [3]
-// peel steps [4] decision due (1 after a scan, 2 after a peel) [5] the lists
-// of the next peel come from a scan.
+// peel steps [4] decision due (1 after a scan, 2 after a peel) [5] the list
+// of the next peel comes from a scan [6,7] alive arcs.
 enum : unsigned { KP_SCAN = 0, KP_PEEL = 1, KP_DONE = 6, KP_ERROR = 7, KP_LIMIT = 8 };
 
 __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
@@ -340,6 +508,7 @@ __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
   q.j = (int)lds.sq[3];
   unsigned due = lds.sq[4];
   q.from_scan = lds.sq[5] != 0;
+  q.alive_arcs = (unsigned long long)lds.sq[6] | ((unsigned long long)lds.sq[7] << 32);
   const bool lead = vg.bid == 0 && threadIdx.x == 0;
   auto save = [&](unsigned ph) {
     if (lead) {
@@ -349,6 +518,7 @@ __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
       store_relaxed(&out.v[3], (unsigned)q.j);
       store_relaxed(&out.v[4], due);
       store_relaxed(&out.v[5], q.from_scan ? 1u : 0u);
+      store_relaxed((unsigned long long *)&out.v[6], q.alive_arcs);
     }
   };
   if (phase >= KP_DONE) { save(phase); return; }
@@ -356,40 +526,38 @@ __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
   if ((long long)q.s + q.j > 4ll * a.g.n + 64) { due = 0; save(KP_LIMIT); return; }
   ViewRef ref;
   Totals V;
-  bool have = false;
+  bool have = false, pull = false;
   if (due == 1) {
-    const Totals T = kview(vg, a, SLOT_SCAN, q.j & 1, lds, ref);
-    V = T;
+    V = kview(vg, a.w, SLOT_SCAN, regions(a.w, q.j & 1, vg.nb), lds, ref);
     have = true;
-    if (T.ovf) {
+    const Totals TA = rec_totals(a.w.rec + SLOT_ALIVE + (q.s & 1), vg.nb, lds.red);
+    if (V.ovf || TA.ovf) {
       if (lead) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
       due = 0;
       save(KP_ERROR);
       return;
     }
-    const int r = after_scan(vg, a, q, T, lds);
+    const int r = after_scan(vg, a, q, V, TA, lds);
     due = 0;
     if (r < 0) { save(KP_DONE); return; }
     if (r == 0) phase = KP_SCAN;
-    else { phase = KP_PEEL; q.from_scan = true; }
+    else { phase = KP_PEEL; q.from_scan = true; pull = pull_step(q, V, a.P); }
   } else if (due == 2) {
-    V = kview(vg, a, q.j % 3, q.j & 1, lds, ref);
+    V = kview(vg, a.w, q.j % 3, regions(a.w, q.j & 1, vg.nb), lds, ref);
     have = true;
     q.from_scan = false;
     due = 0;
     if (V.nf == 0) { ++q.k; phase = KP_SCAN; }
     else if (V.ovf || a.P.filter == 2) phase = KP_SCAN;
-    else phase = KP_PEEL;
+    else { phase = KP_PEEL; pull = pull_step(q, V, a.P); }
   }
   if (phase == KP_SCAN) {
-    kscan(vg, a, q.k, q.s, q.j & 1, lds);
+    kscan_phase(vg, a, q, lds);
     ++q.s;
     due = 1;
     save(KP_SCAN);
   } else {
-    // the decision above built the view of exactly these lists
-    if (!have) V = kview(vg, a, q.from_scan ? SLOT_SCAN : q.j % 3, q.j & 1, lds, ref);
-    kpeel(vg, a, q.k, q.j, ref, V, lds);
+    kpeel(vg, a, q, pull, have, V, ref, lds);
     if (lead) atomic_add_u32(&C->stats.v[6], 1u);
     ++q.j;
     due = 2;
@@ -409,44 +577,45 @@ hipError_t kcore_seq_launch(const KArgs &a, unsigned L, int grid, hipStream_t s,
 
 const void *kcore_seq_kernel() { return (const void *)k_kcore_seq; }
 
-// Set-up for a run on G workgroups: core -1, current degrees, alive list 0 =
-// every vertex, workgroup b holding a contiguous range of per = (n / G
-// rounded up to 64) vertices.
-__global__ void k_kcore_init(KArgs a, unsigned G) {
+// Set-up, launched with the run's grid: core -1, stamp -1, current degrees,
+// and alive list 0 = every vertex (workgroup b appends a contiguous range of
+// about n / G vertices through the online filter into its regions).
+__global__ void __launch_bounds__(kBlock) k_kcore_init(KArgs a) {
+  __shared__ LdsBins bins;
+  const VGrid vg = hw_grid();
   const int n = a.g.n;
-  const unsigned cap = alive_cap(a.w, G);
-  const long long per = (((long long)n + G - 1) / G + 63) / 64 * 64;
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-       v += (long long)gridDim.x * blockDim.x) {
-    a.core[v] = -1;
-    a.w.deg[v] = total_degree(a.g, (int)v);
-    const long long b = v / per;
-    a.w.alive[0][b * cap + (v - b * per)] = (int)v;
+  const Regions R = alive_regions(a.w, 0, vg.nb);
+  bins_begin(bins, R, 0);
+  WaveStats st;
+  const long long per = ((long long)n + vg.nb - 1) / vg.nb;
+  const long long lo = (long long)vg.bid * per;
+  const long long hi = lo + per < n ? lo + per : n;
+  for (long long base = lo; base < hi; base += kBlock) {
+    const long long v = base + threadIdx.x;
+    const bool ok = v < hi;
+    int td = 0;
+    if (ok) {
+      td = total_degree(a.g, (int)v);
+      a.core[v] = -1;
+      a.w.stamp[v] = -1;
+      a.w.deg[v] = td;
+    }
+    bins_append(ok, (int)v, td, R, vg.bid, a.P, a.P.chunk, bins, st);
   }
-  for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < G;
-       b += (long long)gridDim.x * blockDim.x) {
-    const long long lo = b * per;
-    const long long c = lo >= n ? 0 : (n - lo < per ? n - lo : per);
-    a.w.alive_cnt[b] = (unsigned)c;
-  }
+  bins_end(bins, st, a.w.rec + SLOT_ALIVE, vg.bid);
   Ctrl *C = a.w.ctrl;
-  if (blockIdx.x == 0) reset_barrier(C);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (vg.bid == 0) reset_barrier(C);
+  if (vg.bid == 0 && threadIdx.x == 0) {
     for (int i = 0; i < 32; ++i) { C->state.v[i] = 0; C->stats.v[i] = 0; C->aux.v[i] = 0; }
     C->error.v[0] = 0;
   }
-  if (blockIdx.x == 1)
+  if (vg.bid == 1 || vg.nb == 1)
     for (int i = threadIdx.x; i < kStatLines * 4; i += blockDim.x) C->statw[i / 4].v[i % 4] = 0u;
 }
 
 hipError_t kcore_launch(const KArgs &a, int grid, hipStream_t s, bool init) {
-  if (init) {
-    int g = (a.g.n + kBlock - 1) / kBlock;
-    g = g < 2 ? 2 : (g > 4096 ? 4096 : g);
-    hipLaunchKernelGGL(k_kcore_init, dim3(g), dim3(kBlock), 0, s, a, (unsigned)grid);
-  } else {
-    hipLaunchKernelGGL(k_kcore_fused, dim3(grid), dim3(kBlock), 0, s, a);
-  }
+  if (init) hipLaunchKernelGGL(k_kcore_init, dim3(grid), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL(k_kcore_fused, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -24,8 +24,9 @@ enum : int { EXIT_NONE = 0, EXIT_DONE = 1, EXIT_SWITCH = 2, EXIT_ERROR = 3, EXIT
 enum : int { BIN_SMALL = 0, BIN_MED = 1, BIN_LARGE = 2, NBINS = 3 };
 
 // record slots: 0..2 rotate with the iteration (the lists a compute phase
-// appends for the next iteration); 3 holds lists built by a ballot scan
-enum : int { NSLOTS = 4, SLOT_SCAN = 3 };
+// appends for the next iteration); 3 holds lists built by a ballot scan;
+// 4 and 5 the k-core alive lists (by scan parity)
+enum : int { NSLOTS = 6, SLOT_SCAN = 3, SLOT_ALIVE = 4 };
 
 struct alignas(128) Line {
   unsigned v[32];
@@ -48,7 +49,7 @@ struct Ctrl {
   Line error;                   // SX_ERR_*
   Line state;                   // run state of the fused kernels
   Line stats;                   // u32 [4] ballot scans, [5] pull iterations,
-                                // [6] iterations
+                                // [6] iterations; u64 [8] k-core scan entries
   Line aux;                     // algorithm scratch
   Line seq[2];                  // sequenced mode: run state handed from launch
                                 // L (reads seq[L&1]) to launch L+1
@@ -81,9 +82,8 @@ struct Work {
   unsigned long long *fbits;       // frontier bitmap (pull)
   int *stamp;                      // per-vertex int: SSSP iteration stamps
   int *deg;                        // k-core current degree
-  int *alive[2];                   // k-core per-workgroup alive lists
-  unsigned tot_a;                  // entries per alive array
-  unsigned *alive_cnt;             // [2][kMaxGrid] alive list lengths
+  int *al_s[2], *al_m[2];          // k-core alive lists, binned like the
+  unsigned long long *al_l[2];     // worklists (same capacities), by parity
   unsigned *alive_min;             // [2][kMaxGrid] minimum survivor degree
   float *contrib[2];               // PageRank contributions (double buffered)
   float *dang;                     // PageRank dangling partials [2][kMaxGrid][2]
@@ -99,7 +99,8 @@ struct Params {
                                 // before overflow (0: the whole region)
   int filter;                   // 0 JIT, 1 online, 2 ballot
   int direction;                // 0 auto, 1 push, 2 pull
-  float alpha, beta;            // direction heuristic
+  float alpha, beta;            // direction heuristic (vote)
+  float alpha_w, beta_w;        // direction heuristic (aggregation)
   int max_iters;
   float pr_d;
   int pr_iters;
@@ -176,9 +177,13 @@ struct DecideIn {
 // BFS (vote): push -> pull when the frontier's arcs exceed the unexplored
 // arcs / alpha, pull -> push when the frontier falls below n / beta (the
 // direction-optimising rule of Beamer et al., which the paper's push/pull
-// switching follows for BFS: push first and last, pull in between).  SSSP:
-// pull while the frontier's arcs exceed m / alpha.  JIT filter choice: the
-// online filter's lists are used unless a bin overflowed.
+// switching follows for BFS: push first and last, pull in between).  SSSP
+// (aggregation): pull while the frontier's arcs exceed m / alpha_w, back to
+// push below m / beta_w.  A pull iteration of SSSP reads every in-arc (no
+// early exit under a minimum), so it pays only when the frontier's arcs
+// approach m: alpha_w = 1.25 (measured on MI355X, R-MAT s22: push 66 G
+// arcs/s, pull 81 G arcs/s).  JIT filter choice: the online filter's lists
+// are used unless a region overflowed.
 __host__ __device__ inline Decision decide_core(const DecideIn &in, const Params &P,
                                                 unsigned long long &mu) {
   Decision d{false, false, false, false};
@@ -190,7 +195,7 @@ __host__ __device__ inline Decision decide_core(const DecideIn &in, const Params
     if (dir == 1) pull = false;
     else if (dir == 2) pull = true;
     else if (in.vote) pull = (double)in.mf > (double)mu / P.alpha;
-    else pull = (double)in.mf > (double)in.m / P.alpha;
+    else pull = (double)in.mf > (double)in.m / P.alpha_w;
     d.to_pull = pull;
     d.ballot = !pull && (P.filter == 2 || (P.filter == 0 && in.ovf));
   } else {
@@ -198,7 +203,7 @@ __host__ __device__ inline Decision decide_core(const DecideIn &in, const Params
     if (dir == 2) push = false;
     else if (dir == 1) push = true;
     else if (in.vote) push = (double)in.nf < (double)in.n / P.beta;
-    else push = (double)in.mf < (double)in.m / P.beta;
+    else push = (double)in.mf < (double)in.m / P.beta_w;
     d.to_push = push;
   }
   return d;

@@ -168,3 +168,34 @@ def test_rmat16_workload(engine):
     c, _ = run(engine, g, sx.SX_KCORE, dg=dg)
     np.testing.assert_array_equal(c, oracle.kcore_g(g))
     dg.close()
+
+
+@pytest.mark.parametrize("scale", [18, 20])
+def test_kcore_pull_steps(engine, scale):
+    """Dense last levels of R-MAT s18 / s20 take pull steps whose large
+    candidates are split into chunks settled by different workgroups (one of
+    them may delete the vertex while another reads it).  Every direction and
+    both kernel arrangements must give the oracle's core numbers."""
+    g = gen.rmat(scale, seed=2)
+    ref = oracle.kcore_g(g)
+    dg = engine.load(g)
+    for name, pol in [("auto", sx.Policy()), ("auto-fused", sx.Policy(fused=sx.SX_FUSED)),
+                      ("pull", sx.Policy(direction=sx.SX_DIR_PULL)),
+                      ("push-fused", sx.Policy(fused=sx.SX_FUSED, direction=sx.SX_DIR_PUSH)),
+                      ("ballot", sx.Policy(filter=sx.SX_FILTER_BALLOT))]:
+        announce(f"kcore rmat{scale} {name}")
+        c, st = run(engine, g, sx.SX_KCORE, -1, pol, dg=dg)
+        np.testing.assert_array_equal(c, ref)
+        if name == "auto":
+            assert st["pull_iters"] > 0
+    dg.close()
+
+
+def test_kcore_directed_pull(engine):
+    g = gen.rmat(16, seed=4, directed=True)
+    ref = oracle.kcore_g(g)
+    for name, pol in [("auto", sx.Policy()), ("pull", sx.Policy(direction=sx.SX_DIR_PULL)),
+                      ("fused", sx.Policy(fused=sx.SX_FUSED))]:
+        announce(f"kcore rmat16d {name}")
+        c, _ = run(engine, g, sx.SX_KCORE, -1, pol)
+        np.testing.assert_array_equal(c, ref)
