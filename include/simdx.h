@@ -244,7 +244,9 @@ sx_status sx_kernel_info_get(sx_ctx *ctx, const char *name, sx_kernel_info *out)
  * thresholds (outputs 2, 3: log2 of the small/medium and medium/large degree
  * thresholds).  Parameters are SX_MLP_NPARAMS floats: W1[32][8] row-major,
  * b1[32], W2[32][32], b2[32], W3[4][32], b3[4].  The outputs never change a
- * result, only the schedule.
+ * result, only the schedule.  The network is consulted for frontiers of at
+ * least 32,768 arcs; below that (where no choice gains more than the inference
+ * costs) the heuristic decides.
  * Features (float[8]) of the decision after an iteration: log2(1+nf)/24,
  * log2(1+mf)/32, log2(1+mu)/32, nf/n, min(reached/n, 4)/4,
  * (log2(1+nf) - log2(1+nf_prev))/8, log2(1+mf/nf)/16, pulling?1:0, where nf
@@ -266,7 +268,7 @@ sx_status sx_mlp_forward(sx_ctx *ctx, const float *d_params, const float *d_x, i
 /* Mean loss over n samples and its gradient (device pointers).  d_target and
  * d_mask are [n][4]: outputs 0 and 1 take a binary cross-entropy on logits
  * against 0/1 targets, outputs 2 and 3 half the squared error; mask entries
- * (0 or 1) select the terms.  d_loss: device float[1]; d_grad: device
+ * are non-negative weights of the terms (0 drops a term, 1 keeps it).  d_loss: device float[1]; d_grad: device
  * float[SX_MLP_NPARAMS].  Sums run in sample order (deterministic). */
 sx_status sx_mlp_loss_grad(sx_ctx *ctx, const float *d_params, const float *d_x, const float *d_target,
                            const float *d_mask, int32_t n, float *d_loss, float *d_grad,

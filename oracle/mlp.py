@@ -6,7 +6,7 @@ The network (a project extension, not in the paper): 8 frontier features ->
 
 Outputs: y0 = logit of "pull", y1 = logit of "ballot filter", y2 = log2 of
 the small/medium bin threshold, y3 = log2 of the medium/large threshold.
-Per-sample loss, with a 0/1 mask per output:
+Per-sample loss, with a non-negative weight (0/1 mask) per output:
     m0 * BCE(y0, t0) + m1 * BCE(y1, t1) + m2 * (y2 - t2)^2 / 2 + m3 * (y3 - t3)^2 / 2
 (BCE on logits), averaged over the batch.
 """

@@ -68,8 +68,9 @@ struct sx_graph {
   int weighted;
   int directed;
   std::vector<void *> owned;  // device allocations to free
-  Ctrl *h_ctrl = nullptr;     // pinned host mirror of the first lines of Ctrl
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  Ctrl *h_ctrl = nullptr;     // pinned host mirrors of the first lines of Ctrl
+  Ctrl *h_ctrl2 = nullptr;    // (two: one per batch in flight)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evb[2] = {nullptr, nullptr};
 };
 
 struct sx_program {
@@ -206,8 +207,11 @@ static void free_graph(sx_graph *G) {
   if (!G) return;
   for (void *p : G->owned) (void)hipFree(p);
   if (G->h_ctrl) (void)hipHostFree(G->h_ctrl);
+  if (G->h_ctrl2) (void)hipHostFree(G->h_ctrl2);
   if (G->ev0) (void)hipEventDestroy(G->ev0);
   if (G->ev1) (void)hipEventDestroy(G->ev1);
+  for (hipEvent_t e : G->evb)
+    if (e) (void)hipEventDestroy(e);
   delete G;
 }
 
@@ -376,8 +380,11 @@ extern "C" sx_status sx_graph_load(sx_ctx *ctx, const sx_graph_desc *d, void *hi
                  kMaxGrid, true, w));
   HTRY(hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), st));
   HTRY(hipHostMalloc((void **)&G->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
+  HTRY(hipHostMalloc((void **)&G->h_ctrl2, sizeof(Ctrl), hipHostMallocDefault));
   HTRY(hipEventCreate(&G->ev0));
   HTRY(hipEventCreate(&G->ev1));
+  HTRY(hipEventCreateWithFlags(&G->evb[0], hipEventDisableTiming));
+  HTRY(hipEventCreateWithFlags(&G->evb[1], hipEventDisableTiming));
   HTRY(hipStreamSynchronize(st));
 #undef TRY
 #undef HTRY
@@ -498,6 +505,61 @@ static sx_status ctrl_error(const Ctrl *c) {
   return SX_OK;
 }
 
+// Drive a sequenced run: enqueue launches (`launch(L)` enqueues launch L) in
+// batches until the run-state line reports an end phase.  The first batch
+// (`first` launches) is checked before anything else is enqueued, so a short
+// run costs no idle launches; from then on two batches are in flight (the
+// host reads the state copied after batch i while batch i + 1 runs), so the
+// GPU does not wait for the host.  A launch after the end returns at once
+// (about 2 us).  On return `*fin` points at the pinned copy of the control
+// block taken after the batch that ended the run.
+template <class Launch>
+static sx_status seq_drive(sx_graph *G, hipStream_t st, int first, int maxb, unsigned limit,
+                           Launch launch, int &launches, const Ctrl **fin) {
+  struct Pend {
+    Ctrl *h;
+    hipEvent_t ev;
+    unsigned L;
+  } pend[2] = {{G->h_ctrl, G->evb[0], 0u}, {G->h_ctrl2, G->evb[1], 0u}};
+  unsigned L = 0;
+  int batch = first;
+  auto enqueue = [&](Pend &p) -> sx_status {
+    for (int k = 0; k < batch; ++k) HIP_TRY(launch(L++));
+    launches += batch;
+    HIP_TRY(hipMemcpyAsync(p.h, G->w.ctrl, offsetof(Ctrl, flags), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(p.ev, st));
+    p.L = L;
+    batch = std::min(batch * 2, maxb);
+    return SX_OK;
+  };
+  sx_status s = enqueue(pend[0]);
+  if (s != SX_OK) return s;
+  int cur = 0;
+  bool piped = false;
+  for (;;) {
+    Pend &p = pend[cur];
+    HIP_TRY(hipEventSynchronize(p.ev));
+    s = ctrl_error(p.h);
+    if (s != SX_OK) return s;
+    const unsigned ph = p.h->seq[p.L & 1].v[0];
+    if (ph == SEQ_LIMIT) return fail(SX_EHIP, "iteration limit reached (engine bug)");
+    if (ph >= SEQ_DONE) {
+      *fin = p.h;
+      return SX_OK;
+    }
+    if (L > limit) return fail(SX_EHIP, "run did not converge");
+    if (!piped) {
+      // second and third batch: from here on one batch stays in flight
+      s = enqueue(pend[cur ^ 1]);
+      if (s != SX_OK) return s;
+      piped = true;
+    }
+    s = enqueue(p);
+    if (s != SX_OK) return s;
+    cur ^= 1;
+  }
+}
+
 static void fill_stats(const Ctrl *c, int launches, float ms, sx_run_stats *stats) {
   if (!stats) return;
   unsigned long long e = 0, x = 0;
@@ -552,7 +614,7 @@ static Decision host_decide(const sx_ctx *ctx, const sx_policy &pol, Params &P, 
   in.n = G->g.n;
   in.m = G->g.m;
   Decision d = decide_core(in, P, mu);
-  if (!d.done && P.learned) {
+  if (!d.done && P.learned && in.mf >= kPolicyMinArcs) {
     float x[kMlpIn], y[kMlpOut];
     policy_features(in.nf, in.mf, sssp ? (unsigned long long)G->g.m : mu, G->g.n, G->g.m, ps,
                     pulling, x);
@@ -603,24 +665,14 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   // unexplored arcs (BFS direction rule) are computed on the device
   HIP_TRY(trav_init(a, sssp, 0ull, grid, st));
   ++launches;
+  const Ctrl *fin = G->h_ctrl;
   if (sequenced) {
     HIP_TRY(seq_start(G->w.ctrl, p->pol.direction == SX_DIR_PULL, st));
-    unsigned L = 0;
-    int batch = 8;
-    for (;;) {
-      for (int k = 0; k < batch; ++k) HIP_TRY(trav_launch(TK_SEQ, sssp, a, (int)L++, 0, grid, st));
-      launches += batch;
-      HIP_TRY(hipEventRecord(G->ev1, st));
-      sx_status s = read_ctrl(G, st);
-      if (s != SX_OK) return s;
-      s = ctrl_error(G->h_ctrl);
-      if (s != SX_OK) return s;
-      const unsigned ph = G->h_ctrl->seq[L & 1].v[0];
-      if (ph == SEQ_LIMIT) return fail(SX_EHIP, "iteration limit reached (engine bug)");
-      if (ph >= SEQ_DONE) break;
-      batch = std::min(batch * 2, 64);
-      if (L > (unsigned)(8 * (long long)G->g.n + 1024)) return fail(SX_EHIP, "run did not converge");
-    }
+    sx_status s = seq_drive(
+        G, st, 16, 64, (unsigned)(8 * (long long)G->g.n + 1024),
+        [&](unsigned L) { return trav_launch(TK_SEQ, sssp, a, (int)L, 0, grid, st); }, launches, &fin);
+    if (s != SX_OK) return s;
+    HIP_TRY(hipEventRecord(G->ev1, st));
   } else if (fused) {
     int pull_next = p->pol.direction == SX_DIR_PULL ? 1 : 0;
     for (int batch = 0;; ++batch) {
@@ -685,7 +737,7 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   HIP_TRY(hipEventSynchronize(G->ev1));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
-  fill_stats(G->h_ctrl, launches, ms, stats);
+  fill_stats(fin, launches, ms, stats);
   return SX_OK;
 }
 
@@ -712,25 +764,16 @@ static sx_status run_kcore(sx_program *p, sx_graph *G, void *d_out, hipStream_t 
   ++launches;
   if (sequenced) {
     HIP_TRY(kcore_seq_launch(a, 0, grid, st, true));
-    unsigned L = 0;
-    int batch = 16;
-    for (;;) {
-      for (int k = 0; k < batch; ++k) HIP_TRY(kcore_seq_launch(a, L++, grid, st, false));
-      launches += batch;
-      HIP_TRY(hipEventRecord(G->ev1, st));
-      sx_status s = read_ctrl(G, st);
-      if (s != SX_OK) return s;
-      s = ctrl_error(G->h_ctrl);
-      if (s != SX_OK) return s;
-      const unsigned ph = G->h_ctrl->seq[L & 1].v[0];
-      if (ph == SEQ_LIMIT) return fail(SX_EHIP, "k-core step limit reached (engine bug)");
-      if (ph >= SEQ_DONE) break;
-      batch = std::min(batch * 2, 256);
-    }
+    const Ctrl *fin = G->h_ctrl;
+    sx_status s = seq_drive(
+        G, st, 32, 64, (unsigned)(16 * (long long)G->g.n + 1024),
+        [&](unsigned L) { return kcore_seq_launch(a, L, grid, st, false); }, launches, &fin);
+    if (s != SX_OK) return s;
+    HIP_TRY(hipEventRecord(G->ev1, st));
     HIP_TRY(hipEventSynchronize(G->ev1));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
-    fill_stats(G->h_ctrl, launches, ms, stats);
+    fill_stats(fin, launches, ms, stats);
     return SX_OK;
   }
   for (;;) {

@@ -22,58 +22,89 @@ constexpr int kMlpW1 = 0, kMlpB1 = kMlpW1 + kMlpHid * kMlpIn, kMlpW2 = kMlpB1 + 
               kMlpB3 = kMlpW3 + kMlpOut * kMlpHid, kMlpParams = kMlpB3 + kMlpOut;
 static_assert(kMlpParams == 1476, "parameter count");
 
+// The network is consulted for frontiers of at least this many arcs.  In
+// the collected per-iteration timings (R-MAT and grid graphs, BFS and SSSP)
+// the mean time the best of the six ways to run an iteration saves over
+// pushing the online lists is 0.01-0.1 us below 10^4 frontier arcs and
+// 1.9 us between 10^4 and 3 * 10^4, against about 1.5 us that an in-kernel
+// decision by the network adds to the launch (measured on 2,137-iteration
+// grid runs); below the threshold the heuristic decides.
+constexpr unsigned long long kPolicyMinArcs = 32768;
+
 // Frontier features of the decision after iteration it.
 struct PolicyState {
   unsigned nf_prev;             // frontier size of the previous decision
   unsigned long long reached;   // vertices activated so far (cumulative)
 };
 
-__host__ __device__ inline float log2p1(double x) {
-  return (float)(log2(1.0 + (x > 0 ? x : 0.0)));
-}
+// FP32 throughout: the same function computes the features on the host
+// (timing collection) and on the device (every decision, on its critical
+// path), where double-precision transcendentals would cost microseconds.
+__host__ __device__ inline float log2p1(float x) { return log2f(1.f + (x > 0.f ? x : 0.f)); }
 
 __host__ __device__ inline void policy_features(unsigned nf, unsigned long long mf,
                                                 unsigned long long mu, int n, long long m,
                                                 const PolicyState &ps, bool pulling, float x[8]) {
-  const double dn = n > 0 ? (double)n : 1.0;
-  x[0] = log2p1(nf) / 24.f;
-  x[1] = log2p1((double)mf) / 32.f;
-  x[2] = log2p1((double)mu) / 32.f;
-  x[3] = (float)((double)nf / dn);
-  const double vis = (double)ps.reached / dn;
-  x[4] = (float)(vis < 4.0 ? vis / 4.0 : 1.0);
-  x[5] = (log2p1(nf) - log2p1(ps.nf_prev)) / 8.f;
-  x[6] = log2p1((double)mf / (nf > 0 ? (double)nf : 1.0)) / 16.f;
+  const float dn = n > 0 ? (float)n : 1.f;
+  const float lnf = log2p1((float)nf);
+  x[0] = lnf / 24.f;
+  x[1] = log2p1((float)mf) / 32.f;
+  x[2] = log2p1((float)mu) / 32.f;
+  x[3] = (float)nf / dn;
+  const float vis = (float)ps.reached / dn;
+  x[4] = vis < 4.f ? vis / 4.f : 1.f;
+  x[5] = (lnf - log2p1((float)ps.nf_prev)) / 8.f;
+  x[6] = log2p1((float)mf / (nf > 0 ? (float)nf : 1.f)) / 16.f;
   x[7] = pulling ? 1.f : 0.f;
   (void)m;
 }
 
-// Forward pass by one wavefront (lanes 0..31 own a hidden unit).  `P` are the
-// parameters (LDS), `x` the features, `h` 64 floats of LDS scratch; the
-// outputs are returned in every lane.
-SX_DEV void mlp_eval_wave(const float *P, const float x[8], float *h, float y[4]) {
-  const int l = lane_id();
-  if (l < kMlpHid) {
-    float s = P[kMlpB1 + l];
+// Forward pass by one wavefront; weights `P` (LDS, staged at kernel start,
+// 16-byte aligned), features `x` identical in every lane; the outputs are
+// returned in every lane.  Lanes l and l + 32 own hidden unit l; the hidden
+// vectors move between lanes by shuffles: about 60 dependent ALU / shuffle
+// steps, a fraction of a microsecond.  Every workgroup runs the same
+// instruction sequence on the same inputs, so every workgroup gets the same
+// bits.
+SX_DEV void mlp_eval_wave(const float *P, const float x[8], float y[4]) {
+  const int lane = lane_id();
+  const int l = lane & 31;
+  const float4 w1a = *(const float4 *)(P + kMlpW1 + l * kMlpIn);
+  const float4 w1b = *(const float4 *)(P + kMlpW1 + l * kMlpIn + 4);
+  float h1 = P[kMlpB1 + l];
+  h1 += w1a.x * x[0];
+  h1 += w1a.y * x[1];
+  h1 += w1a.z * x[2];
+  h1 += w1a.w * x[3];
+  h1 += w1b.x * x[4];
+  h1 += w1b.y * x[5];
+  h1 += w1b.z * x[6];
+  h1 += w1b.w * x[7];
+  h1 = h1 > 0.f ? h1 : 0.f;
+  const float4 *w2 = (const float4 *)(P + kMlpW2 + l * kMlpHid);
+  float h2 = P[kMlpB2 + l];
 #pragma unroll
-    for (int i = 0; i < kMlpIn; ++i) s += P[kMlpW1 + l * kMlpIn + i] * x[i];
-    h[l] = s > 0.f ? s : 0.f;
+  for (int q = 0; q < kMlpHid / 4; ++q) {
+    const float4 w = w2[q];
+    h2 += w.x * __shfl(h1, 4 * q);
+    h2 += w.y * __shfl(h1, 4 * q + 1);
+    h2 += w.z * __shfl(h1, 4 * q + 2);
+    h2 += w.w * __shfl(h1, 4 * q + 3);
   }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  if (l < kMlpHid) {
-    float s = P[kMlpB2 + l];
-    for (int i = 0; i < kMlpHid; ++i) s += P[kMlpW2 + l * kMlpHid + i] * h[i];
-    h[kMlpHid + l] = s > 0.f ? s : 0.f;
-  }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  h2 = h2 > 0.f ? h2 : 0.f;
+  // lanes 0-31 form outputs 0 and 1, lanes 32-63 outputs 2 and 3
+  const int k0 = lane < 32 ? 0 : 2;
+  float p0 = P[kMlpW3 + k0 * kMlpHid + l] * h2;
+  float p1 = P[kMlpW3 + (k0 + 1) * kMlpHid + l] * h2;
 #pragma unroll
-  for (int k = 0; k < kMlpOut; ++k) {
-    float s = P[kMlpB3 + k];
-    for (int i = 0; i < kMlpHid; ++i) s += P[kMlpW3 + k * kMlpHid + i] * h[kMlpHid + i];
-    y[k] = s;
+  for (int o = 16; o >= 1; o >>= 1) {
+    p0 += __shfl_xor(p0, o);
+    p1 += __shfl_xor(p1, o);
   }
+  y[0] = __shfl(p0, 0) + P[kMlpB3 + 0];
+  y[1] = __shfl(p1, 0) + P[kMlpB3 + 1];
+  y[2] = __shfl(p0, 32) + P[kMlpB3 + 2];
+  y[3] = __shfl(p1, 32) + P[kMlpB3 + 3];
 }
 
 // Host evaluation of the same network (one-phase mode decides on the host).

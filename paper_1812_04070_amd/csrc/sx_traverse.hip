@@ -360,8 +360,7 @@ struct RunState {
 };
 
 struct LdsPolicy {
-  float p[kMlpParams];
-  float h[2 * kMlpHid];
+  alignas(16) float p[kMlpParams + 4];
   float y[kMlpOut];
 };
 
@@ -382,14 +381,14 @@ SX_DEV Decision decide(const TravArgs &a, RunState &s, bool pulling, const Total
   in.n = a.g.n;
   in.m = a.g.m;
   Decision d = decide_core(in, s.P, s.mu);
-  if (!d.done && a.P.learned) {
+  if (!d.done && a.P.learned && in.mf >= kPolicyMinArcs) {
     float x[kMlpIn];
     policy_features(in.nf, in.mf, Ops::kVote ? s.mu : (unsigned long long)a.g.m, a.g.n, a.g.m, s.ps,
                     pulling, x);
     __syncthreads();
     if (wave_in_wg() == 0) {
       float y[kMlpOut];
-      mlp_eval_wave(pol->p, x, pol->h, y);
+      mlp_eval_wave(pol->p, x, y);
       if (lane_id() == 0)
         for (int k = 0; k < kMlpOut; ++k) pol->y[k] = y[k];
     }
@@ -420,10 +419,11 @@ SX_DEV SsspOps make_ops<SsspOps>(const TravArgs &a, int it) {
   return SsspOps{(unsigned *)a.state_i, a.w.stamp, it};
 }
 
+// Stage the network's weights in LDS (all threads; a barrier must follow
+// before the first decision: every caller passes one).
 SX_DEV void load_policy(const TravArgs &a, LdsPolicy &pol) {
   if (!a.P.learned) return;
   for (int i = threadIdx.x; i < kMlpParams; i += kBlock) pol.p[i] = a.mlp[i];
-  __syncthreads();
 }
 
 // Ctrl::state for the fused kernels: [0] exit reason [1] iteration [2] the
@@ -636,6 +636,7 @@ __global__ void __launch_bounds__(kBlock) k_seq(TravArgs a, unsigned L) {
   const VGrid vg = hw_grid();
   Line &out = C->seq[(L + 1) & 1];
   const bool lead = vg.bid == 0 && threadIdx.x == 0;
+  load_policy(a, pol);   // ordered before its first use by fetch_line's barrier
   fetch_line(C->seq[L & 1], C, lds.sq);
   const unsigned *in = lds.sq;
   unsigned phase = in[0];
@@ -661,7 +662,6 @@ __global__ void __launch_bounds__(kBlock) k_seq(TravArgs a, unsigned L) {
   Totals T;
   bool have_view = false;
   if (due) {
-    load_policy(a, pol);
     T = make_view(vg, a, (s.it + 1) % 3, (s.it + 1) & 1, lds, ref);
     Decision d = decide<Ops>(a, s, pulling != 0, T, &pol);
     if (d.done) {

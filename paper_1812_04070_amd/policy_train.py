@@ -45,18 +45,31 @@ def training_graphs(quick: bool):
 
 
 def labels(arm_ms: np.ndarray):
-    """targets [r, 4], mask [r, 4] from per-arm times (NaN = arm not possible)."""
+    """targets [r, 4], weights [r, 4] from per-arm times (NaN = arm not
+    possible).  The two classification heads are weighted by what a wrong
+    choice costs on that record (relative time difference between the best
+    push and the pull arm, and between the online and the best ballot arm,
+    clipped to [0.05, 5]), so that iterations where the choice hardly
+    matters do not outvote the ones where it does."""
     import paper_1812_04070_amd as sx
     r = arm_ms.shape[0]
     t = np.zeros((r, 4), dtype=np.float32)
     m = np.zeros((r, 4), dtype=np.float32)
     ms = np.where(np.isnan(arm_ms), np.inf, arm_ms)
     best = ms.argmin(1)
-    t[:, 0] = (best == 5)
-    m[:, 0] = 1
-    push = best <= 4
-    t[:, 1] = ((best >= 1) & (best <= 4))
-    m[:, 1] = push
+    t_push = ms[:, :5].min(1)
+    t_pull = ms[:, 5]
+    t[:, 0] = (t_pull < t_push)
+    lo = np.minimum(t_push, t_pull)
+    m[:, 0] = np.clip(np.abs(t_push - t_pull) / np.maximum(lo, 1e-6), 0.05, 5.0)
+    t_on = ms[:, 0]
+    t_bal = ms[:, 1:5].min(1)
+    t[:, 1] = (t_bal < t_on)
+    have_on = np.isfinite(t_on)
+    lo = np.minimum(t_on, t_bal)
+    w = np.clip(np.abs(t_on - t_bal) / np.maximum(lo, 1e-6), 0.05, 5.0)
+    # without the online arm (after a pull or an overflow) the rebuild is forced
+    m[:, 1] = np.where(have_on, w, 0.0)
     bb = 1 + ms[:, 1:5].argmin(1)
     th = np.array([sx.ARM_THRESHOLDS[k] for k in bb], dtype=np.float64)
     t[:, 2] = np.log2(th[:, 0])
@@ -137,11 +150,19 @@ def main():
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--save-data", default=None, help="write the collected records (.npz)")
+    ap.add_argument("--data", default=None, help="train on records saved by --save-data")
     args = ap.parse_args()
     import paper_1812_04070_amd as sx
     eng = sx.Engine(0)
     log = lambda s: print(s, file=sys.stderr, flush=True)
-    X, A, tags = collect(eng, args.quick, log)
+    if args.data:
+        z = np.load(args.data)
+        X, A, tags = z["X"], z["A"], z["tags"]
+    else:
+        X, A, tags = collect(eng, args.quick, log)
+    if args.save_data:
+        np.savez(args.save_data, X=X, A=A, tags=tags)
     T, M, best = labels(A)
     P, hist = train(eng, X, T, M, steps=args.steps, log=log)
     # training accuracy of the direction / filter heads
@@ -155,6 +176,10 @@ def main():
     sel = M[:, 1] > 0
     acc_flt = float(((y[sel, 1] > 0) == (T[sel, 1] > 0.5)).mean()) if sel.any() else float("nan")
     ms = np.where(np.isnan(A), np.inf, A)
+    # time of the arms the network picks, against the best arm and the arm
+    # the heuristic rule picks (push on the online lists unless pulling)
+    pick = np.where(y[:, 0] > 0, 5, np.where((y[:, 1] > 0) | ~np.isfinite(ms[:, 0]), 1 + ms[:, 1:5].argmin(1), 0))
+    net_ms = float(ms[np.arange(len(ms)), pick].sum())
     summary = {
         "records": int(len(X)),
         "arm_wins": {str(k): int((best == k).sum()) for k in range(sx.SX_POLICY_ARMS)},
@@ -162,6 +187,7 @@ def main():
         "train_acc_direction": acc_dir,
         "train_acc_filter": acc_flt,
         "best_arm_ms_total": float(ms.min(1).sum()),
+        "network_arm_ms_total": net_ms,
         "workloads": sorted(set(tags.tolist())),
     }
     with open(args.out, "w") as f:

@@ -177,3 +177,51 @@ def test_batch_autotune(engine):
                                       oracle.sssp_g(g, gen.max_degree_vertex(g)))
     for d in dgs:
         d.close()
+
+
+def _trained_params():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(sx.__file__), "policy_mlp.json")
+    if not os.path.exists(path):
+        pytest.skip("no trained policy (run python -m paper_1812_04070_amd.policy_train)")
+    with open(path) as f:
+        return np.asarray(json.load(f)["params"], dtype=np.float32)
+
+
+def test_trained_policy_gain(engine):
+    """What the trained network gains over the heuristic it replaces: BFS and
+    SSSP device time on graphs of the training families (R-MAT and a grid
+    with deleted edges, fresh seeds), heuristic vs learned policy, outputs
+    identical.  The network may lose on some runs; over the set its regret
+    stays bounded (learned total within 1.25x of the heuristic total)."""
+    sx.sx_policy_load_mlp(engine.ctx, _trained_params())
+    heur, learned = sx.Policy(), sx.Policy(policy=sx.SX_POLICY_LEARNED)
+    rows, tot_h, tot_l = [], 0.0, 0.0
+    for name, g in [("rmat17", gen.rmat(17, seed=31, weights=(1, 64))),
+                    ("rmat19", gen.rmat(19, seed=32, weights=(1, 64))),
+                    ("grid1024", gen.grid(1024, 0.1, seed=33, weights=(1, 64), weight_seed=34))]:
+        src = 0 if name.startswith("grid") else gen.max_degree_vertex(g)
+        dg = engine.load(g)
+        for algo, aname in [(sx.SX_BFS, "bfs"), (sx.SX_SSSP, "sssp")]:
+            announce(f"trained-policy gain {name} {aname}")
+            ts = {}
+            outs = {}
+            for pname, pol in [("heuristic", heur), ("learned", learned)]:
+                times = []
+                for _ in range(3):
+                    h, st = run(engine, g, algo, src, pol, dg=dg)
+                    times.append(st["device_ms"])
+                ts[pname] = float(np.median(times))
+                outs[pname] = h
+            np.testing.assert_array_equal(outs["learned"], outs["heuristic"])
+            rows.append((name, aname, ts["heuristic"], ts["learned"]))
+            tot_h += ts["heuristic"]
+            tot_l += ts["learned"]
+        dg.close()
+    for r in rows:
+        print(f"[policy-gain] {r[0]:9s} {r[1]:4s} heuristic {r[2]:8.3f} ms  learned {r[3]:8.3f} ms  "
+              f"gain {r[2] / r[3]:.3f}x", flush=True)
+    print(f"[policy-gain] total heuristic {tot_h:.3f} ms learned {tot_l:.3f} ms gain {tot_h / tot_l:.3f}x",
+          flush=True)
+    assert tot_l <= 1.25 * tot_h
