@@ -43,8 +43,10 @@ namespace sx {
 // vertices that a level deletes lead to a few hubs, and device-scope atomics
 // on one address are serialised (~11 ns each).  Summing is exact: the
 // activation test needs only the value before and after each atomic.
-constexpr int kHot = 256;          // table entries (power of two)
+constexpr int kHot = 4096;         // table entries (power of two, 32 KB of LDS)
+constexpr int kHotProbes = 8;
 constexpr int kHotDeg = 64;        // current degree from which a target is summed
+constexpr unsigned long long kHotMinArcs = 65536;  // steps below this push directly
 constexpr float kPullAlpha = 16.f; // pull when frontier arcs > alive arcs / alpha
 
 struct LdsK {
@@ -178,10 +180,13 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
   const Work &w = a.w;
   const DevGraph &g = a.g;
   const unsigned cs = T.cnt[BIN_SMALL], cm = T.cnt[BIN_MED], cl = T.cnt[BIN_LARGE];
-  for (int i = threadIdx.x; i < kHot; i += kBlock) {
-    lds.hkey[i] = -1;
-    lds.hcnt[i] = 0;
-  }
+  // the table pays for its set-up and flush only in large steps
+  const bool hot = T.mf >= kHotMinArcs;
+  if (hot)
+    for (int i = threadIdx.x; i < kHot; i += kBlock) {
+      lds.hkey[i] = -1;
+      lds.hcnt[i] = 0;
+    }
   const Regions NR = regions(w, (j + 1) & 1, vg.nb);
   bins_begin(lds.bins, NR, a.P.online_cap);   // its barrier also covers the table
   WaveStats st;
@@ -189,9 +194,8 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
   int *deg = w.deg;
   // one decrement of u into the table; false when its probe sequence is full
   auto hot_add = [&](int u) {
-    const unsigned h = ((unsigned)u * 2654435761u) >> 24;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    const unsigned h = ((unsigned)u * 2654435761u) >> 20;
+    for (int p = 0; p < kHotProbes; ++p) {
       const unsigned s = (h + (unsigned)p) & (kHot - 1);
       const int prev = atomicCAS(&lds.hkey[s], -1, u);
       if (prev == -1 || prev == u) {
@@ -208,7 +212,7 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
     if (ok) {
       ++edges;
       const int d = deg[u];   // a stale (higher) value only costs an atomic
-      if (d > k && !(d >= kHotDeg && hot_add(u))) {
+      if (d > k && !(hot && d >= kHotDeg && hot_add(u))) {
         const int old = atomic_sub_i32(&deg[u], 1);
         if (old == k + 1) {
           act = true;
@@ -232,9 +236,9 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
   // apply the summed decrements: u is activated by the atomic whose range
   // (old - c, old] holds k, i.e. old > k >= old - c
   __syncthreads();
-  if (wave_in_wg() < kHot / 64) {
-    const int u = lds.hkey[threadIdx.x];
-    const int c = lds.hcnt[threadIdx.x];
+  for (int t0 = 0; hot && t0 < kHot; t0 += kBlock) {
+    const int u = lds.hkey[t0 + threadIdx.x];
+    const int c = lds.hcnt[t0 + threadIdx.x];
     bool act = false;
     int du = 0;
     if (u >= 0 && c > 0 && (unsigned)u < (unsigned)g.n) {
