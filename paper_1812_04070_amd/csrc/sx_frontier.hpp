@@ -467,25 +467,20 @@ SX_DEV void ballot_fill(const VGrid &vg, int count, Pred pred, Deg degree, Verte
 // prefix sum of their degrees in LDS, then walks the concatenated arcs 64 at
 // a time (one arc per lane), so lanes stay busy however degrees vary.
 template <class Acc, class Op>
-SX_DEV void visit_med(int n, Acc item, unsigned cnt, const int *off, const int *idx, Op &op,
-                      unsigned gw, unsigned nwaves);
-
-template <class Acc, class Op>
 SX_DEV void visit_small(int n, Acc item, unsigned cnt, const int *off, const int *idx, Op &op,
                         unsigned gw, unsigned nwaves, int *lds /* 3*64 per wave */) {
-  // a short list would leave most wavefronts idle while a few walk 64 rows
-  // each: give every vertex a wavefront of its own instead (its row is
-  // shorter than 64 arcs, so one round)
-  if (cnt <= nwaves / 4) {
-    visit_med(n, item, cnt, off, idx, op, gw, nwaves);
-    return;
-  }
+  // Group size: enough vertices per wavefront task that every wavefront of
+  // the grid gets about one task, at most 64.  A fixed 64 would leave most
+  // wavefronts idle on lists of tens of thousands of vertices while a few
+  // walk 64 rows each, round after round.
+  const unsigned per = (cnt + nwaves - 1) / (nwaves ? nwaves : 1);
+  const int gs = per < 1 ? 1 : (per > 64 ? 64 : (int)per);
   const int lane = lane_id();
   int *l_v = lds, *l_beg = lds + 64, *l_ex = lds + 128;
-  for (unsigned c = gw; c * 64u < cnt; c += nwaves) {
-    const unsigned i = c * 64u + lane;
+  for (unsigned c = gw; c * (unsigned)gs < cnt; c += nwaves) {
+    const unsigned i = c * (unsigned)gs + lane;
     int v = -1, beg = 0, deg = 0;
-    if (i < cnt) {
+    if (lane < gs && i < cnt) {
       const int x = item(i);
       if ((unsigned)x < (unsigned)n) {
         v = x;
@@ -504,7 +499,7 @@ SX_DEV void visit_small(int n, Acc item, unsigned cnt, const int *off, const int
       const bool ok = e < total;
       int owner = 0;
       if (ok) {
-        int lo = 0, hi = 63;
+        int lo = 0, hi = gs - 1;
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
           if (l_ex[mid] <= e) lo = mid;

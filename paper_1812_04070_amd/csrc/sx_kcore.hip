@@ -52,6 +52,8 @@ constexpr float kPullAlpha = 16.f; // pull when frontier arcs > alive arcs / alp
 struct LdsK {
   int hkey[kHot];
   int hcnt[kHot];
+  unsigned short hlist[kHot];      // slots in use, in order of first use
+  unsigned hn;
   int small[kWaves][192];
   LdsBins bins, bins2;
   LdsView view;
@@ -182,11 +184,13 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
   const unsigned cs = T.cnt[BIN_SMALL], cm = T.cnt[BIN_MED], cl = T.cnt[BIN_LARGE];
   // the table pays for its set-up and flush only in large steps
   const bool hot = T.mf >= kHotMinArcs;
-  if (hot)
+  if (hot) {
     for (int i = threadIdx.x; i < kHot; i += kBlock) {
       lds.hkey[i] = -1;
       lds.hcnt[i] = 0;
     }
+    if (threadIdx.x == 0) lds.hn = 0;
+  }
   const Regions NR = regions(w, (j + 1) & 1, vg.nb);
   bins_begin(lds.bins, NR, a.P.online_cap);   // its barrier also covers the table
   WaveStats st;
@@ -200,6 +204,7 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
       const int prev = atomicCAS(&lds.hkey[s], -1, u);
       if (prev == -1 || prev == u) {
         atomicAdd(&lds.hcnt[s], 1);
+        if (prev == -1) lds.hlist[atomicAdd(&lds.hn, 1u)] = (unsigned short)s;
         return true;
       }
     }
@@ -236,9 +241,12 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
   // apply the summed decrements: u is activated by the atomic whose range
   // (old - c, old] holds k, i.e. old > k >= old - c
   __syncthreads();
-  for (int t0 = 0; hot && t0 < kHot; t0 += kBlock) {
-    const int u = lds.hkey[t0 + threadIdx.x];
-    const int c = lds.hcnt[t0 + threadIdx.x];
+  const unsigned used = hot ? lds.hn : 0u;
+  for (unsigned t0 = 0; t0 < used; t0 += kBlock) {
+    const unsigned t = t0 + threadIdx.x;
+    const int slot = t < used ? (int)lds.hlist[t] : 0;
+    const int u = t < used ? lds.hkey[slot] : -1;
+    const int c = t < used ? lds.hcnt[slot] : 0;
     bool act = false;
     int du = 0;
     if (u >= 0 && c > 0 && (unsigned)u < (unsigned)g.n) {
