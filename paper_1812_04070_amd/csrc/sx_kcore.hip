@@ -47,6 +47,16 @@ constexpr int kHot = 4096;         // table entries (power of two, 32 KB of LDS)
 constexpr int kHotProbes = 8;
 constexpr int kHotDeg = 64;        // current degree from which a target is summed
 constexpr unsigned long long kHotMinArcs = 65536;  // steps below this push directly
+// Local cascades: a vertex that a push step activates is deleted by the same
+// workgroup within the same step when its degree is below kLocalDeg and the
+// workgroup's LDS queue (kLocalQ entries) has room; only the others wait for
+// the next step.  The deletions of one level form chains (a deletion takes a
+// neighbour to k, which is deleted next, ...); on R-MAT s22 a level needs ~3
+// grid-wide steps without this, most of them with a handful of vertices and
+// each paying a launch and a record prefix.  Every vertex is still deleted
+// exactly once (by the update that activated it), so the result is the same.
+constexpr int kLocalDeg = 256;
+constexpr int kLocalQ = 2048;
 constexpr float kPullAlpha = 16.f; // pull when frontier arcs > alive arcs / alpha
 
 struct LdsK {
@@ -54,6 +64,8 @@ struct LdsK {
   int hcnt[kHot];
   unsigned short hlist[kHot];      // slots in use, in order of first use
   unsigned hn;
+  int lq[kLocalQ];                 // local cascade queue
+  unsigned lq_head, lq_tail;
   int small[kWaves][192];
   LdsBins bins, bins2;
   LdsView view;
@@ -191,6 +203,10 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
     }
     if (threadIdx.x == 0) lds.hn = 0;
   }
+  if (threadIdx.x == 0) {
+    lds.lq_head = 0;
+    lds.lq_tail = 0;
+  }
   const Regions NR = regions(w, (j + 1) & 1, vg.nb);
   bins_begin(lds.bins, NR, a.P.online_cap);   // its barrier also covers the table
   WaveStats st;
@@ -210,6 +226,30 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
     }
     return false;
   };
+  // An activated vertex u (degree du): into the local queue (deleted in this
+  // step, stamp j) or the next step's list (stamp j + 1).  Called
+  // convergently by whole wavefronts.
+  auto activate = [&](bool act, int u, int du) {
+    const bool want = act && du < kLocalDeg;
+    const uint64_t mk = ballot(want);
+    bool local = false;
+    if (mk) {
+      const int leader = __ffsll((long long)mk) - 1;
+      unsigned base = 0;
+      if (lane_id() == leader) base = atomicAdd(&lds.lq_tail, (unsigned)__popcll(mk));
+      base = __shfl(base, leader);
+      if (want) {
+        const unsigned pos = base + lane_prefix(mk);
+        if (pos < (unsigned)kLocalQ) {
+          lds.lq[pos] = u;
+          local = true;
+        }
+      }
+    }
+    if (act) mark_deleted(a, u, k, local ? j : j + 1);
+    bins_append(act && !local, u, du, NR, vg.bid, a.P, a.P.chunk, lds.bins, st);
+  };
+  bool use_hot = hot;
   auto op = [&](int v, int u, int arc, bool ok) {
     (void)v; (void)arc;
     bool act = false;
@@ -217,16 +257,15 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
     if (ok) {
       ++edges;
       const int d = deg[u];   // a stale (higher) value only costs an atomic
-      if (d > k && !(hot && d >= kHotDeg && hot_add(u))) {
+      if (d > k && !(use_hot && d >= kHotDeg && hot_add(u))) {
         const int old = atomic_sub_i32(&deg[u], 1);
         if (old == k + 1) {
           act = true;
           du = total_degree(g, u);
-          mark_deleted(a, u, k, j + 1);
         }
       }
     }
-    bins_append(act, u, du, NR, vg.bid, a.P, a.P.chunk, lds.bins, st);
+    activate(act, u, du);
   };
   const unsigned gw = vg.bid * kWaves + wave_in_wg();
   const unsigned nw = vg.nb * kWaves;
@@ -254,13 +293,33 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
       if (old > k && old - c <= k) {
         act = true;
         du = total_degree(g, u);
-        mark_deleted(a, u, k, j + 1);
       }
     }
-    bins_append(act, u, du, NR, vg.bid, a.P, a.P.chunk, lds.bins, st);
+    activate(act, u, du);
+  }
+  // drain the local queue: batches [head, tail) until no deletion adds more
+  // (the summing table is not used here: it was flushed above)
+  use_hot = false;
+  unsigned long long local_done = 0;
+  for (;;) {
+    __syncthreads();
+    const unsigned h = lds.lq_head;
+    const unsigned t = lds.lq_tail < (unsigned)kLocalQ ? lds.lq_tail : (unsigned)kLocalQ;
+    __syncthreads();
+    if (h >= t) break;
+    for (int pass = 0; pass < (g.directed ? 2 : 1); ++pass) {
+      const int *off = pass ? g.in_off : g.off;
+      const int *idx = pass ? g.in_idx : g.idx;
+      visit_small(g.n, [&](unsigned i) { return lds.lq[h + i]; }, t - h, off, idx, op,
+                  (unsigned)wave_in_wg(), (unsigned)kWaves, lds.small[wave_in_wg()]);
+    }
+    local_done += t - h;
+    if (threadIdx.x == 0) lds.lq_head = t;
   }
   bins_end(lds.bins, st, w.rec + ((j + 1) % 3), vg.bid);
-  add_stats(w.ctrl, vg.bid, edges, vg.bid == 0 ? (unsigned long long)cs + cm + cl : 0ull, lds.red);
+  add_stats(w.ctrl, vg.bid, edges,
+            (vg.bid == 0 ? (unsigned long long)cs + cm + cl : 0ull) + (threadIdx.x == 0 ? local_done : 0ull),
+            lds.red);
 }
 
 // Pull step j: every alive vertex of the alive list (view `A`) counts its
