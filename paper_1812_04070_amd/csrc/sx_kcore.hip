@@ -49,14 +49,17 @@ constexpr int kHotDeg = 64;        // current degree from which a target is summ
 constexpr unsigned long long kHotMinArcs = 65536;  // steps below this push directly
 // Local cascades: a vertex that a push step activates is deleted by the same
 // workgroup within the same step when its degree is below kLocalDeg and the
-// workgroup's LDS queue (kLocalQ entries) has room; only the others wait for
-// the next step.  The deletions of one level form chains (a deletion takes a
+// workgroup's budget (kLocalQ queued vertices, kLocalArcs arcs) has room;
+// the others wait for the next step, where the whole grid shares them (one
+// workgroup walking a dense level's cascade alone would take longer than the
+// grid-wide steps it saves).  The deletions of one level form chains (a deletion takes a
 // neighbour to k, which is deleted next, ...); on R-MAT s22 a level needs ~3
 // grid-wide steps without this, most of them with a handful of vertices and
 // each paying a launch and a record prefix.  Every vertex is still deleted
 // exactly once (by the update that activated it), so the result is the same.
 constexpr int kLocalDeg = 256;
 constexpr int kLocalQ = 2048;
+constexpr unsigned kLocalArcs = 8192;   // arcs a workgroup takes on locally per step
 constexpr float kPullAlpha = 16.f; // pull when frontier arcs > alive arcs / alpha
 
 struct LdsK {
@@ -65,7 +68,7 @@ struct LdsK {
   unsigned short hlist[kHot];      // slots in use, in order of first use
   unsigned hn;
   int lq[kLocalQ];                 // local cascade queue
-  unsigned lq_head, lq_tail;
+  unsigned lq_head, lq_tail, lq_arcs;
   int small[kWaves][192];
   LdsBins bins, bins2;
   LdsView view;
@@ -206,6 +209,7 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
   if (threadIdx.x == 0) {
     lds.lq_head = 0;
     lds.lq_tail = 0;
+    lds.lq_arcs = 0;
   }
   const Regions NR = regions(w, (j + 1) & 1, vg.nb);
   bins_begin(lds.bins, NR, a.P.online_cap);   // its barrier also covers the table
@@ -234,15 +238,20 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
     const uint64_t mk = ballot(want);
     bool local = false;
     if (mk) {
-      const int leader = __ffsll((long long)mk) - 1;
-      unsigned base = 0;
-      if (lane_id() == leader) base = atomicAdd(&lds.lq_tail, (unsigned)__popcll(mk));
-      base = __shfl(base, leader);
+      const int incl = wave_incl_scan(want ? du : 0);
+      unsigned base = 0, abase = 0;
+      if (lane_id() == 63) {
+        base = atomicAdd(&lds.lq_tail, (unsigned)__popcll(mk));
+        abase = atomicAdd(&lds.lq_arcs, (unsigned)incl);
+      }
+      base = __shfl(base, 63);
+      abase = __shfl(abase, 63);
       if (want) {
         const unsigned pos = base + lane_prefix(mk);
         if (pos < (unsigned)kLocalQ) {
-          lds.lq[pos] = u;
-          local = true;
+          // a reserved slot is always written: -1 (skipped) when over budget
+          local = abase + (unsigned)incl <= kLocalArcs;
+          lds.lq[pos] = local ? u : -1;
         }
       }
     }
@@ -563,7 +572,8 @@ __global__ void __launch_bounds__(kBlock) k_kcore_fused(KArgs a) {
 // decision taken at the start of the launch after it; launch L reads
 // Ctrl::seq[L & 1] and writes seq[(L+1) & 1]: [0] phase [1] k [2] scans [3]
 // peel steps [4] decision due (1 after a scan, 2 after a peel) [5] the list
-// of the next peel comes from a scan [6,7] alive arcs.
+// of the next peel comes from a scan [6,7] alive arcs [30] L + 1 when
+// launch L (a peel) appended to the next list.
 enum : unsigned { KP_SCAN = 0, KP_PEEL = 1, KP_DONE = 6, KP_ERROR = 7, KP_LIMIT = 8 };
 
 __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
@@ -613,6 +623,12 @@ __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
     if (r < 0) { save(KP_DONE); return; }
     if (r == 0) phase = KP_SCAN;
     else { phase = KP_PEEL; q.from_scan = true; pull = pull_step(q, V, a.P); }
+  } else if (due == 2 && lds.sq[30] != L) {
+    // the peel appended nothing (no workgroup stamped the line): next level
+    q.from_scan = false;
+    due = 0;
+    ++q.k;
+    phase = KP_SCAN;
   } else if (due == 2) {
     V = kview(vg, a.w, q.j % 3, regions(a.w, q.j & 1, vg.nb), lds, ref);
     have = true;
@@ -630,6 +646,11 @@ __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
   } else {
     kpeel(vg, a, q, pull, have, V, ref, lds);
     if (lead) atomic_add_u32(&C->stats.v[6], 1u);
+    // a workgroup that appended to the next list stamps the line the next
+    // launch reads with L + 1 (unique per launch, so nothing is cleared; a
+    // stale match only costs the record prefix the decision builds anyway)
+    if (threadIdx.x == 0 && (lds.bins.cnt[0] | lds.bins.cnt[1] | lds.bins.cnt[2] | lds.bins.ovf))
+      store_relaxed(&out.v[30], L + 1);
     ++q.j;
     due = 2;
     save(KP_PEEL);
