@@ -40,7 +40,51 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--fused", type=int, default=0, help="0 auto, 1 fused, 2 unfused, 3 sequenced")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched / learned-policy leg")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB ten times (scales the HBM "
+                         "byte counters of a profiler run) and exit")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kcore_seq_rmat22_hbm_traffic.json")
+KERNEL_SOURCES = ["sx_kcore.hip", "sx_frontier.hpp", "sx_device.hpp", "sx_types.hpp"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1812_04070_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kname: str):
+    """HBM bytes per launch of `kname` from the committed profiler counters
+    (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by the same counters of a
+    plain copy), or None when they were taken on other kernel sources or
+    another kernel."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("kernel") != kname or t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_calib(mib: int):
+    import torch
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 10}))
 
 
 def algo_bytes(kind: str, st: dict, n: int, reached: int) -> float:
@@ -177,6 +221,9 @@ def main():
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the engine has no multi-GPU "
               "path; the sharding design is described but not built.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calib:
+        copy_calib(args.copy_calib)
+        return
     import torch
     import paper_1812_04070_amd as sx
     from paper_1812_04070_amd import gen
@@ -269,7 +316,7 @@ def main():
                          "vertex_expansions": last[k]["vertex_expansions"]} for k in per},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "launches": phase_launches,
+                     "traffic": measured_traffic(kname), "launches": phase_launches,
                      "avg_launch_us": round(avg_launch_us, 3),
                      "algorithmic_bytes_per_launch": round(nbytes / phase_launches, 1)},
     }

@@ -75,6 +75,13 @@ SX_DEV bool atomic_cas_i32(int *p, int expected, int desired) {
   return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, SX_AG);
 }
+// compare-and-swap returning the value found (== expected when it swapped),
+// so that several can be in flight before the first result is looked at
+SX_DEV int atomic_cas_old_i32(int *p, int expected, int desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       SX_AG);
+  return expected;
+}
 SX_DEV int atomic_exch_i32(int *p, int v) {
   return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, SX_AG);
 }

@@ -458,14 +458,20 @@ SX_DEV void ballot_fill(const VGrid &vg, int count, Pred pred, Deg degree, Verte
 }
 
 // ------------------------------------------------- worklist traversal ---
-// Visit every arc of every worklist entry.  `op(v, u, arc, lane_valid)` is
-// called convergently by whole wavefronts; it performs Compute + Combine for
-// arc v->u and the online append itself.  Entries outside [0, n) are
-// skipped (a defence: lists only ever hold vertex ids).
+// Visit every arc of every worklist entry.  `op(v, u, arc, ok)` receives
+// kIlp arcs per lane (arrays of kIlp: source, target, arc index, lane
+// valid), is called convergently by whole wavefronts, and performs Compute +
+// Combine for those arcs and the online appends itself.  Handing a lane
+// several independent arcs at once lets an op issue all their loads, then
+// all their atomics, before waiting for any: the chain target id -> target
+// state -> atomic costs its latency once per kIlp arcs instead of once per
+// arc.  Entries outside [0, n) are skipped (a defence: lists only ever hold
+// vertex ids).
+constexpr int kIlp = 4;
 
-// Small bin: a wavefront takes 64 vertices, stages their row starts and a
-// prefix sum of their degrees in LDS, then walks the concatenated arcs 64 at
-// a time (one arc per lane), so lanes stay busy however degrees vary.
+// Small bin: a wavefront takes up to 64 vertices, stages their row starts
+// and a prefix sum of their degrees in LDS, then walks the concatenated arcs
+// 64 * kIlp at a time, so lanes stay busy however degrees vary.
 template <class Acc, class Op>
 SX_DEV void visit_small(int n, Acc item, unsigned cnt, const int *off, const int *idx, Op &op,
                         unsigned gw, unsigned nwaves, int *lds /* 3*64 per wave */) {
@@ -494,29 +500,35 @@ SX_DEV void visit_small(int n, Acc item, unsigned cnt, const int *off, const int
     l_beg[lane] = beg;
     l_ex[lane] = incl - deg;
     __builtin_amdgcn_wave_barrier();
-    for (int j = 0; j < total; j += 64) {
-      const int e = j + lane;
-      const bool ok = e < total;
-      int owner = 0;
-      if (ok) {
-        int lo = 0, hi = gs - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (l_ex[mid] <= e) lo = mid;
-          else hi = mid - 1;
+    for (int j = 0; j < total; j += 64 * kIlp) {
+      int vv[kIlp], u[kIlp], arc[kIlp];
+      bool ok[kIlp];
+#pragma unroll
+      for (int r = 0; r < kIlp; ++r) {
+        const int e = j + r * 64 + lane;
+        ok[r] = e < total;
+        int owner = 0;
+        if (ok[r]) {
+          int lo = 0, hi = gs - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (l_ex[mid] <= e) lo = mid;
+            else hi = mid - 1;
+          }
+          owner = lo;
         }
-        owner = lo;
+        arc[r] = ok[r] ? l_beg[owner] + (e - l_ex[owner]) : 0;
+        vv[r] = ok[r] ? l_v[owner] : 0;
       }
-      const int arc = ok ? l_beg[owner] + (e - l_ex[owner]) : 0;
-      const int vv = ok ? l_v[owner] : 0;
-      const int u = ok ? idx[arc] : 0;
+#pragma unroll
+      for (int r = 0; r < kIlp; ++r) u[r] = ok[r] ? idx[arc[r]] : 0;
       op(vv, u, arc, ok);
     }
     __builtin_amdgcn_wave_barrier();
   }
 }
 
-// Medium bin: one wavefront per vertex.
+// Medium bin: one wavefront per vertex, 64 * kIlp arcs per step.
 template <class Acc, class Op>
 SX_DEV void visit_med(int n, Acc item, unsigned cnt, const int *off, const int *idx, Op &op,
                       unsigned gw, unsigned nwaves) {
@@ -525,16 +537,23 @@ SX_DEV void visit_med(int n, Acc item, unsigned cnt, const int *off, const int *
     const int v = item(i);
     if ((unsigned)v >= (unsigned)n) continue;
     const int beg = off[v], end = off[v + 1];
-    for (int a = beg; a < end; a += 64) {
-      const int arc = a + lane;
-      const bool ok = arc < end;
-      const int u = ok ? idx[arc] : 0;
-      op(v, u, arc, ok);
+    for (int a = beg; a < end; a += 64 * kIlp) {
+      int vv[kIlp], u[kIlp], arc[kIlp];
+      bool ok[kIlp];
+#pragma unroll
+      for (int r = 0; r < kIlp; ++r) {
+        arc[r] = a + r * 64 + lane;
+        ok[r] = arc[r] < end;
+        vv[r] = v;
+        u[r] = ok[r] ? idx[arc[r]] : 0;
+      }
+      op(vv, u, arc, ok);
     }
   }
 }
 
-// Large bin: one workgroup per item (a chunk of `chunk` arcs of one vertex).
+// Large bin: one workgroup per item (a chunk of `chunk` arcs of one vertex),
+// kBlock * kIlp arcs per step.
 template <class Acc, class Op>
 SX_DEV void visit_large(const VGrid &vg, int n, Acc item, unsigned cnt, const int *off,
                         const int *idx, int chunk, Op &op) {
@@ -547,11 +566,17 @@ SX_DEV void visit_large(const VGrid &vg, int n, Acc item, unsigned cnt, const in
     const long long b0 = (long long)vb + (long long)c * chunk;
     const int beg = (int)(b0 < ve ? b0 : ve);
     const int end = (int)((b0 + chunk) < ve ? (b0 + chunk) : ve);
-    for (int a = beg; a < end; a += kBlock) {
-      const int arc = a + (int)threadIdx.x;
-      const bool ok = arc < end;
-      const int u = ok ? idx[arc] : 0;
-      op(v, u, arc, ok);
+    for (int a = beg; a < end; a += kBlock * kIlp) {
+      int vv[kIlp], u[kIlp], arc[kIlp];
+      bool ok[kIlp];
+#pragma unroll
+      for (int r = 0; r < kIlp; ++r) {
+        arc[r] = a + r * kBlock + (int)threadIdx.x;
+        ok[r] = arc[r] < end;
+        vv[r] = v;
+        u[r] = ok[r] ? idx[arc[r]] : 0;
+      }
+      op(vv, u, arc, ok);
     }
   }
 }

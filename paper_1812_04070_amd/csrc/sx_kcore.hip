@@ -259,22 +259,28 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
     bins_append(act && !local, u, du, NR, vg.bid, a.P, a.P.chunk, lds.bins, st);
   };
   bool use_hot = hot;
-  auto op = [&](int v, int u, int arc, bool ok) {
+  // kIlp arcs per lane: all degree loads, then all decrements, then the
+  // degrees of the activated targets, each stage with every arc in flight
+  auto op = [&](const int *v, const int *u, const int *arc, const bool *ok) {
     (void)v; (void)arc;
-    bool act = false;
-    int du = 0;
-    if (ok) {
-      ++edges;
-      const int d = deg[u];   // a stale (higher) value only costs an atomic
-      if (d > k && !(use_hot && d >= kHotDeg && hot_add(u))) {
-        const int old = atomic_sub_i32(&deg[u], 1);
-        if (old == k + 1) {
-          act = true;
-          du = total_degree(g, u);
-        }
-      }
+    int d[kIlp], old[kIlp], du[kIlp];
+    bool dec[kIlp], act[kIlp];
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) d[r] = ok[r] ? deg[u[r]] : 0;  // stale (higher) costs an atomic
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) {
+      edges += ok[r] ? 1 : 0;
+      dec[r] = ok[r] && d[r] > k && !(use_hot && d[r] >= kHotDeg && hot_add(u[r]));
     }
-    activate(act, u, du);
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) old[r] = dec[r] ? atomic_sub_i32(&deg[u[r]], 1) : 0;
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) {
+      act[r] = dec[r] && old[r] == k + 1;
+      du[r] = act[r] ? total_degree(g, u[r]) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) activate(act[r], u[r], du[r]);
   };
   const unsigned gw = vg.bid * kWaves + wave_in_wg();
   const unsigned nw = vg.nb * kWaves;
@@ -290,21 +296,26 @@ SX_DEV void kpeel_push(const VGrid &vg, const KArgs &a, int k, int j, const View
   // (old - c, old] holds k, i.e. old > k >= old - c
   __syncthreads();
   const unsigned used = hot ? lds.hn : 0u;
-  for (unsigned t0 = 0; t0 < used; t0 += kBlock) {
-    const unsigned t = t0 + threadIdx.x;
-    const int slot = t < used ? (int)lds.hlist[t] : 0;
-    const int u = t < used ? lds.hkey[slot] : -1;
-    const int c = t < used ? lds.hcnt[slot] : 0;
-    bool act = false;
-    int du = 0;
-    if (u >= 0 && c > 0 && (unsigned)u < (unsigned)g.n) {
-      const int old = atomic_sub_i32(&deg[u], c);
-      if (old > k && old - c <= k) {
-        act = true;
-        du = total_degree(g, u);
-      }
+  for (unsigned t0 = 0; t0 < used; t0 += kBlock * kIlp) {
+    int u[kIlp], c[kIlp], old[kIlp], du[kIlp];
+    bool act[kIlp];
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) {
+      const unsigned t = t0 + r * kBlock + threadIdx.x;
+      const int slot = t < used ? (int)lds.hlist[t] : 0;
+      u[r] = t < used ? lds.hkey[slot] : -1;
+      c[r] = t < used ? lds.hcnt[slot] : 0;
+      if (!(u[r] >= 0 && c[r] > 0 && (unsigned)u[r] < (unsigned)g.n)) c[r] = 0;
     }
-    activate(act, u, du);
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) old[r] = c[r] ? atomic_sub_i32(&deg[u[r]], c[r]) : 0;
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) {
+      act[r] = c[r] && old[r] > k && old[r] - c[r] <= k;
+      du[r] = act[r] ? total_degree(g, u[r]) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) activate(act[r], u[r], du[r]);
   }
   // drain the local queue: batches [head, tail) until no deletion adds more
   // (the summing table is not used here: it was flushed above)

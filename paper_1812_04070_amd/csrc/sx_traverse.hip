@@ -42,10 +42,19 @@ struct BfsOps {
   static constexpr bool kVote = true;
   int *depth;
   int it;
-  // push Compute + Combine for arc v->u; true when u becomes active
-  SX_DEV bool push(int v, int u, int arc, const DevGraph &g, unsigned &err) const {
+  // push Compute + Combine for kIlp arcs v->u per lane; act[r]: u becomes
+  // active.  All depth loads, then all claims, are in flight together.
+  SX_DEV void push(const int *v, const int *u, const int *arc, const bool *ok, const DevGraph &g,
+                   unsigned &err, bool *act) const {
     (void)v; (void)arc; (void)g; (void)err;
-    return depth[u] == -1 && atomic_cas_i32(&depth[u], -1, it + 1);
+    int d[kIlp], got[kIlp];
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) d[r] = ok[r] ? depth[u[r]] : 0;
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r)
+      got[r] = ok[r] && d[r] == -1 ? atomic_cas_old_i32(&depth[u[r]], -1, it + 1) : 0;
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) act[r] = ok[r] && d[r] == -1 && got[r] == -1;
   }
   SX_DEV bool next_active(int v) const { return depth[v] == it + 1; }
   SX_DEV bool in_frontier(int v) const { return depth[v] == it; }
@@ -57,14 +66,34 @@ struct SsspOps {
   unsigned *dist;
   int *stamp;
   int it;
-  SX_DEV bool push(int v, int u, int arc, const DevGraph &g, unsigned &err) const {
-    const unsigned dv = dist[v];
-    const unsigned nd = dv + g.w[arc];
-    if (nd < dv || nd == 0xFFFFFFFFu) { err = SX_ERR_OVERFLOW; return false; }
-    if (nd >= dist[u]) return false;
-    const unsigned old = atomic_min_u32(&dist[u], nd);
-    if (nd >= old) return false;
-    return atomic_exch_i32(&stamp[u], it + 1) != it + 1;
+  // relax kIlp arcs per lane: loads, then the atomic minimums, then the
+  // stamps of the improved targets, each stage with all arcs in flight
+  SX_DEV void push(const int *v, const int *u, const int *arc, const bool *ok, const DevGraph &g,
+                   unsigned &err, bool *act) const {
+    unsigned dv[kIlp], w[kIlp], du[kIlp], nd[kIlp], old[kIlp];
+    bool tr[kIlp];
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) {
+      dv[r] = ok[r] ? dist[v[r]] : 0u;
+      w[r] = ok[r] ? g.w[arc[r]] : 0u;
+      du[r] = ok[r] ? dist[u[r]] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) {
+      nd[r] = dv[r] + w[r];
+      const bool bad = nd[r] < dv[r] || nd[r] == 0xFFFFFFFFu;
+      if (ok[r] && bad) err = SX_ERR_OVERFLOW;
+      tr[r] = ok[r] && !bad && nd[r] < du[r];
+      old[r] = tr[r] ? atomic_min_u32(&dist[u[r]], nd[r]) : 0u;
+    }
+    int st[kIlp];
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) {
+      tr[r] = tr[r] && nd[r] < old[r];
+      st[r] = tr[r] ? atomic_exch_i32(&stamp[u[r]], it + 1) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) act[r] = tr[r] && st[r] != it + 1;
   }
   SX_DEV bool next_active(int v) const { return stamp[v] == it + 1; }
   SX_DEV bool in_frontier(int v) const { return stamp[v] == it; }
@@ -97,14 +126,17 @@ SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   WaveStats st;
   unsigned err = 0;
   long long edges = 0;
-  auto op = [&](int v, int u, int arc, bool ok) {
-    bool act = false;
-    int du = 0;
-    if (ok) {
-      ++edges;
-      if (ops.push(v, u, arc, g, err)) { act = true; du = degree_of(g.off, u); }
+  auto op = [&](const int *v, const int *u, const int *arc, const bool *ok) {
+    bool act[kIlp];
+    ops.push(v, u, arc, ok, g, err, act);
+    int du[kIlp];
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) {
+      edges += ok[r] ? 1 : 0;
+      du[r] = act[r] ? degree_of(g.off, u[r]) : 0;
     }
-    bins_append(act, u, du, NR, vg.bid, P, P.chunk, lds.bins, st);
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) bins_append(act[r], u[r], du[r], NR, vg.bid, P, P.chunk, lds.bins, st);
   };
   const unsigned gw = vg.bid * kWaves + wave_in_wg();
   const unsigned nw = vg.nb * kWaves;
