@@ -228,9 +228,11 @@ sx_status sx_batch_autotune(sx_ctx *ctx, const sx_query *queries, int32_t nq, co
 
 /* Library/build facts for the measurement harness: kernel register use and
  * persistent-grid sizing (the Eq. 1 analogue).  name: one of "bfs_fused",
- * "sssp_fused", "bfs_seq", "sssp_seq", "bfs_push_step", "bfs_pull_step",
- * "sssp_push_step", "sssp_pull_step", "ballot_scan", "pull_scan",
- * "kcore_fused", "kcore_seq", "pagerank_fused", "batch".
+ * "sssp_fused", "bfs_seq", "sssp_seq", "bfs_seq_wide", "sssp_seq_wide" (the
+ * sequenced kernels for graphs of 2^25 arcs or more, built for three
+ * workgroups per CU), "bfs_push_step", "bfs_pull_step", "sssp_push_step",
+ * "sssp_pull_step", "ballot_scan", "pull_scan", "kcore_fused", "kcore_seq",
+ * "pagerank_fused", "batch".
  * Errors: SX_EINVAL (unknown name), SX_EHIP. */
 typedef struct {
   int32_t vgprs, sgprs, lds_bytes, block, wgs_per_cu, grid_wgs, cus;

@@ -440,6 +440,9 @@ extern "C" sx_status sx_program_set_policy(sx_program *p, const sx_policy *pol) 
 // ---------------------------------------------------------- occupancy ---
 // Persistent grid (Section 5, Eq. 1): resident workgroups per CU for this
 // kernel x number of CUs.
+// Graphs from this many arcs up run the wide sequenced traversal kernel.
+static const long long kBigGraphArcs = 1ll << 25;
+
 static int persistent_grid(sx_ctx *ctx, const void *kernel, int requested) {
   int per = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess || per < 1)
@@ -475,7 +478,7 @@ static Params make_params(const sx_program *p, const sx_graph *G, int grid) {
   P.direction = pol.direction;
   P.alpha = 14.0f;
   P.beta = 24.0f;
-  P.alpha_w = 1.25f;
+  P.alpha_w = 0.5f;
   P.beta_w = 4.0f;
   // a BFS level or a Bellman-Ford round adds at least one vertex to the set
   // of settled ones, so n + 2 iterations bound every correct run
@@ -642,8 +645,10 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   const bool fused = p->pol.fused == SX_FUSED;
   const bool sequenced = p->pol.fused == SX_SEQUENCED || p->pol.fused == SX_FUSE_AUTO;
   int grid;
+  // large graphs take the wide sequenced kernel (three workgroups per CU)
+  const int seq_kind = G->g.m >= kBigGraphArcs ? TK_SEQ_WIDE : TK_SEQ;
   if (sequenced) {
-    grid = plain_grid(ctx, trav_kernel(TK_SEQ, sssp));
+    grid = plain_grid(ctx, trav_kernel(seq_kind, sssp));
     if (p->pol.grid_wgs > 0) grid = std::min(grid, p->pol.grid_wgs);
   } else if (fused) {
     grid = persistent_grid(ctx, trav_kernel(TK_FUSED, sssp), p->pol.grid_wgs);
@@ -670,7 +675,7 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
     HIP_TRY(seq_start(G->w.ctrl, p->pol.direction == SX_DIR_PULL, st));
     sx_status s = seq_drive(
         G, st, 16, 64, (unsigned)(8 * (long long)G->g.n + 1024),
-        [&](unsigned L) { return trav_launch(TK_SEQ, sssp, a, (int)L, 0, grid, st); }, launches, &fin);
+        [&](unsigned L) { return trav_launch(seq_kind, sssp, a, (int)L, 0, grid, st); }, launches, &fin);
     if (s != SX_OK) return s;
     HIP_TRY(hipEventRecord(G->ev1, st));
   } else if (fused) {
@@ -1211,6 +1216,8 @@ extern "C" sx_status sx_kernel_info_get(sx_ctx *ctx, const char *name, sx_kernel
       {"sssp_fused", trav_kernel(TK_FUSED, 1), true},
       {"bfs_seq", trav_kernel(TK_SEQ, 0), false},
       {"sssp_seq", trav_kernel(TK_SEQ, 1), false},
+      {"bfs_seq_wide", trav_kernel(TK_SEQ_WIDE, 0), false},
+      {"sssp_seq_wide", trav_kernel(TK_SEQ_WIDE, 1), false},
       {"bfs_push_step", trav_kernel(TK_PUSH_STEP, 0), false},
       {"bfs_pull_step", trav_kernel(TK_PULL_STEP, 0), false},
       {"sssp_push_step", trav_kernel(TK_PUSH_STEP, 1), false},

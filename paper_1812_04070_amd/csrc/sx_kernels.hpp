@@ -8,7 +8,8 @@ namespace sx {
 // traversal kernels; trav_launch's `it` is the iteration (TK_SEQ: the launch
 // number) and `arg` the direction (TK_FUSED: 1 = pull) or whether the push
 // lists come from a ballot scan (TK_PUSH_STEP)
-enum TravKernel { TK_FUSED, TK_PUSH_STEP, TK_BALLOT, TK_PULL_SCAN, TK_PULL_STEP, TK_SEQ, TK_COUNT };
+enum TravKernel { TK_FUSED, TK_PUSH_STEP, TK_BALLOT, TK_PULL_SCAN, TK_PULL_STEP, TK_SEQ, TK_SEQ_WIDE,
+                  TK_COUNT };
 
 const void *trav_kernel(int kind, int sssp);
 hipError_t trav_launch(int kind, int sssp, const TravArgs &a, int it, int arg, int grid,

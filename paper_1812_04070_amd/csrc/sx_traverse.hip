@@ -660,8 +660,14 @@ SX_DEV void seq_store(Line &l, unsigned phase, const RunState &s, unsigned pulli
   store_relaxed(&l.v[12], rebuilt);
 }
 
-template <class Ops>
-__global__ void __launch_bounds__(kBlock) k_seq(TravArgs a, unsigned L) {
+// kMinWaves = 6 (the wide form, for large graphs): at least six wavefronts
+// per SIMD (80 VGPRs, a few spilled to scratch), three workgroups per CU
+// instead of two, which the latency-bound push steps of large graphs turn
+// into throughput (R-MAT s22 SSSP 3.39 -> 3.09 ms).  The spills lengthen
+// each phase's critical path, so graphs with small frontiers and thousands
+// of iterations use kMinWaves = 1 (the compiler's own choice, no spills).
+template <class Ops, int kMinWaves>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMinWaves))) k_seq(TravArgs a, unsigned L) {
   __shared__ LdsTrav lds;
   __shared__ LdsPolicy pol;
   Ctrl *C = a.w.ctrl;
@@ -847,7 +853,9 @@ SX_DEV bool batch_query(const VGrid &vg, const TravArgs &a, GridBarrier &bar, Ld
   return bar.sync();
 }
 
-__global__ void __launch_bounds__(kBlock) k_batch(BatchArgs b) {
+// Four wavefronts per SIMD (128 VGPRs, spilling): two workgroups per CU, so
+// twice the teams run at once (256 queries over 64 graphs: 609 -> 561 ms).
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_batch(BatchArgs b) {
   __shared__ LdsTrav lds;
   __shared__ LdsPolicy pol;
   const unsigned team = blockIdx.x / (unsigned)b.team;
@@ -933,7 +941,8 @@ const void *trav_kernel(int kind, int sssp) {
     case TK_BALLOT: return sssp ? (const void *)k_ballot<SsspOps> : (const void *)k_ballot<BfsOps>;
     case TK_PULL_SCAN: return sssp ? (const void *)k_pull_scan<SsspOps> : (const void *)k_pull_scan<BfsOps>;
     case TK_PULL_STEP: return sssp ? (const void *)k_pull_step<SsspOps> : (const void *)k_pull_step<BfsOps>;
-    case TK_SEQ: return sssp ? (const void *)k_seq<SsspOps> : (const void *)k_seq<BfsOps>;
+    case TK_SEQ: return sssp ? (const void *)k_seq<SsspOps, 1> : (const void *)k_seq<BfsOps, 1>;
+    case TK_SEQ_WIDE: return sssp ? (const void *)k_seq<SsspOps, 6> : (const void *)k_seq<BfsOps, 6>;
     default: return nullptr;
   }
 }
@@ -963,8 +972,12 @@ hipError_t trav_launch(int kind, int sssp, const TravArgs &a, int it, int arg, i
       else hipLaunchKernelGGL(k_pull_step<BfsOps>, g, b, 0, s, a, it);
       break;
     case TK_SEQ:
-      if (sssp) hipLaunchKernelGGL(k_seq<SsspOps>, g, b, 0, s, a, (unsigned)it);
-      else hipLaunchKernelGGL(k_seq<BfsOps>, g, b, 0, s, a, (unsigned)it);
+      if (sssp) hipLaunchKernelGGL((k_seq<SsspOps, 1>), g, b, 0, s, a, (unsigned)it);
+      else hipLaunchKernelGGL((k_seq<BfsOps, 1>), g, b, 0, s, a, (unsigned)it);
+      break;
+    case TK_SEQ_WIDE:
+      if (sssp) hipLaunchKernelGGL((k_seq<SsspOps, 6>), g, b, 0, s, a, (unsigned)it);
+      else hipLaunchKernelGGL((k_seq<BfsOps, 6>), g, b, 0, s, a, (unsigned)it);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -180,9 +180,12 @@ struct DecideIn {
 // switching follows for BFS: push first and last, pull in between).  SSSP
 // (aggregation): pull while the frontier's arcs exceed m / alpha_w, back to
 // push below m / beta_w.  A pull iteration of SSSP reads every in-arc (no
-// early exit under a minimum), so it pays only when the frontier's arcs
-// approach m: alpha_w = 1.25 (measured on MI355X, R-MAT s22: push 66 G
-// arcs/s, pull 81 G arcs/s).  JIT filter choice: the online filter's lists
+// early exit under a minimum), so it would pay only when the frontier's arcs
+// exceed m by the ratio of the two arc rates.  With four arcs per lane in
+// flight, pushing is faster at every iteration measured on MI355X (R-MAT
+// s22: 3.09 ms pushing throughout against 3.60 ms with the one pull
+// iteration that alpha_w = 1.25 chose), so alpha_w = 0.5: a frontier's arcs
+// never exceed 2m, and pull stays available to the policy and the caller.  JIT filter choice: the online filter's lists
 // are used unless a region overflowed.
 __host__ __device__ inline Decision decide_core(const DecideIn &in, const Params &P,
                                                 unsigned long long &mu) {
