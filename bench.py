@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--fused", type=int, default=0, help="0 auto, 1 fused, 2 unfused, 3 sequenced")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched / learned-policy leg")
+    ap.add_argument("--pagerank", action="store_true",
+                    help="instead of the step: time PageRank (pull, FP32, 20 iterations) on the "
+                         "directed R-MAT scale 24 graph and print its own JSON line")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (scales the HBM "
                          "byte counters of a profiler run) and exit")
@@ -215,6 +218,66 @@ def load_trained_policy():
         return np.asarray(json.load(f)["params"], dtype=np.float32)
 
 
+def pagerank_main(args):
+    """PageRank on the directed R-MAT scale-24 graph (edge factor 16, deduped,
+    no self loops): one run = 20 pull iterations in one persistent launch.
+    Algorithmic bytes per iteration: 8 per arc (CSC neighbour id +
+    contribution) + 20 per vertex (row offsets, out-degree, rank read and
+    write, contribution write)."""
+    import torch
+    import paper_1812_04070_amd as sx
+    from paper_1812_04070_amd import gen
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    g = gen.workload_graph("rmat24d", scale_override=args.scale if args.scale != 22 else None)
+    log(f"[bench] graph rmat{args.scale if args.scale != 22 else 24}d: n={g.n} arcs={g.m} gen "
+        f"{time.perf_counter()-t0:.1f}s")
+    eng = sx.Engine(0)
+    dg = eng.load(g)
+    out = torch.empty(g.n, dtype=torch.float32, device=eng.device)
+    pol = sx.Policy()
+    for _ in range(args.warmup):
+        eng.run(dg, sx.SX_PAGERANK, -1, pol, out=out)
+    torch.cuda.synchronize()
+    dev = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = eng.run(dg, sx.SX_PAGERANK, -1, pol, out=out)
+        dev.append(st["device_ms"])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    iters = int(st["iterations"])
+    dev_ms = float(np.median(dev))
+    nbytes = (8.0 * g.m + 20.0 * g.n) * iters
+    achieved = nbytes / (dev_ms / 1e3) / 1e9
+    r = eng.to_host(dg, sx.SX_PAGERANK, out)
+    result = {
+        "metric": "PageRank pull FP32, directed R-MAT s24, 20 iterations",
+        "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "rmat24d-pagerank", "n": g.n, "arcs": g.m, "iterations": iters,
+                   "damping": 0.85},
+        "roofline": {"bound": "hbm", "kernel": "k_pr_fused", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "launches": 1, "avg_launch_us": round(1e3 * dev_ms, 1),
+                     "algorithmic_bytes_per_launch": nbytes},
+    }
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.pagerank_g(g)
+        cpu_s = time.perf_counter() - t0
+        result["rel_l1_vs_oracle"] = float(np.abs(r.astype(np.float64) - ref).sum() / np.abs(ref).sum())
+        result["cpu_baseline"] = {"value": round(1e3 * cpu_s, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+                                  "sample": "the full 20-iteration FP64 PageRank of the same graph, serial C"}
+    else:
+        result["cpu_baseline"] = None
+    dg.close()
+    eng.close()
+    print(json.dumps(result))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -223,6 +286,9 @@ def main():
         sys.exit(2)
     if args.copy_calib:
         copy_calib(args.copy_calib)
+        return
+    if args.pagerank:
+        pagerank_main(args)
         return
     import torch
     import paper_1812_04070_amd as sx

@@ -101,6 +101,30 @@ SX_DEV void pr_finish_vertex(const PrArgs &a, int v, CSum s, float D, bool last,
   if (od == 0) cadd(dang, r);
 }
 
+// s += src[ii[e]] for e = e0, e0 + stride, ... < end, in that order.  The
+// indices and contributions of kIlp consecutive terms are loaded before any
+// of them is added, so a lane has kIlp gathers in flight instead of one; the
+// additions keep their order, so the sum is the same bits.
+SX_DEV void gather(CSum &s, const float *src, const int *ii, int e0, int end, int stride,
+                   long long &edges) {
+  int e = e0;
+  for (; e + (kIlp - 1) * stride < end; e += kIlp * stride) {
+    int u[kIlp];
+    float x[kIlp];
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) u[r] = ii[e + r * stride];
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) x[r] = src[u[r]];
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) cadd(s, x[r]);
+    edges += kIlp;
+  }
+  for (; e < end; e += stride) {
+    cadd(s, src[ii[e]]);
+    ++edges;
+  }
+}
+
 SX_DEV void pr_iteration(const PrArgs &a, int t, const ViewRef &L, const Totals &T, LdsPr &lds) {
   const Work &w = a.w;
   const float *src = w.contrib[t & 1];
@@ -117,7 +141,7 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const ViewRef &L, const Totals 
     if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
-    for (int e = beg + (int)threadIdx.x; e < end; e += kBlock) { cadd(s, src[ii[e]]); ++edges; }
+    gather(s, src, ii, beg + (int)threadIdx.x, end, kBlock, edges);
     s = wg_merge(s, lds.f);
     if (threadIdx.x == 0) pr_finish_vertex(a, v, s, D, last, dst, dang);
   }
@@ -129,7 +153,7 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const ViewRef &L, const Totals 
     if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
-    for (int e = beg + lane; e < end; e += 64) { cadd(s, src[ii[e]]); ++edges; }
+    gather(s, src, ii, beg + lane, end, 64, edges);
     s = wave_merge(s);
     if (lane == 0) pr_finish_vertex(a, v, s, D, last, dst, dang);
   }
@@ -139,8 +163,7 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const ViewRef &L, const Totals 
     if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
-    for (int e = beg; e < end; ++e) cadd(s, src[ii[e]]);
-    edges += end - beg;
+    gather(s, src, ii, beg, end, 1, edges);
     pr_finish_vertex(a, v, s, D, last, dst, dang);
   }
   dang = wg_merge(dang, lds.f);
