@@ -67,7 +67,12 @@ enum {
   SX_UNDIRECTED = 1u,    /* CSR is symmetric; in_* must be NULL               */
   SX_DEVICE_PTRS = 2u,   /* pointers are device memory: borrowed, not copied;
                             the caller keeps them alive until destroy          */
-  SX_VALIDATE = 4u       /* check offsets monotone and ids in range (host)    */
+  SX_VALIDATE = 4u,      /* check offsets monotone and ids in range (host)    */
+  SX_REORDER = 8u        /* renumber vertices by decreasing degree on load
+                            (device arrays the graph owns, ~2x the CSR while
+                            building); runs take and return original ids, the
+                            mapping costs one gather per run; not for batches
+                            or policy collection (SX_EUNSUPPORTED)            */
 };
 
 typedef struct {
@@ -79,7 +84,8 @@ typedef struct {
   const int32_t *in_offsets; /* [n+1] CSC; NULL for undirected graphs          */
   const int32_t *in_indices; /* [m] in-neighbours                              */
   const uint32_t *in_weights;/* [m] or NULL                                    */
-  uint32_t flags;            /* SX_UNDIRECTED | SX_DEVICE_PTRS | SX_VALIDATE   */
+  uint32_t flags;            /* SX_UNDIRECTED | SX_DEVICE_PTRS | SX_VALIDATE |
+                                SX_REORDER                                     */
 } sx_graph_desc;
 
 /* Make the graph resident on the device (host arrays are copied; the caller

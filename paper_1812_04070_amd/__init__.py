@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libsimdx.so")
 SX_OK, SX_EINVAL, SX_ENOMEM, SX_EHIP, SX_EUNSUPPORTED, SX_EDEADLOCK, SX_EOVERFLOW, SX_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 # graph flags
-SX_UNDIRECTED, SX_DEVICE_PTRS, SX_VALIDATE = 1, 2, 4
+SX_UNDIRECTED, SX_DEVICE_PTRS, SX_VALIDATE, SX_REORDER = 1, 2, 4, 8
 # algorithms
 SX_BFS, SX_SSSP, SX_KCORE, SX_PAGERANK = 0, 1, 2, 3
 # policy enums
@@ -320,7 +320,7 @@ class DeviceGraph:
     """A host graph (paper_1812_04070_amd.gen.Graph) made resident through torch
     tensors and borrowed by the library (SX_DEVICE_PTRS)."""
 
-    def __init__(self, engine: "Engine", g, validate: bool = False):
+    def __init__(self, engine: "Engine", g, validate: bool = False, reorder: bool = False):
         import torch
         self.engine = engine
         self.n, self.m = int(g.n), int(g.m)
@@ -342,7 +342,7 @@ class DeviceGraph:
             self._t["in_weights"] = up(g.in_weights, np.int32) if g.in_weights is not None else None
         ptr = lambda k: (self._t[k].data_ptr() if self._t.get(k) is not None and self._t[k].numel() else
                          (self._t[k].data_ptr() if self._t.get(k) is not None else None))
-        flags = SX_DEVICE_PTRS | (0 if self.directed else SX_UNDIRECTED)
+        flags = SX_DEVICE_PTRS | (0 if self.directed else SX_UNDIRECTED) | (SX_REORDER if reorder else 0)
         desc = sx_graph_desc(self.n, self.m, ptr("offsets"), ptr("indices"), ptr("weights"),
                              ptr("in_offsets") if self.directed else None,
                              ptr("in_indices") if self.directed else None,
@@ -394,8 +394,10 @@ class Engine:
             self.programs[key] = sx_program_register(self.ctx, algo, pr_damping, pr_iters)
         return self.programs[key]
 
-    def load(self, g, validate: bool = False) -> DeviceGraph:
-        return DeviceGraph(self, g, validate)
+    def load(self, g, validate: bool = False, reorder: bool = False) -> DeviceGraph:
+        """Make `g` resident.  reorder: the library renumbers the vertices by
+        decreasing degree (SX_REORDER); runs still take and return original ids."""
+        return DeviceGraph(self, g, validate, reorder)
 
     def run(self, dg: DeviceGraph, algo: int, source: int = -1, policy: Optional[Policy] = None,
             out=None, pr_damping: float = 0.85, pr_iters: int = 20):

@@ -71,6 +71,12 @@ struct sx_graph {
   Ctrl *h_ctrl = nullptr;     // pinned host mirrors of the first lines of Ctrl
   Ctrl *h_ctrl2 = nullptr;    // (two: one per batch in flight)
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evb[2] = {nullptr, nullptr};
+  // degree-ordered renumbering (SX_REORDER): old id -> new id on the device
+  // and the host, and the run's state array in the new numbering
+  bool reordered = false;
+  int *d_inv = nullptr;
+  std::vector<int> h_inv;
+  void *state = nullptr;
 };
 
 struct sx_program {
@@ -373,6 +379,30 @@ extern "C" sx_status sx_graph_load(sx_ctx *ctx, const sx_graph_desc *d, void *hi
     TRY(upload(d->in_offsets, sizeof(int) * (size_t)(n + 1), (const void **)&g.in_off));
     TRY(upload(d->in_indices, sizeof(int) * (size_t)m, (const void **)&g.in_idx));
     TRY(upload(d->in_weights, sizeof(unsigned) * (size_t)m, (const void **)&g.in_w));
+  }
+  if (d->flags & SX_REORDER) {
+    // renumber by decreasing degree into arrays the graph owns; temporaries
+    // are freed once the build has finished on the stream
+    std::vector<void *> temps;
+    auto own = [&](void **p, size_t bytes) -> hipError_t {
+      return dalloc(G, p, bytes) == SX_OK ? hipSuccess : hipErrorOutOfMemory;
+    };
+    auto tmp = [&](void **p, size_t bytes) -> hipError_t {
+      hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+      if (e == hipSuccess) temps.push_back(*p);
+      return e;
+    };
+    G->h_inv.resize((size_t)n);
+    DevGraph g2;
+    const hipError_t e = reorder_build(g, own, tmp, st, g2, &G->d_inv, G->h_inv.data());
+    for (void *p : temps) (void)hipFree(p);
+    if (e != hipSuccess) {
+      free_graph(G);
+      return fail(e == hipErrorOutOfMemory ? SX_ENOMEM : SX_EHIP, "renumbering: %s", hipGetErrorString(e));
+    }
+    g = g2;
+    G->reordered = true;
+    TRY(dalloc(G, &G->state, sizeof(int) * (size_t)(n > 0 ? n : 1)));
   }
   // workspace
   Work &w = G->w;
@@ -866,6 +896,7 @@ extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_
   if (p->ap.algo != SX_BFS && p->ap.algo != SX_SSSP) return fail(SX_EINVAL, "BFS or SSSP only");
   sx_graph *G = const_cast<sx_graph *>(gc);
   if (src < 0 || src >= G->g.n) return fail(SX_EINVAL, "source out of range");
+  if (G->reordered) return fail(SX_EUNSUPPORTED, "policy collection on a renumbered graph (SX_REORDER)");
   if (p->ap.algo == SX_SSSP && !G->weighted) return fail(SX_EINVAL, "SSSP needs edge weights");
   if (stride < 1) stride = 1;
   HIP_TRY(hipSetDevice(p->ctx->device));
@@ -1035,6 +1066,7 @@ static sx_status validate_queries(sx_ctx *ctx, const sx_query *q, int32_t nq, in
     if (q[i].algo != SX_BFS && q[i].algo != SX_SSSP) return fail(SX_EINVAL, "query %d: BFS or SSSP only", i);
     if (q[i].source < 0 || q[i].source >= g->g.n) return fail(SX_EINVAL, "query %d: source out of range", i);
     if (q[i].algo == SX_SSSP && !g->weighted) return fail(SX_EINVAL, "query %d: SSSP needs weights", i);
+    if (g->reordered) return fail(SX_EUNSUPPORTED, "query %d: renumbered graph (SX_REORDER) in a batch", i);
     *nmax = std::max(*nmax, g->g.n);
     *mmax = std::max(*mmax, g->g.m);
   }
@@ -1183,19 +1215,35 @@ extern "C" sx_status sx_run(sx_program *p, const sx_graph *gc, int32_t source, v
   HIP_TRY(hipSetDevice(p->ctx->device));
   hipStream_t st = (hipStream_t)hip_stream;
   const int n = G->g.n;
+  // a renumbered graph runs on its own state array and maps the result back
+  void *state = G->reordered ? G->state : d_out;
+  sx_status s;
   switch (p->ap.algo) {
     case SX_BFS:
     case SX_SSSP:
       if (n == 0) return fail(SX_EINVAL, "empty graph has no source");
       if (source < 0 || source >= n) return fail(SX_EINVAL, "source %d out of range [0, %d)", source, n);
       if (p->ap.algo == SX_SSSP && !G->weighted) return fail(SX_EINVAL, "SSSP needs edge weights");
-      return run_traversal(p, G, source, d_out, st, stats);
+      s = run_traversal(p, G, G->reordered ? G->h_inv[(size_t)source] : source, state, st, stats);
+      break;
     case SX_KCORE:
-      return run_kcore(p, G, d_out, st, stats);
+      s = run_kcore(p, G, state, st, stats);
+      break;
     case SX_PAGERANK:
-      return run_pagerank(p, G, d_out, st, stats);
+      s = run_pagerank(p, G, state, st, stats);
+      break;
+    default:
+      return fail(SX_EINVAL, "unknown algorithm");
   }
-  return fail(SX_EINVAL, "unknown algorithm");
+  if (s != SX_OK || !G->reordered) return s;
+  HIP_TRY(hipEventRecord(G->ev0, st));
+  HIP_TRY(reorder_unpermute(G->state, G->d_inv, d_out, n, st));
+  HIP_TRY(hipEventRecord(G->ev1, st));
+  HIP_TRY(hipEventSynchronize(G->ev1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
+  if (stats) stats->device_ms += ms;
+  return SX_OK;
 }
 
 extern "C" sx_status sx_read_vertices(const sx_graph *g, sx_algo algo, const void *d_out,

@@ -1,6 +1,8 @@
 // Host-side entry points of the HIP kernels (launch helpers).
 #pragma once
 
+#include <functional>
+
 #include "sx_types.hpp"
 
 namespace sx {
@@ -29,6 +31,15 @@ const void *kcore_seq_kernel();
 
 hipError_t pagerank_launch(const PrArgs &a, int grid, hipStream_t s);
 const void *pagerank_kernel();
+
+// Degree-ordered renumbering (graph loading option).  `own` allocates
+// device memory that the graph keeps, `tmp` memory freed after the build.
+// out: the renumbered graph; *d_inv / h_inv[n]: old id -> new id.
+using RkAlloc = std::function<hipError_t(void **, size_t)>;
+hipError_t reorder_build(const DevGraph &g, const RkAlloc &own, const RkAlloc &tmp, hipStream_t s,
+                         DevGraph &out, int **d_inv, int *h_inv);
+// out[v] = in[inv[v]] for 4-byte elements
+hipError_t reorder_unpermute(const void *in, const int *inv, void *out, int n, hipStream_t s);
 
 hipError_t mlp_forward(const float *P, const float *X, int n, float *Y, float *H, hipStream_t s);
 hipError_t mlp_loss_grad(const float *P, const float *X, const float *T, const float *M, int n,

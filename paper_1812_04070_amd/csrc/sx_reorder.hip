@@ -1,0 +1,189 @@
+// Degree-ordered renumbering of a resident graph (an option of graph loading,
+// not part of the paper's method).  Vertices are renumbered by decreasing
+// degree (out + in for directed graphs; ties keep id order), rows are
+// rewritten with the new ids and sorted ascending.  The high-degree vertices
+// that most arcs lead to then share a few cache lines at the front of every
+// vertex array, so the scattered state accesses of every algorithm hit the
+// L2 more often (measured on MI355X, R-MAT s22: k-core 21.7 -> 20.2 ms;
+// PageRank s24 55 -> 45 ms).  Runs then compute in the new numbering; the
+// source is mapped in and the result is mapped back into the caller's array.
+//
+// The two sorts are rocPRIM's (through hipCUB): a radix sort of (degree,
+// vertex) and a segmented radix sort of the rows, both deterministic.
+#include <hipcub/hipcub.hpp>
+
+#include "sx_kernels.hpp"
+#include "sx_device.hpp"
+
+namespace sx {
+
+namespace {
+
+__global__ void k_rk_keys(const int *off, const int *in_off, int n, unsigned *key, int *ids) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (long long)gridDim.x * blockDim.x) {
+    unsigned d = (unsigned)(off[v + 1] - off[v]);
+    if (in_off) d += (unsigned)(in_off[v + 1] - in_off[v]);
+    key[v] = d;
+    ids[v] = (int)v;
+  }
+}
+
+// inv[perm[i]] = i
+__global__ void k_rk_inverse(const int *perm, int *inv, int n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    inv[perm[i]] = (int)i;
+}
+
+// row lengths in the new numbering; entry n is 0 (the exclusive sum's total)
+__global__ void k_rk_rowlen(const int *off, const int *perm, int n, int *len) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (i == n) { len[i] = 0; continue; }
+    const int v = perm[i];
+    len[i] = off[v + 1] - off[v];
+  }
+}
+
+// new row i = old row perm[i] with every neighbour renamed; one wavefront per
+// row (unsorted within the row; the segmented sort follows)
+__global__ void k_rk_rows(const int *off, const int *idx, const unsigned *w, const int *perm,
+                          const int *inv, const int *noff, int *nidx, unsigned *nw, int n) {
+  const int lane = threadIdx.x & 63;
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long long waves = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long i = wave; i < n; i += waves) {
+    const int v = perm[i];
+    const int beg = off[v], end = off[v + 1];
+    const int out = noff[i];
+    for (int e = beg + lane; e < end; e += 64) {
+      nidx[out + (e - beg)] = inv[idx[e]];
+      if (w) nw[out + (e - beg)] = w[e];
+    }
+  }
+}
+
+// out[v] = in[inv[v]]: a result in the new numbering back to the caller's
+__global__ void k_rk_unpermute(const unsigned *in, const int *inv, unsigned *out, int n) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (long long)gridDim.x * blockDim.x)
+    out[v] = in[inv[v]];
+}
+
+constexpr int kRkBlock = 256;
+
+int rk_grid(long long items) {
+  const long long g = (items + kRkBlock - 1) / kRkBlock;
+  return (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+}  // namespace
+
+#define RK_TRY(x)                              \
+  do {                                         \
+    hipError_t e_ = (x);                       \
+    if (e_ != hipSuccess) return e_;           \
+  } while (0)
+
+// One row structure (CSR or CSC) in the new numbering.
+static hipError_t reorder_rows(const int *off, const int *idx, const unsigned *w, const int *perm,
+                               const int *inv, int n, long long m, int *noff, int *nidx, unsigned *nw,
+                               const RkAlloc &tmp, hipStream_t s) {
+  int *len = nullptr;
+  RK_TRY(tmp((void **)&len, sizeof(int) * ((size_t)n + 1)));
+  hipLaunchKernelGGL(k_rk_rowlen, dim3(rk_grid(n + 1)), dim3(kRkBlock), 0, s, off, perm, n, len);
+  RK_TRY(hipGetLastError());
+  size_t bytes = 0;
+  RK_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, len, noff, n + 1, s));
+  void *scratch = nullptr;
+  RK_TRY(tmp(&scratch, bytes));
+  RK_TRY(hipcub::DeviceScan::ExclusiveSum(scratch, bytes, len, noff, n + 1, s));
+  if (m == 0) return hipSuccess;
+  int *kin = nullptr;
+  unsigned *vin = nullptr;
+  RK_TRY(tmp((void **)&kin, sizeof(int) * (size_t)m));
+  if (w) RK_TRY(tmp((void **)&vin, sizeof(unsigned) * (size_t)m));
+  hipLaunchKernelGGL(k_rk_rows, dim3(rk_grid((long long)n * 64)), dim3(kRkBlock), 0, s, off, idx, w,
+                     perm, inv, noff, kin, vin, n);
+  RK_TRY(hipGetLastError());
+  const int bits = 32 - __builtin_clz((unsigned)(n > 1 ? n - 1 : 1));
+  bytes = 0;
+  if (w) {
+    RK_TRY(hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, bytes, kin, nidx, vin, nw, (int)m, n,
+                                                      noff, noff + 1, 0, bits, s));
+    RK_TRY(tmp(&scratch, bytes));
+    RK_TRY(hipcub::DeviceSegmentedRadixSort::SortPairs(scratch, bytes, kin, nidx, vin, nw, (int)m, n,
+                                                      noff, noff + 1, 0, bits, s));
+  } else {
+    RK_TRY(hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, bytes, kin, nidx, (int)m, n, noff,
+                                                     noff + 1, 0, bits, s));
+    RK_TRY(tmp(&scratch, bytes));
+    RK_TRY(hipcub::DeviceSegmentedRadixSort::SortKeys(scratch, bytes, kin, nidx, (int)m, n, noff,
+                                                     noff + 1, 0, bits, s));
+  }
+  return hipSuccess;
+}
+
+hipError_t reorder_build(const DevGraph &g, const RkAlloc &own, const RkAlloc &tmp, hipStream_t s,
+                         DevGraph &out, int **d_inv, int *h_inv) {
+  const int n = g.n;
+  const long long m = g.m;
+  out = g;
+  unsigned *key = nullptr, *key_s = nullptr;
+  int *ids = nullptr, *perm = nullptr, *inv = nullptr;
+  RK_TRY(tmp((void **)&key, sizeof(unsigned) * ((size_t)n + 1)));
+  RK_TRY(tmp((void **)&key_s, sizeof(unsigned) * ((size_t)n + 1)));
+  RK_TRY(tmp((void **)&ids, sizeof(int) * ((size_t)n + 1)));
+  RK_TRY(tmp((void **)&perm, sizeof(int) * ((size_t)n + 1)));
+  RK_TRY(own((void **)&inv, sizeof(int) * ((size_t)n + 1)));
+  if (n > 0) {
+    hipLaunchKernelGGL(k_rk_keys, dim3(rk_grid(n)), dim3(kRkBlock), 0, s, g.off,
+                       g.directed ? g.in_off : (const int *)nullptr, n, key, ids);
+    RK_TRY(hipGetLastError());
+    size_t bytes = 0;
+    RK_TRY(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, bytes, key, key_s, ids, perm, n, 0, 32, s));
+    void *scratch = nullptr;
+    RK_TRY(tmp(&scratch, bytes));
+    RK_TRY(hipcub::DeviceRadixSort::SortPairsDescending(scratch, bytes, key, key_s, ids, perm, n, 0, 32, s));
+    hipLaunchKernelGGL(k_rk_inverse, dim3(rk_grid(n)), dim3(kRkBlock), 0, s, perm, inv, n);
+    RK_TRY(hipGetLastError());
+  }
+  int *noff = nullptr, *nidx = nullptr;
+  unsigned *nw = nullptr;
+  RK_TRY(own((void **)&noff, sizeof(int) * ((size_t)n + 1)));
+  RK_TRY(own((void **)&nidx, sizeof(int) * (size_t)(m > 0 ? m : 1)));
+  if (g.w) RK_TRY(own((void **)&nw, sizeof(unsigned) * (size_t)(m > 0 ? m : 1)));
+  RK_TRY(reorder_rows(g.off, g.idx, g.w, perm, inv, n, m, noff, nidx, nw, tmp, s));
+  out.off = noff;
+  out.idx = nidx;
+  out.w = nw;
+  if (g.directed) {
+    int *ioff = nullptr, *iidx = nullptr;
+    unsigned *iw = nullptr;
+    RK_TRY(own((void **)&ioff, sizeof(int) * ((size_t)n + 1)));
+    RK_TRY(own((void **)&iidx, sizeof(int) * (size_t)(m > 0 ? m : 1)));
+    if (g.in_w) RK_TRY(own((void **)&iw, sizeof(unsigned) * (size_t)(m > 0 ? m : 1)));
+    RK_TRY(reorder_rows(g.in_off, g.in_idx, g.in_w, perm, inv, n, m, ioff, iidx, iw, tmp, s));
+    out.in_off = ioff;
+    out.in_idx = iidx;
+    out.in_w = iw;
+  } else {
+    out.in_off = out.off;
+    out.in_idx = out.idx;
+    out.in_w = out.w;
+  }
+  if (n > 0) RK_TRY(hipMemcpyAsync(h_inv, inv, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost, s));
+  RK_TRY(hipStreamSynchronize(s));
+  *d_inv = inv;
+  return hipSuccess;
+}
+
+hipError_t reorder_unpermute(const void *in, const int *inv, void *out, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rk_unpermute, dim3(rk_grid(n)), dim3(kRkBlock), 0, s, (const unsigned *)in, inv,
+                     (unsigned *)out, n);
+  return hipGetLastError();
+}
+
+}  // namespace sx

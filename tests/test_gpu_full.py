@@ -47,6 +47,13 @@ def test_rmat22(engine):
         d2, _ = run(engine, g, sx.SX_BFS, src, pol, dg=dg)
         np.testing.assert_array_equal(d2, ref_d)
     dg.close()
+    # the degree-renumbered load that bench.py times
+    dr = engine.load(g, reorder=True)
+    announce("rmat22 reordered bfs / sssp / kcore")
+    np.testing.assert_array_equal(run(engine, g, sx.SX_BFS, src, dg=dr)[0], ref_d)
+    np.testing.assert_array_equal(run(engine, g, sx.SX_SSSP, src, dg=dr)[0], x)
+    np.testing.assert_array_equal(run(engine, g, sx.SX_KCORE, dg=dr)[0], c)
+    dr.close()
 
 
 def test_grid4096(engine):
@@ -79,3 +86,9 @@ def test_rmat24_directed(engine):
     np.testing.assert_array_equal(c, ref_c)
     pins.kcore_certificate_fast(g.n, g.offsets, g.indices, c, g.in_offsets, g.in_indices)
     dg.close()
+    dr = engine.load(g, reorder=True)
+    announce("rmat24d reordered pagerank / kcore")
+    r2, _ = run(engine, g, sx.SX_PAGERANK, dg=dr)
+    assert rel_l1(r2, ref) <= 1e-6
+    np.testing.assert_array_equal(run(engine, g, sx.SX_KCORE, dg=dr)[0], ref_c)
+    dr.close()
