@@ -801,7 +801,7 @@ static sx_status run_kcore(sx_program *p, sx_graph *G, void *d_out, hipStream_t 
     HIP_TRY(kcore_seq_launch(a, 0, grid, st, true));
     const Ctrl *fin = G->h_ctrl;
     sx_status s = seq_drive(
-        G, st, 32, 64, (unsigned)(16 * (long long)G->g.n + 1024),
+        G, st, 16, 16, (unsigned)(16 * (long long)G->g.n + 1024),
         [&](unsigned L) { return kcore_seq_launch(a, L, grid, st, false); }, launches, &fin);
     if (s != SX_OK) return s;
     HIP_TRY(hipEventRecord(G->ev1, st));
