@@ -60,7 +60,7 @@ constexpr unsigned long long kHotMinArcs = 65536;  // steps below this push dire
 constexpr int kLocalDeg = 256;
 constexpr int kLocalQ = 2048;
 constexpr unsigned kLocalArcs = 8192;   // arcs a workgroup takes on locally per step
-constexpr float kPullAlpha = 16.f; // pull when frontier arcs > alive arcs / alpha
+constexpr float kPullAlpha = 8.f;  // pull when frontier arcs > alive arcs / alpha
 
 struct LdsK {
   int hkey[kHot];
