@@ -134,7 +134,7 @@ void sx_program_destroy(sx_program *p);
  *             filter, which keeps results exact) |
  *             SX_FILTER_BALLOT (always rebuild the worklist by ballot scan)
  *  bin_small  degree below which one lane takes a vertex (default 64)
- *  bin_large  degree from which a workgroup takes chunks of a vertex (256)
+ *  bin_large  degree from which a workgroup takes chunks of a vertex (512)
  *  online_cap SX_FILTER_JIT only: online-filter capacity in entries per
  *             wavefront and bin (a workgroup of 8 wavefronts overflows past
  *             8 x online_cap entries in a bin); 0 = the workgroup's region
