@@ -402,7 +402,7 @@ struct LdsPolicy {
 // ballot rebuild: the online lists are incomplete.
 template <class Ops>
 SX_DEV Decision decide(const TravArgs &a, RunState &s, bool pulling, const Totals &T,
-                       LdsPolicy *pol) {
+                       LdsPolicy *pol, bool stage = false) {
   DecideIn in;
   in.nf = T.nf;
   in.mf = T.mf;
@@ -417,6 +417,10 @@ SX_DEV Decision decide(const TravArgs &a, RunState &s, bool pulling, const Total
     float x[kMlpIn];
     policy_features(in.nf, in.mf, Ops::kVote ? s.mu : (unsigned long long)a.g.m, a.g.n, a.g.m, s.ps,
                     pulling, x);
+    // stage the weights only for a decision the network takes (the barrier
+    // below orders the copy before the evaluation)
+    if (stage)
+      for (int i = threadIdx.x; i < kMlpParams; i += kBlock) pol->p[i] = a.mlp[i];
     __syncthreads();
     if (wave_in_wg() == 0) {
       float y[kMlpOut];
@@ -674,7 +678,6 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMi
   const VGrid vg = hw_grid();
   Line &out = C->seq[(L + 1) & 1];
   const bool lead = vg.bid == 0 && threadIdx.x == 0;
-  load_policy(a, pol);   // ordered before its first use by fetch_line's barrier
   fetch_line(C->seq[L & 1], C, lds.sq);
   const unsigned *in = lds.sq;
   unsigned phase = in[0];
@@ -701,7 +704,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMi
   bool have_view = false;
   if (due) {
     T = make_view(vg, a, (s.it + 1) % 3, (s.it + 1) & 1, lds, ref);
-    Decision d = decide<Ops>(a, s, pulling != 0, T, &pol);
+    // one launch per phase: the weights are staged only by a launch whose
+    // decision evaluates the network
+    Decision d = decide<Ops>(a, s, pulling != 0, T, &pol, true);
     if (d.done) {
       ++s.it;
       if (lead) seq_store(out, s.it >= a.P.max_iters ? SEQ_LIMIT : SEQ_DONE, s, pulling, 0, 0);
