@@ -43,8 +43,12 @@ def parse():
     ap.add_argument("--fused", type=int, default=0, help="0 auto, 1 fused, 2 unfused, 3 sequenced")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched / learned-policy leg")
     ap.add_argument("--pagerank", action="store_true",
-                    help="instead of the step: time PageRank (pull, FP32, 20 iterations) on the "
-                         "directed R-MAT scale 24 graph and print its own JSON line")
+                    help="instead of the step: time PageRank (pull, FP32, 20 iterations) and the "
+                         "k-core decomposition on the directed R-MAT scale 24 graph and print "
+                         "their own JSON line")
+    ap.add_argument("--grid", action="store_true",
+                    help="instead of the step: time BFS + SSSP on the 4096 x 4096 grid with 10%% of "
+                         "its edges deleted and print their own JSON line")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (scales the HBM "
                          "byte counters of a profiler run) and exit")
@@ -114,6 +118,20 @@ def algo_bytes(kind: str, st: dict, n: int, reached: int) -> float:
     if kind == "kcore":
         return 8.0 * e + 12.0 * st["scan_entries"] + 16.0 * n
     raise KeyError(kind)
+
+
+def trav_kernel_name(kind: str, fused: int, arcs: int) -> str:
+    """Name of the phase kernel a run of `kind` launches (graphs of 2^25 arcs
+    or more take the traversal kernel built for six wavefronts per SIMD)."""
+    if fused == 2:
+        return "unfused per-phase kernels"
+    seq = fused in (0, 3)
+    if kind == "kcore":
+        return "k_kcore_seq" if seq else "k_kcore_fused"
+    ops = "BfsOps" if kind == "bfs" else "SsspOps"
+    if not seq:
+        return f"k_fused<{ops}>"
+    return f"k_seq<{ops}, 6>" if arcs >= (1 << 25) else f"k_seq<{ops}>"
 
 
 def cpu_leg(g, src, ref_step_edges):
@@ -256,6 +274,29 @@ def pagerank_main(args):
     nbytes = (8.0 * g.m + 20.0 * g.n) * iters
     achieved = nbytes / (dev_ms / 1e3) / 1e9
     r = eng.to_host(dg, sx.SX_PAGERANK, out)
+    # the k-core decomposition of the same graph (degree = in + out), timed
+    # on its own after PageRank
+    kout = torch.empty(g.n, dtype=torch.int32, device=eng.device)
+    for _ in range(args.warmup):
+        eng.run(dg, sx.SX_KCORE, -1, pol, out=kout)
+    torch.cuda.synchronize()
+    kdev = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, kst = eng.run(dg, sx.SX_KCORE, -1, pol, out=kout)
+        kdev.append(kst["device_ms"])
+    torch.cuda.synchronize()
+    kms = 1e3 * (time.perf_counter() - t0) / args.steps
+    kdev_ms = float(np.median(kdev))
+    klaunch = max(1, int(kst["launches"]) - 1)
+    kbytes = algo_bytes("kcore", kst, g.n, g.n)
+    kc = eng.to_host(dg, sx.SX_KCORE, kout)
+    log(f"[bench] k-core {kms:.2f} ms/run ({klaunch} phase launches)")
+    kcore = {"ms": round(kms, 3), "device_ms": round(kdev_ms, 3), "gteps": round(g.m / (kms / 1e3) / 1e9, 3),
+             "kernel": trav_kernel_name("kcore", 0, g.m), "launches": klaunch,
+             "levels_scanned": kst["ballot_iters"], "peel_steps": kst["iterations"],
+             "avg_launch_us": round(1e3 * kdev_ms / klaunch, 3),
+             "achieved_GBs": round(kbytes / (kdev_ms / 1e3) / 1e9, 2)}
     result = {
         "metric": "PageRank pull FP32, directed R-MAT s24, 20 iterations",
         "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -276,6 +317,100 @@ def pagerank_main(args):
         result["rel_l1_vs_oracle"] = float(np.abs(r.astype(np.float64) - ref).sum() / np.abs(ref).sum())
         result["cpu_baseline"] = {"value": round(1e3 * cpu_s, 1), "unit": "ms", "cores": 1, "kind": "oracle",
                                   "sample": "the full 20-iteration FP64 PageRank of the same graph, serial C"}
+        t0 = time.perf_counter()
+        kref = oracle.kcore_g(g)
+        kcore["oracle_ms"] = round(1e3 * (time.perf_counter() - t0), 1)
+        kcore["bit_exact"] = bool(np.array_equal(kc, kref))
+    else:
+        result["cpu_baseline"] = None
+    result["kcore"] = kcore
+    dg.close()
+    eng.close()
+    print(json.dumps(result))
+
+
+def grid_main(args):
+    """BFS + SSSP on the 4096 x 4096 four-neighbour grid with 10 % of its
+    edges deleted (weights in [1, 1000]) from the highest-degree vertex
+    (ties to the lowest id): the high-diameter workload, thousands of small
+    iterations.  Loaded without renumbering (grid ids already keep neighbours
+    close).  value = GTEPS of the step (twice the source component's
+    undirected edges over the step time)."""
+    import torch
+    import paper_1812_04070_amd as sx
+    from paper_1812_04070_amd import gen
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    g = gen.workload_graph("grid4096")
+    src = gen.max_degree_vertex(g)
+    log(f"[bench] graph grid4096: n={g.n} arcs={g.m} src={src} gen {time.perf_counter()-t0:.1f}s")
+    eng = sx.Engine(0)
+    dg = eng.load(g)
+    out_bfs = torch.empty(g.n, dtype=torch.int32, device=eng.device)
+    out_sssp = torch.empty(g.n, dtype=torch.int32, device=eng.device)
+    pol = sx.Policy(fused=args.fused)
+
+    def step():
+        _, sb = eng.run(dg, sx.SX_BFS, src, pol, out=out_bfs)
+        _, ss = eng.run(dg, sx.SX_SSSP, src, pol, out=out_sssp)
+        return sb, ss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    per = {"bfs": [], "sssp": []}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sb, ss = step()
+        per["bfs"].append(sb)
+        per["sssp"].append(ss)
+        log(f"[bench] grid step done: bfs {sb['device_ms']:.2f} ms, sssp {ss['device_ms']:.2f} ms")
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    d = eng.to_host(dg, sx.SX_BFS, out_bfs)
+    x = eng.to_host(dg, sx.SX_SSSP, out_sssp)
+    deg = g.out_degree().astype(np.int64)
+    m_cc = int(deg[d >= 0].sum() // 2)
+    reached = int((d >= 0).sum())
+    value = 2 * m_cc / (ms_step / 1e3) / 1e9
+    algo_ms = {k: float(np.median([s["device_ms"] for s in v])) for k, v in per.items()}
+    last = {k: v[-1] for k, v in per.items()}
+    dom = max(algo_ms, key=algo_ms.get)
+    nbytes = algo_bytes(dom, last[dom], g.n, reached)
+    phase_launches = max(1, int(last[dom]["launches"]) - 1)
+    avg_launch_us = 1e3 * algo_ms[dom] / phase_launches
+    achieved = nbytes / phase_launches / (avg_launch_us / 1e6) / 1e9
+    result = {
+        "metric": "GTEPS BFS/SSSP on a 4096^2 grid (10% edges deleted), bit-exact",
+        "value": round(value, 4), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "grid4096-bfs-sssp", "side": 4096, "deleted": 0.1, "n": g.n, "arcs": g.m,
+                   "source": src, "weights": [1, 1000], "m_cc": m_cc, "reached": reached, "reorder": False},
+        "per_algo": {k: {"device_ms": round(algo_ms[k], 3), "iterations": last[k]["iterations"],
+                         "launches": last[k]["launches"], "pull_iters": last[k]["pull_iters"],
+                         "ballot_iters": last[k]["ballot_iters"], "edges_inspected": last[k]["edges_inspected"],
+                         "vertex_expansions": last[k]["vertex_expansions"]} for k in per},
+        "roofline": {"bound": "hbm", "kernel": trav_kernel_name(dom, args.fused, g.m),
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "launches": phase_launches,
+                     "avg_launch_us": round(avg_launch_us, 3),
+                     "algorithmic_bytes_per_launch": round(nbytes / phase_launches, 1)},
+    }
+    if not args.no_cpu:
+        import oracle
+        log("[bench] cpu oracle leg")
+        t0 = time.perf_counter()
+        rd = oracle.bfs_g(g, src)
+        t1 = time.perf_counter()
+        rx = oracle.sssp_g(g, src)
+        t2 = time.perf_counter()
+        result["cpu_baseline"] = {
+            "value": round(2 * m_cc / (t2 - t0) / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": (f"one full step on the same grid: FIFO-queue BFS {1e3*(t1-t0):.0f} ms and binary-heap "
+                       f"Dijkstra {1e3*(t2-t1):.0f} ms, serial C -O2 on one host core"),
+            "ms_per_step": round(1e3 * (t2 - t0), 1)}
+        result["bit_exact"] = bool(np.array_equal(d, rd) and np.array_equal(x, rx))
     else:
         result["cpu_baseline"] = None
     dg.close()
@@ -294,6 +429,9 @@ def main():
         return
     if args.pagerank:
         pagerank_main(args)
+        return
+    if args.grid:
+        grid_main(args)
         return
     import torch
     import paper_1812_04070_amd as sx
@@ -362,10 +500,7 @@ def main():
     phase_launches = max(1, int(last[dom]["launches"]) - 1)
     avg_launch_us = 1e3 * algo_ms[dom] / phase_launches
     achieved = nbytes / phase_launches / (avg_launch_us / 1e6) / 1e9
-    seq = args.fused in (0, 3)
-    kname = {"bfs": "k_seq<BfsOps>" if seq else "k_fused<BfsOps>",
-             "sssp": "k_seq<SsspOps>" if seq else "k_fused<SsspOps>",
-             "kcore": "k_kcore_seq" if seq else "k_kcore_fused"}[dom]
+    kname = trav_kernel_name(dom, args.fused, g.m)
 
     result = {
         "metric": "GTEPS BFS/SSSP R-MAT s22, bit-exact; learned-policy+batched vs heuristic speedup",
