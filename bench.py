@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--grid", action="store_true",
                     help="instead of the step: time BFS + SSSP on the 4096 x 4096 grid with 10%% of "
                          "its edges deleted and print their own JSON line")
+    ap.add_argument("--delta", type=int, default=-1,
+                    help="SSSP delta-stepping bucket width (0 = none; default: the workload's own)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (scales the HBM "
                          "byte counters of a profiler run) and exit")
@@ -349,10 +351,11 @@ def grid_main(args):
     out_bfs = torch.empty(g.n, dtype=torch.int32, device=eng.device)
     out_sssp = torch.empty(g.n, dtype=torch.int32, device=eng.device)
     pol = sx.Policy(fused=args.fused)
+    delta = max(args.delta, 0)
 
     def step():
         _, sb = eng.run(dg, sx.SX_BFS, src, pol, out=out_bfs)
-        _, ss = eng.run(dg, sx.SX_SSSP, src, pol, out=out_sssp)
+        _, ss = eng.run(dg, sx.SX_SSSP, src, pol, out=out_sssp, sssp_delta=delta)
         return sb, ss
 
     for _ in range(args.warmup):
@@ -386,7 +389,8 @@ def grid_main(args):
         "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": "grid4096-bfs-sssp", "side": 4096, "deleted": 0.1, "n": g.n, "arcs": g.m,
-                   "source": src, "weights": [1, 1000], "m_cc": m_cc, "reached": reached, "reorder": False},
+                   "source": src, "weights": [1, 1000], "m_cc": m_cc, "reached": reached, "reorder": False,
+                   "sssp_delta": delta},
         "per_algo": {k: {"device_ms": round(algo_ms[k], 3), "iterations": last[k]["iterations"],
                          "launches": last[k]["launches"], "pull_iters": last[k]["pull_iters"],
                          "ballot_iters": last[k]["ballot_iters"], "edges_inspected": last[k]["edges_inspected"],

@@ -116,10 +116,20 @@ sx_status sx_graph_info(const sx_graph *g, int32_t *n, int64_t *m, int32_t *dire
  *              uniformly.  Output float rank (FP32 arithmetic). */
 typedef enum { SX_BFS = 0, SX_SSSP = 1, SX_KCORE = 2, SX_PAGERANK = 3 } sx_algo;
 
+/* sssp_delta: bucket width of delta-stepping for SX_SSSP (Section 3.3: the
+ * vertices whose distances lie in the lowest non-empty bucket [B - delta, B)
+ * are relaxed together; the others stay listed, unexpanded, until the bound
+ * B reaches them).  0 = no buckets: every listed vertex is expanded in every
+ * iteration (plain frontier relaxation).  Results are identical for any
+ * value; it changes the work and the iteration count only.  Used by the
+ * sequenced arrangement (SX_FUSE_AUTO / SX_SEQUENCED); the persistent and
+ * unfused arrangements and batches relax without buckets, and a run that
+ * switches to pull steps drops the buckets from then on. */
 typedef struct {
   sx_algo algo;
   float pr_damping;      /* PageRank damping d (0.85)                          */
   int32_t pr_iters;      /* PageRank iterations (20)                           */
+  uint32_t sssp_delta;   /* SSSP bucket width (0 = none)                       */
 } sx_algo_params;
 
 sx_status sx_program_register(sx_ctx *ctx, const sx_algo_params *params, sx_program **out);

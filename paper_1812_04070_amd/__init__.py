@@ -60,7 +60,8 @@ class sx_graph_desc(ctypes.Structure):
 
 
 class sx_algo_params(ctypes.Structure):
-    _fields_ = [("algo", ctypes.c_int), ("pr_damping", ctypes.c_float), ("pr_iters", ctypes.c_int32)]
+    _fields_ = [("algo", ctypes.c_int), ("pr_damping", ctypes.c_float), ("pr_iters", ctypes.c_int32),
+                ("sssp_delta", ctypes.c_uint32)]
 
 
 class sx_policy(ctypes.Structure):
@@ -196,9 +197,9 @@ def sx_graph_destroy(g) -> None:
     lib().sx_graph_destroy(g)
 
 
-def sx_program_register(ctx, algo: int, pr_damping: float = 0.85, pr_iters: int = 20):
+def sx_program_register(ctx, algo: int, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0):
     h = ctypes.c_void_p()
-    p = sx_algo_params(algo, pr_damping, pr_iters)
+    p = sx_algo_params(algo, pr_damping, pr_iters, sssp_delta)
     check(lib().sx_program_register(ctx, ctypes.byref(p), ctypes.byref(h)), "sx_program_register")
     return h
 
@@ -388,10 +389,10 @@ class Engine:
         import torch
         return torch.cuda.current_stream(self.device).cuda_stream
 
-    def program(self, algo: int, pr_damping: float = 0.85, pr_iters: int = 20):
-        key = (algo, pr_damping, pr_iters)
+    def program(self, algo: int, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0):
+        key = (algo, pr_damping, pr_iters, sssp_delta)
         if key not in self.programs:
-            self.programs[key] = sx_program_register(self.ctx, algo, pr_damping, pr_iters)
+            self.programs[key] = sx_program_register(self.ctx, algo, pr_damping, pr_iters, sssp_delta)
         return self.programs[key]
 
     def load(self, g, validate: bool = False, reorder: bool = False) -> DeviceGraph:
@@ -400,10 +401,11 @@ class Engine:
         return DeviceGraph(self, g, validate, reorder)
 
     def run(self, dg: DeviceGraph, algo: int, source: int = -1, policy: Optional[Policy] = None,
-            out=None, pr_damping: float = 0.85, pr_iters: int = 20):
-        """Run and return (torch device tensor, stats dict)."""
+            out=None, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0):
+        """Run and return (torch device tensor, stats dict).  sssp_delta: SSSP
+        bucket width of delta-stepping (0 = none)."""
         import torch
-        p = self.program(algo, pr_damping, pr_iters)
+        p = self.program(algo, pr_damping, pr_iters, sssp_delta)
         sx_program_set_policy(p, (policy or Policy()).c())
         if out is None:
             dt = {SX_PAGERANK: torch.float32}.get(algo, torch.int32)

@@ -515,8 +515,12 @@ static Params make_params(const sx_program *p, const sx_graph *G, int grid) {
   P.alpha_w = 0.5f;
   P.beta_w = 4.0f;
   // a BFS level or a Bellman-Ford round adds at least one vertex to the set
-  // of settled ones, so n + 2 iterations bound every correct run
-  P.max_iters = G ? G->g.n + 2 : INT_MAX / 2;
+  // of settled ones, so n + 2 iterations bound every correct run.  With
+  // buckets, each bucket takes at most (its vertices + 1) rounds: 2n + 4.
+  const bool seq_arr = p->pol.fused == SX_SEQUENCED || p->pol.fused == SX_FUSE_AUTO;
+  P.delta = p->ap.algo == SX_SSSP && seq_arr ? p->ap.sssp_delta : 0u;
+  P.max_iters = G ? (P.delta ? (int)std::min<long long>(2ll * G->g.n + 4, INT_MAX / 2) : G->g.n + 2)
+                  : INT_MAX / 2;
   P.pr_d = p->ap.pr_damping;
   P.pr_iters = p->ap.pr_iters;
   P.learned = pol.policy == SX_POLICY_LEARNED ? 1 : 0;

@@ -45,8 +45,8 @@ struct BfsOps {
   // push Compute + Combine for kIlp arcs v->u per lane; act[r]: u becomes
   // active.  All depth loads, then all claims, are in flight together.
   SX_DEV void push(const int *v, const int *u, const int *arc, const bool *ok, const DevGraph &g,
-                   unsigned &err, bool *act) const {
-    (void)v; (void)arc; (void)g; (void)err;
+                   unsigned &err, bool *act, unsigned &lowest) const {
+    (void)v; (void)arc; (void)g; (void)err; (void)lowest;
     int d[kIlp], got[kIlp];
 #pragma unroll
     for (int r = 0; r < kIlp; ++r) d[r] = ok[r] ? depth[u[r]] : 0;
@@ -67,9 +67,10 @@ struct SsspOps {
   int *stamp;
   int it;
   // relax kIlp arcs per lane: loads, then the atomic minimums, then the
-  // stamps of the improved targets, each stage with all arcs in flight
+  // stamps of the improved targets, each stage with all arcs in flight;
+  // `lowest` keeps the smallest distance this lane set
   SX_DEV void push(const int *v, const int *u, const int *arc, const bool *ok, const DevGraph &g,
-                   unsigned &err, bool *act) const {
+                   unsigned &err, bool *act, unsigned &lowest) const {
     unsigned dv[kIlp], w[kIlp], du[kIlp], nd[kIlp], old[kIlp];
     bool tr[kIlp];
 #pragma unroll
@@ -91,6 +92,7 @@ struct SsspOps {
     for (int r = 0; r < kIlp; ++r) {
       tr[r] = tr[r] && nd[r] < old[r];
       st[r] = tr[r] ? atomic_exch_i32(&stamp[u[r]], it + 1) : 0;
+      if (tr[r] && nd[r] < lowest) lowest = nd[r];
     }
 #pragma unroll
     for (int r = 0; r < kIlp; ++r) act[r] = tr[r] && st[r] != it + 1;
@@ -117,18 +119,68 @@ SX_DEV void raise_error(Ctrl *C, unsigned e) { store_relaxed(&C->error.v[0], e);
 // --------------------------------------------------------- push phase ---
 // Compute + combine over the current lists (view `cur`, totals T); the
 // online filter records the activated vertices into slot it+1 (parity it+1).
+//
+// Delta-stepping (SSSP, bound B below 0xFFFFFFFF; Section 3.3 of the paper
+// adopts it to widen the set of vertices relaxed together): only list
+// vertices with distance < B are expanded; the others are carried into the
+// next lists unexpanded (stamped as active for iteration it+1, so a ballot
+// rebuild finds them too).  Distances only fall, so a vertex read as far by
+// the carrying pass and as near by its visitor is both carried and expanded
+// (redundant, never lost).  The smallest distance set or carried in the
+// step goes to Ctrl::aux[(it+1) % 3], from which the next decision moves B.
 template <class Ops>
 SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, const Ops &ops, int it,
-                         const ViewRef &cur, const Totals &T, LdsTrav &lds) {
+                         const ViewRef &cur, const Totals &T, LdsTrav &lds,
+                         unsigned B = 0xFFFFFFFFu) {
   const DevGraph &g = a.g;
   const Regions NR = regions(a.w, (it + 1) & 1, vg.nb);
   bins_begin(lds.bins, NR, P.online_cap);
   WaveStats st;
   unsigned err = 0;
   long long edges = 0;
+  unsigned lowest = 0xFFFFFFFFu;
+  const bool buckets = !Ops::kVote && B != 0xFFFFFFFFu;
+  // a far vertex (distance >= B) reads as -1, which every visitor skips
+  auto near = [&](int v) -> int {
+    if constexpr (Ops::kVote) {
+      return v;
+    } else {
+      return buckets && (unsigned)v < (unsigned)g.n && ops.dist[v] >= B ? -1 : v;
+    }
+  };
+  if constexpr (!Ops::kVote) {
+    if (buckets) {
+      const unsigned cs = T.cnt[BIN_SMALL], cm = T.cnt[BIN_MED], cl = T.cnt[BIN_LARGE];
+      const unsigned total = cs + cm + cl;
+      const unsigned tid = vg.bid * kBlock + threadIdx.x, nt = vg.nb * kBlock;
+      // wave-uniform trip count: all lanes take part in the appends
+      for (unsigned base = tid - lane_id(); base < total; base += nt) {
+        const unsigned i = base + lane_id();
+        bool carry = false;
+        int v = -1;
+        if (i < total) {
+          unsigned long long item;
+          if (i < cs) item = (unsigned)cur.small(i);
+          else if (i < cs + cm) item = (unsigned)cur.med(i - cs);
+          else item = cur.large(i - cs - cm);
+          v = (int)(item & 0xffffffffu);
+          const bool first = i < cs + cm || (item >> 32) == 0;   // one chunk per vertex
+          if (first && (unsigned)v < (unsigned)g.n) {
+            const unsigned d = ops.dist[v];
+            if (d >= B) {
+              if (d < lowest) lowest = d;
+              carry = atomic_exch_i32(&ops.stamp[v], it + 1) != it + 1;
+            }
+          }
+        }
+        const int dv = carry ? degree_of(g.off, v) : 0;
+        bins_append(carry, v, dv, NR, vg.bid, P, P.chunk, lds.bins, st);
+      }
+    }
+  }
   auto op = [&](const int *v, const int *u, const int *arc, const bool *ok) {
     bool act[kIlp];
-    ops.push(v, u, arc, ok, g, err, act);
+    ops.push(v, u, arc, ok, g, err, act, lowest);
     int du[kIlp];
 #pragma unroll
     for (int r = 0; r < kIlp; ++r) {
@@ -140,12 +192,38 @@ SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   };
   const unsigned gw = vg.bid * kWaves + wave_in_wg();
   const unsigned nw = vg.nb * kWaves;
-  visit_large(vg, g.n, [&](unsigned i) { return cur.large(i); }, T.cnt[BIN_LARGE], g.off, g.idx,
-              P.chunk, op);
-  visit_med(g.n, [&](unsigned i) { return cur.med(i); }, T.cnt[BIN_MED], g.off, g.idx, op, gw, nw);
-  visit_small(g.n, [&](unsigned i) { return cur.small(i); }, T.cnt[BIN_SMALL], g.off, g.idx, op, gw,
-              nw, lds.small[wave_in_wg()]);
-  bins_end(lds.bins, st, a.w.rec + ((it + 1) % 3), vg.bid);
+  // (the medium and large visitors call their accessor with every lane of a
+  // wavefront on one entry: lane 0's reading decides for the wavefront)
+  visit_large(vg, g.n,
+              [&](unsigned i) {
+                const unsigned long long x = cur.large(i);
+                if (!buckets) return x;
+                const int far = __shfl(near((int)(x & 0xffffffffu)) < 0 ? 1 : 0, 0);
+                return far ? (x | 0xffffffffull) : x;
+              },
+              T.cnt[BIN_LARGE], g.off, g.idx, P.chunk, op);
+  visit_med(g.n,
+            [&](unsigned i) {
+              const int v = cur.med(i);
+              return buckets ? __shfl(near(v), 0) : v;
+            },
+            T.cnt[BIN_MED], g.off, g.idx, op, gw, nw);
+  visit_small(g.n, [&](unsigned i) { return near(cur.small(i)); }, T.cnt[BIN_SMALL], g.off, g.idx, op,
+              gw, nw, lds.small[wave_in_wg()]);
+  bins_end(lds.bins, st, a.w.rec + ((it + 1) % 3), vg.bid);   // ends with a barrier
+  if (buckets) {
+    const unsigned m = wave_min_u(lowest);
+    if (lane_id() == 0) lds.cnt[wave_in_wg()] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned x = 0xFFFFFFFFu;
+      for (int w2 = 0; w2 < kWaves; ++w2) x = lds.cnt[w2] < x ? lds.cnt[w2] : x;
+      if (x != 0xFFFFFFFFu) atomic_min_u32(&a.w.ctrl->aux.v[(it + 1) % 3], x);
+      // the word step it+1 lowers; its last reader was the decision before
+      // this step
+      if (vg.bid == 0) store_relaxed(&a.w.ctrl->aux.v[(it + 2) % 3], 0xFFFFFFFFu);
+    }
+  }
   if (err) raise_error(a.w.ctrl, err);
   add_stats(a.w.ctrl, vg.bid, edges,
             vg.bid == 0 ? (unsigned long long)T.cnt[0] + T.cnt[1] + T.cnt[2] : 0ull, lds.red);
@@ -389,6 +467,7 @@ struct RunState {
   unsigned long long mu;
   PolicyState ps;
   Params P;
+  unsigned B = 0xFFFFFFFFu;     // delta-stepping bound (sequenced SSSP)
 };
 
 struct LdsPolicy {
@@ -649,7 +728,8 @@ __global__ void __launch_bounds__(kBlock) k_pull_step(TravArgs a, int it) {
 enum : unsigned { PH_PUSH = 0, PH_BALLOT = 1, PH_PULL_SCAN = 2, PH_PULL = 3 };
 // seq line: [0] phase [1] iteration [2,3] unexplored arcs [4] previous
 // frontier size [6,7] activated so far [8] t1 [9] t2 [10] pulling [11] a
-// decision is due [12] the push lists come from a ballot scan
+// decision is due [12] the push lists come from a ballot scan [13] the
+// delta-stepping bound (0: not set yet)
 SX_DEV void seq_store(Line &l, unsigned phase, const RunState &s, unsigned pulling, unsigned due,
                       unsigned rebuilt) {
   store_relaxed(&l.v[0], phase);
@@ -662,6 +742,7 @@ SX_DEV void seq_store(Line &l, unsigned phase, const RunState &s, unsigned pulli
   store_relaxed(&l.v[10], pulling);
   store_relaxed(&l.v[11], due);
   store_relaxed(&l.v[12], rebuilt);
+  store_relaxed(&l.v[13], s.B);
 }
 
 // kMinWaves = 6 (the wide form, for large graphs): at least six wavefronts
@@ -691,6 +772,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMi
   unsigned pulling = in[10];
   const unsigned due = in[11];
   unsigned rebuilt = in[12];
+  s.B = in[13] ? in[13] : (a.P.delta ? a.P.delta : 0xFFFFFFFFu);
   if (phase >= SEQ_DONE) {
     if (lead) seq_store(out, phase, s, pulling, 0, rebuilt);
     return;
@@ -711,6 +793,20 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMi
       ++s.it;
       if (lead) seq_store(out, s.it >= a.P.max_iters ? SEQ_LIMIT : SEQ_DONE, s, pulling, 0, 0);
       return;
+    }
+    // delta-stepping: once no listed vertex lies below the bound, move it to
+    // the end of the bucket holding the smallest listed distance (empty
+    // buckets are skipped); pull steps relax without buckets
+    if (s.B != 0xFFFFFFFFu) {
+      if (pulling || d.to_pull) {
+        s.B = 0xFFFFFFFFu;
+      } else {
+        const unsigned lo = load_relaxed(&C->aux.v[(s.it + 1) % 3]);
+        if (lo != 0xFFFFFFFFu && lo >= s.B) {
+          const unsigned long long nb = ((unsigned long long)lo / a.P.delta + 1ull) * a.P.delta;
+          s.B = nb >= 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned)nb;
+        }
+      }
     }
     if (!pulling) {
       if (d.to_pull) { pulling = 1; phase = PH_PULL_SCAN; ++s.it; }
@@ -735,7 +831,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMi
         if (rebuilt && !scan_fits(a, T)) break;
       }
       if (lead) atomic_add_u32(&C->stats.v[6], 1u);
-      push_phase(vg, a, s.P, ops, it, ref, T, lds);
+      push_phase(vg, a, s.P, ops, it, ref, T, lds, s.B);
       if (lead) seq_store(out, PH_PUSH, s, 0, 1, 0);
       break;
     case PH_BALLOT:
@@ -769,6 +865,8 @@ __global__ void k_seq_start(Ctrl *C, unsigned pull_first) {
     l.v[0] = pull_first ? PH_PULL_SCAN : PH_PUSH;
     l.v[10] = pull_first;
     *(unsigned long long *)&l.v[2] = *(unsigned long long *)&C->state.v[6];
+    // delta-stepping: smallest distance set by each step (three rotating words)
+    for (int i = 0; i < 3; ++i) C->aux.v[i] = 0xFFFFFFFFu;
   }
 }
 
