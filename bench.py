@@ -351,7 +351,9 @@ def grid_main(args):
     out_bfs = torch.empty(g.n, dtype=torch.int32, device=eng.device)
     out_sssp = torch.empty(g.n, dtype=torch.int32, device=eng.device)
     pol = sx.Policy(fused=args.fused)
-    delta = max(args.delta, 0)
+    # bucket width 20,000 (about 40 mean arc weights): the best of a sweep
+    # from 100 to 300,000 on this grid (619 ms without buckets, 215 ms)
+    delta = args.delta if args.delta >= 0 else 20000
 
     def step():
         _, sb = eng.run(dg, sx.SX_BFS, src, pol, out=out_bfs)
