@@ -351,9 +351,10 @@ def grid_main(args):
     out_bfs = torch.empty(g.n, dtype=torch.int32, device=eng.device)
     out_sssp = torch.empty(g.n, dtype=torch.int32, device=eng.device)
     pol = sx.Policy(fused=args.fused)
-    # bucket width 20,000 (about 40 mean arc weights): the best of a sweep
-    # from 100 to 300,000 on this grid (619 ms without buckets, 215 ms)
-    delta = args.delta if args.delta >= 0 else 20000
+    # the engine's own bucket width: 40 mean arc weights on a graph this
+    # sparse, about 20,000 here (a sweep from 100 to 300,000 on this grid put
+    # the best widths at 20,000-50,000: 215 ms against 619 without buckets)
+    delta = args.delta if args.delta >= 0 else sx.SX_DELTA_AUTO
 
     def step():
         _, sb = eng.run(dg, sx.SX_BFS, src, pol, out=out_bfs)
@@ -392,7 +393,7 @@ def grid_main(args):
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": "grid4096-bfs-sssp", "side": 4096, "deleted": 0.1, "n": g.n, "arcs": g.m,
                    "source": src, "weights": [1, 1000], "m_cc": m_cc, "reached": reached, "reorder": False,
-                   "sssp_delta": delta},
+                   "sssp_delta": "auto" if delta == sx.SX_DELTA_AUTO else delta},
         "per_algo": {k: {"device_ms": round(algo_ms[k], 3), "iterations": last[k]["iterations"],
                          "launches": last[k]["launches"], "pull_iters": last[k]["pull_iters"],
                          "ballot_iters": last[k]["ballot_iters"], "edges_inspected": last[k]["edges_inspected"],

@@ -120,7 +120,10 @@ typedef enum { SX_BFS = 0, SX_SSSP = 1, SX_KCORE = 2, SX_PAGERANK = 3 } sx_algo;
  * vertices whose distances lie in the lowest non-empty bucket [B - delta, B)
  * are relaxed together; the others stay listed, unexpanded, until the bound
  * B reaches them).  0 = no buckets: every listed vertex is expanded in every
- * iteration (plain frontier relaxation).  Results are identical for any
+ * iteration (plain frontier relaxation).  SX_DELTA_AUTO = the engine
+ * chooses: 40 times the mean arc weight on graphs with fewer than 8 arcs per
+ * vertex, no buckets on denser graphs (the weights are summed on the device
+ * once per graph, before the run's timed region).  Results are identical for any
  * value; it changes the work and the iteration count only.  Used by the
  * sequenced arrangement (SX_FUSE_AUTO / SX_SEQUENCED); the persistent and
  * unfused arrangements and batches relax without buckets, and a run that
@@ -131,6 +134,7 @@ typedef struct {
   int32_t pr_iters;      /* PageRank iterations (20)                           */
   uint32_t sssp_delta;   /* SSSP bucket width (0 = none)                       */
 } sx_algo_params;
+#define SX_DELTA_AUTO 0xFFFFFFFFu
 
 sx_status sx_program_register(sx_ctx *ctx, const sx_algo_params *params, sx_program **out);
 void sx_program_destroy(sx_program *p);

@@ -197,6 +197,9 @@ def sx_graph_destroy(g) -> None:
     lib().sx_graph_destroy(g)
 
 
+SX_DELTA_AUTO = 0xFFFFFFFF
+
+
 def sx_program_register(ctx, algo: int, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0):
     h = ctypes.c_void_p()
     p = sx_algo_params(algo, pr_damping, pr_iters, sssp_delta)

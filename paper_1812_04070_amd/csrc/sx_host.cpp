@@ -77,6 +77,7 @@ struct sx_graph {
   int *d_inv = nullptr;
   std::vector<int> h_inv;
   void *state = nullptr;
+  long long weight_sum = -1;  // sum of the arc weights, once SX_DELTA_AUTO needed it
 };
 
 struct sx_program {
@@ -676,6 +677,28 @@ static Decision host_decide(const sx_ctx *ctx, const sx_policy &pol, Params &P, 
   return d;
 }
 
+// SX_DELTA_AUTO: buckets of about 40 mean arc weights on graphs with fewer
+// than 8 arcs per vertex (meshes and road-like graphs, thousands of
+// iterations: on the 4096^2 grid with weights in [1, 1000] the best widths
+// measured were 20,000-50,000), none on denser graphs, whose few iterations
+// buckets only multiply (R-MAT s22: every width tried was slower).
+static sx_status auto_delta(sx_graph *G, hipStream_t st, unsigned *delta) {
+  *delta = 0;
+  const long long n = G->g.n, m = G->g.m;
+  if (!G->g.w || n <= 0 || m <= 0 || m >= 8 * n) return SX_OK;
+  if (G->weight_sum < 0) {
+    unsigned long long *d = (unsigned long long *)&G->w.ctrl->aux.v[4];
+    HIP_TRY(weight_sum(G->g.w, m, d, st));
+    unsigned long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    G->weight_sum = (long long)h;
+  }
+  const double w = std::floor(40.0 * (double)G->weight_sum / (double)m + 0.5);
+  *delta = (unsigned)std::min(std::max(w, 1.0), 2147483647.0);
+  return SX_OK;
+}
+
 static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out, hipStream_t st,
                                sx_run_stats *stats) {
   const int sssp = p->ap.algo == SX_SSSP;
@@ -703,6 +726,10 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   a.src = src;
   a.mlp = ctx->d_mlp;
   if (a.P.learned && !ctx->d_mlp) return fail(SX_ESTATE, "learned policy without loaded MLP");
+  if (sssp && a.P.delta == SX_DELTA_AUTO) {
+    sx_status s = auto_delta(G, st, &a.P.delta);
+    if (s != SX_OK) return s;
+  }
   int launches = 0;
   HIP_TRY(hipEventRecord(G->ev0, st));
   // unexplored arcs (BFS direction rule) are computed on the device

@@ -20,6 +20,7 @@ hipError_t trav_init(const TravArgs &a, int sssp, unsigned long long mu0, int ru
                      hipStream_t s);
 hipError_t batch_launch(const BatchArgs &b, int grid, hipStream_t s);
 hipError_t seq_start(Ctrl *c, bool pull_first, hipStream_t s);
+hipError_t weight_sum(const unsigned *w, long long m, unsigned long long *out, hipStream_t s);
 // phases of the sequenced mode (Ctrl::seq[..].v[0])
 enum : unsigned { SEQ_DONE = 6, SEQ_ERROR = 7, SEQ_LIMIT = 8 };
 const void *batch_kernel();

@@ -1096,6 +1096,28 @@ hipError_t trav_init(const TravArgs &a, int sssp, unsigned long long mu0, int ru
   return hipGetLastError();
 }
 
+// Sum of the m arc weights into *out (zeroed first): one 64-bit atomic per
+// wavefront.  Used once per graph to choose a delta-stepping width.
+__global__ void __launch_bounds__(256) k_weight_sum(const unsigned *w, long long m,
+                                                    unsigned long long *out) {
+  long long s = 0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (long long)gridDim.x * blockDim.x)
+    s += (long long)w[e];
+  s = wave_sum_ll(s);
+  if (lane_id() == 0 && s) atomic_add_u64(out, (unsigned long long)s);
+}
+
+hipError_t weight_sum(const unsigned *w, long long m, unsigned long long *out, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(unsigned long long), s);
+  if (e != hipSuccess) return e;
+  if (m <= 0) return hipSuccess;
+  long long grid = (m + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_weight_sum, dim3((unsigned)grid), dim3(256), 0, s, w, m, out);
+  return hipGetLastError();
+}
+
 hipError_t seq_start(Ctrl *c, bool pull_first, hipStream_t s) {
   hipLaunchKernelGGL(k_seq_start, dim3(1), dim3(64), 0, s, c, pull_first ? 1u : 0u);
   return hipGetLastError();

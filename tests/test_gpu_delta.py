@@ -39,7 +39,7 @@ GRAPHS = [
                                                        [1 + i % 7 for i in range(200)])),
 ]
 
-DELTAS = [1, 7, 64, 1000, 1 << 31]
+DELTAS = [1, 7, 64, 1000, sx.SX_DELTA_AUTO, 1 << 31]
 
 POLICIES = [
     ("auto", sx.Policy()),
@@ -82,12 +82,33 @@ def test_delta_cuts_relaxations_on_grid(engine):
     x0, st0 = run(engine, g, sx.SX_SSSP, s, None, dg=dg)
     announce("delta grid-128 delta=500")
     x1, st1 = run(engine, g, sx.SX_SSSP, s, None, dg=dg, sssp_delta=500)
+    announce("delta grid-128 automatic width")
+    x2, st2 = run(engine, g, sx.SX_SSSP, s, None, dg=dg, sssp_delta=sx.SX_DELTA_AUTO)
     dg.close()
     np.testing.assert_array_equal(x0, ref)
     np.testing.assert_array_equal(x1, ref)
-    print(f"[delta] grid-128 arcs inspected: none {st0['edges_inspected']} delta=500 {st1['edges_inspected']}; "
-          f"iterations {st0['iterations']} -> {st1['iterations']}")
+    np.testing.assert_array_equal(x2, ref)
+    print(f"[delta] grid-128 arcs inspected: none {st0['edges_inspected']} delta=500 {st1['edges_inspected']} "
+          f"auto {st2['edges_inspected']}; iterations {st0['iterations']} -> {st1['iterations']}, "
+          f"{st2['iterations']}")
     assert st1["edges_inspected"] < st0["edges_inspected"]
+    assert st2["edges_inspected"] < st0["edges_inspected"]
+
+
+def test_delta_auto_keeps_dense_graphs_unbucketed(engine):
+    """The automatic width leaves graphs of 8+ arcs per vertex without
+    buckets: the same iterations as the plain run."""
+    g = gen.rmat(14, seed=5, weights=(1, 64))
+    assert g.m >= 8 * g.n
+    s = gen.max_degree_vertex(g)
+    dg = engine.load(g)
+    announce("delta rmat14 none / auto")
+    x0, st0 = run(engine, g, sx.SX_SSSP, s, None, dg=dg)
+    x1, st1 = run(engine, g, sx.SX_SSSP, s, None, dg=dg, sssp_delta=sx.SX_DELTA_AUTO)
+    dg.close()
+    np.testing.assert_array_equal(x0, oracle.sssp_g(g, s))
+    np.testing.assert_array_equal(x1, x0)
+    assert st1["iterations"] == st0["iterations"]
 
 
 def test_delta_single_and_edgeless(engine):
