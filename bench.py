@@ -122,9 +122,10 @@ def algo_bytes(kind: str, st: dict, n: int, reached: int) -> float:
     raise KeyError(kind)
 
 
-def trav_kernel_name(kind: str, fused: int, arcs: int) -> str:
+def trav_kernel_name(kind: str, fused: int, arcs: int, n: int) -> str:
     """Name of the phase kernel a run of `kind` launches (graphs of 2^25 arcs
-    or more take the traversal kernel built for six wavefronts per SIMD)."""
+    or more and at least 8 arcs per vertex take the traversal kernel built
+    for six wavefronts per SIMD)."""
     if fused == 2:
         return "unfused per-phase kernels"
     seq = fused in (0, 3)
@@ -133,7 +134,7 @@ def trav_kernel_name(kind: str, fused: int, arcs: int) -> str:
     ops = "BfsOps" if kind == "bfs" else "SsspOps"
     if not seq:
         return f"k_fused<{ops}>"
-    return f"k_seq<{ops}, 6>" if arcs >= (1 << 25) else f"k_seq<{ops}>"
+    return f"k_seq<{ops}, 6>" if arcs >= (1 << 25) and arcs >= 8 * n else f"k_seq<{ops}>"
 
 
 def cpu_leg(g, src, ref_step_edges):
@@ -295,7 +296,7 @@ def pagerank_main(args):
     kc = eng.to_host(dg, sx.SX_KCORE, kout)
     log(f"[bench] k-core {kms:.2f} ms/run ({klaunch} phase launches)")
     kcore = {"ms": round(kms, 3), "device_ms": round(kdev_ms, 3), "gteps": round(g.m / (kms / 1e3) / 1e9, 3),
-             "kernel": trav_kernel_name("kcore", 0, g.m), "launches": klaunch,
+             "kernel": trav_kernel_name("kcore", 0, g.m, g.n), "launches": klaunch,
              "levels_scanned": kst["ballot_iters"], "peel_steps": kst["iterations"],
              "avg_launch_us": round(1e3 * kdev_ms / klaunch, 3),
              "achieved_GBs": round(kbytes / (kdev_ms / 1e3) / 1e9, 2)}
@@ -398,7 +399,7 @@ def grid_main(args):
                          "launches": last[k]["launches"], "pull_iters": last[k]["pull_iters"],
                          "ballot_iters": last[k]["ballot_iters"], "edges_inspected": last[k]["edges_inspected"],
                          "vertex_expansions": last[k]["vertex_expansions"]} for k in per},
-        "roofline": {"bound": "hbm", "kernel": trav_kernel_name(dom, args.fused, g.m),
+        "roofline": {"bound": "hbm", "kernel": trav_kernel_name(dom, args.fused, g.m, g.n),
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "launches": phase_launches,
                      "avg_launch_us": round(avg_launch_us, 3),
@@ -507,7 +508,7 @@ def main():
     phase_launches = max(1, int(last[dom]["launches"]) - 1)
     avg_launch_us = 1e3 * algo_ms[dom] / phase_launches
     achieved = nbytes / phase_launches / (avg_launch_us / 1e6) / 1e9
-    kname = trav_kernel_name(dom, args.fused, g.m)
+    kname = trav_kernel_name(dom, args.fused, g.m, g.n)
 
     result = {
         "metric": "GTEPS BFS/SSSP R-MAT s22, bit-exact; learned-policy+batched vs heuristic speedup",

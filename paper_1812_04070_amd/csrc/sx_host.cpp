@@ -471,7 +471,10 @@ extern "C" sx_status sx_program_set_policy(sx_program *p, const sx_policy *pol) 
 // ---------------------------------------------------------- occupancy ---
 // Persistent grid (Section 5, Eq. 1): resident workgroups per CU for this
 // kernel x number of CUs.
-// Graphs from this many arcs up run the wide sequenced traversal kernel.
+// Graphs from this many arcs up, with at least 8 arcs per vertex, run the
+// wide sequenced traversal kernel; sparse graphs keep the unconstrained one
+// however large, since their thousands of small levels pay for its spills
+// on every level (4096^2 grid BFS: 160 ms wide, 47 ms on the 2048^2 grid).
 static const long long kBigGraphArcs = 1ll << 25;
 
 static int persistent_grid(sx_ctx *ctx, const void *kernel, int requested) {
@@ -706,8 +709,9 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   const bool fused = p->pol.fused == SX_FUSED;
   const bool sequenced = p->pol.fused == SX_SEQUENCED || p->pol.fused == SX_FUSE_AUTO;
   int grid;
-  // large graphs take the wide sequenced kernel (three workgroups per CU)
-  const int seq_kind = G->g.m >= kBigGraphArcs ? TK_SEQ_WIDE : TK_SEQ;
+  // large dense graphs take the wide sequenced kernel (three workgroups per CU)
+  const int seq_kind =
+      G->g.m >= kBigGraphArcs && G->g.m >= 8ll * G->g.n ? TK_SEQ_WIDE : TK_SEQ;
   if (sequenced) {
     grid = plain_grid(ctx, trav_kernel(seq_kind, sssp));
     if (p->pol.grid_wgs > 0) grid = std::min(grid, p->pol.grid_wgs);
