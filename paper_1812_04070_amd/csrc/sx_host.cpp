@@ -680,15 +680,18 @@ static Decision host_decide(const sx_ctx *ctx, const sx_policy &pol, Params &P, 
   return d;
 }
 
-// SX_DELTA_AUTO: buckets of about 40 mean arc weights on graphs with fewer
-// than 8 arcs per vertex (meshes and road-like graphs, thousands of
-// iterations: on the 4096^2 grid with weights in [1, 1000] the best widths
-// measured were 20,000-50,000), none on denser graphs, whose few iterations
-// buckets only multiply (R-MAT s22: every width tried was slower).
+// SX_DELTA_AUTO: buckets of about 40 mean arc weights on graphs of at least
+// 2^21 vertices with fewer than 8 arcs per vertex (meshes and road-like
+// graphs, thousands of iterations: on the 4096^2 grid with weights in
+// [1, 1000] the best widths measured were 20,000-50,000, and on the 2048^2
+// grid buckets save 30 %), none on denser graphs, whose few iterations
+// buckets only multiply (R-MAT s22: every width tried was slower), nor on
+// smaller ones, where the extra iterations cost more than the re-expansions
+// they save (1024^2 grid: 5 % slower).
 static sx_status auto_delta(sx_graph *G, hipStream_t st, unsigned *delta) {
   *delta = 0;
   const long long n = G->g.n, m = G->g.m;
-  if (!G->g.w || n <= 0 || m <= 0 || m >= 8 * n) return SX_OK;
+  if (!G->g.w || n < (1ll << 21) || m <= 0 || m >= 8 * n) return SX_OK;
   if (G->weight_sum < 0) {
     unsigned long long *d = (unsigned long long *)&G->w.ctrl->aux.v[4];
     HIP_TRY(weight_sum(G->g.w, m, d, st));

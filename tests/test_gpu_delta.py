@@ -82,22 +82,22 @@ def test_delta_cuts_relaxations_on_grid(engine):
     x0, st0 = run(engine, g, sx.SX_SSSP, s, None, dg=dg)
     announce("delta grid-128 delta=500")
     x1, st1 = run(engine, g, sx.SX_SSSP, s, None, dg=dg, sssp_delta=500)
-    announce("delta grid-128 automatic width")
+    announce("delta grid-128 automatic width (a graph this small stays unbucketed)")
     x2, st2 = run(engine, g, sx.SX_SSSP, s, None, dg=dg, sssp_delta=sx.SX_DELTA_AUTO)
     dg.close()
     np.testing.assert_array_equal(x0, ref)
     np.testing.assert_array_equal(x1, ref)
     np.testing.assert_array_equal(x2, ref)
-    print(f"[delta] grid-128 arcs inspected: none {st0['edges_inspected']} delta=500 {st1['edges_inspected']} "
-          f"auto {st2['edges_inspected']}; iterations {st0['iterations']} -> {st1['iterations']}, "
-          f"{st2['iterations']}")
+    print(f"[delta] grid-128 arcs inspected: none {st0['edges_inspected']} delta=500 {st1['edges_inspected']}; "
+          f"iterations {st0['iterations']} -> {st1['iterations']}")
     assert st1["edges_inspected"] < st0["edges_inspected"]
-    assert st2["edges_inspected"] < st0["edges_inspected"]
+    assert st2["iterations"] == st0["iterations"]
 
 
 def test_delta_auto_keeps_dense_graphs_unbucketed(engine):
     """The automatic width leaves graphs of 8+ arcs per vertex without
-    buckets: the same iterations as the plain run."""
+    buckets: the same iterations as the plain run (the full-size grid test
+    checks that it does bucket the 4096^2 grid)."""
     g = gen.rmat(14, seed=5, weights=(1, 64))
     assert g.m >= 8 * g.n
     s = gen.max_degree_vertex(g)

@@ -67,6 +67,10 @@ def test_grid4096(engine):
     x, st = run(engine, g, sx.SX_SSSP, 0, dg=dg)
     ref = oracle.sssp_g(g, 0)
     np.testing.assert_array_equal(x, ref)
+    announce("grid4096 sssp, automatic bucket width")
+    x, st_auto = run(engine, g, sx.SX_SSSP, 0, dg=dg, sssp_delta=sx.SX_DELTA_AUTO)
+    np.testing.assert_array_equal(x, ref)
+    assert st_auto["edges_inspected"] < st["edges_inspected"] // 10
     dg.close()
 
 
