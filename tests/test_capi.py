@@ -71,3 +71,35 @@ def test_errors_without_device():
     assert rc in (sx.SX_EHIP, sx.SX_EINVAL)
     assert sx.lib().sx_last_error()
     assert sx.lib().sx_status_str(sx.SX_EDEADLOCK)
+
+
+def test_struct_layouts_match_binding(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (a C program built against include/simdx.h prints them), and the
+    binding's constants equal the header's."""
+    import ctypes
+    import shutil
+    import paper_1812_04070_amd as sx
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    structs = [sx.sx_graph_desc, sx.sx_algo_params, sx.sx_policy, sx.sx_run_stats, sx.sx_query,
+               sx.sx_batch_config, sx.sx_kernel_info]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "simdx.h"', 'int main(void) {']
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for field, _ in st._fields_:
+            lines.append(f'  printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines.append('  printf("SX_DELTA_AUTO %u\\n", (unsigned)SX_DELTA_AUTO);')
+    lines.append('  return 0;\n}')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    for st in structs:
+        name = st.__name__
+        assert int(got[name]) == ctypes.sizeof(st), name
+        for field, _ in st._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(st, field).offset, f"{name}.{field}"
+    assert int(got["SX_DELTA_AUTO"]) == sx.SX_DELTA_AUTO
