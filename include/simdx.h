@@ -122,9 +122,10 @@ typedef enum { SX_BFS = 0, SX_SSSP = 1, SX_KCORE = 2, SX_PAGERANK = 3 } sx_algo;
  * B reaches them).  0 = no buckets: every listed vertex is expanded in every
  * iteration (plain frontier relaxation).  SX_DELTA_AUTO = the engine
  * chooses: 40 times the mean arc weight on graphs of at least 2^21 vertices
- * with fewer than 8 arcs per vertex, no buckets on denser or smaller graphs
- * (the weights are summed on the device once per graph, before the run's
- * timed region).  Results are identical for any
+ * with fewer than 8 arcs per vertex, engaging after 64 iterations (runs that
+ * end sooner stay unbucketed), no buckets on denser or smaller graphs (the
+ * weights are summed on the device once per graph, before the run's timed
+ * region).  Results are identical for any
  * value; it changes the work and the iteration count only.  Used by the
  * sequenced arrangement (SX_FUSE_AUTO / SX_SEQUENCED); the persistent and
  * unfused arrangements and batches relax without buckets, and a run that

@@ -523,6 +523,7 @@ static Params make_params(const sx_program *p, const sx_graph *G, int grid) {
   // buckets, each bucket takes at most (its vertices + 1) rounds: 2n + 4.
   const bool seq_arr = p->pol.fused == SX_SEQUENCED || p->pol.fused == SX_FUSE_AUTO;
   P.delta = p->ap.algo == SX_SSSP && seq_arr ? p->ap.sssp_delta : 0u;
+  P.delta_after = 0;
   P.max_iters = G ? (P.delta ? (int)std::min<long long>(2ll * G->g.n + 4, INT_MAX / 2) : G->g.n + 2)
                   : INT_MAX / 2;
   P.pr_d = p->ap.pr_damping;
@@ -680,9 +681,9 @@ static Decision host_decide(const sx_ctx *ctx, const sx_policy &pol, Params &P, 
   return d;
 }
 
-// SX_DELTA_AUTO: buckets of about 40 mean arc weights on graphs of at least
-// 2^21 vertices with fewer than 8 arcs per vertex (meshes and road-like
-// graphs, thousands of iterations: on the 4096^2 grid with weights in
+// SX_DELTA_AUTO: buckets of about 40 mean arc weights, from iteration 64 on,
+// on graphs of at least 2^21 vertices with fewer than 8 arcs per vertex
+// (meshes and road-like graphs, thousands of iterations: on the 4096^2 grid with weights in
 // [1, 1000] the best widths measured were 20,000-50,000, and on the 2048^2
 // grid buckets save 30 %), none on denser graphs, whose few iterations
 // buckets only multiply (R-MAT s22: every width tried was slower), nor on
@@ -736,6 +737,10 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   if (sssp && a.P.delta == SX_DELTA_AUTO) {
     sx_status s = auto_delta(G, st, &a.P.delta);
     if (s != SX_OK) return s;
+    // a run that ends within this many iterations is not high-diameter:
+    // it keeps the plain relaxation (sparse random and R-MAT graphs with
+    // 4-6 arcs per vertex lost 5-13 % to buckets from the first iteration)
+    a.P.delta_after = 64;
   }
   int launches = 0;
   HIP_TRY(hipEventRecord(G->ev0, st));

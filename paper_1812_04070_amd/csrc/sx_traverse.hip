@@ -140,6 +140,8 @@ SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   long long edges = 0;
   unsigned lowest = 0xFFFFFFFFu;
   const bool buckets = !Ops::kVote && B != 0xFFFFFFFFu;
+  // the smallest distance is also kept before the buckets engage
+  const bool record = !Ops::kVote && P.delta != 0u;
   // a far vertex (distance >= B) reads as -1, which every visitor skips
   auto near = [&](int v) -> int {
     if constexpr (Ops::kVote) {
@@ -211,7 +213,7 @@ SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   visit_small(g.n, [&](unsigned i) { return near(cur.small(i)); }, T.cnt[BIN_SMALL], g.off, g.idx, op,
               gw, nw, lds.small[wave_in_wg()]);
   bins_end(lds.bins, st, a.w.rec + ((it + 1) % 3), vg.bid);   // ends with a barrier
-  if (buckets) {
+  if (record) {
     const unsigned m = wave_min_u(lowest);
     if (lane_id() == 0) lds.cnt[wave_in_wg()] = m;
     __syncthreads();
@@ -468,6 +470,7 @@ struct RunState {
   PolicyState ps;
   Params P;
   unsigned B = 0xFFFFFFFFu;     // delta-stepping bound (sequenced SSSP)
+  unsigned dropped = 0;         // 1: buckets dropped for the rest of the run
 };
 
 struct LdsPolicy {
@@ -729,7 +732,7 @@ enum : unsigned { PH_PUSH = 0, PH_BALLOT = 1, PH_PULL_SCAN = 2, PH_PULL = 3 };
 // seq line: [0] phase [1] iteration [2,3] unexplored arcs [4] previous
 // frontier size [6,7] activated so far [8] t1 [9] t2 [10] pulling [11] a
 // decision is due [12] the push lists come from a ballot scan [13] the
-// delta-stepping bound (0: not set yet)
+// delta-stepping bound (0: not set yet) [14] buckets dropped (pull steps)
 SX_DEV void seq_store(Line &l, unsigned phase, const RunState &s, unsigned pulling, unsigned due,
                       unsigned rebuilt) {
   store_relaxed(&l.v[0], phase);
@@ -743,6 +746,7 @@ SX_DEV void seq_store(Line &l, unsigned phase, const RunState &s, unsigned pulli
   store_relaxed(&l.v[11], due);
   store_relaxed(&l.v[12], rebuilt);
   store_relaxed(&l.v[13], s.B);
+  store_relaxed(&l.v[14], s.dropped);
 }
 
 // kMinWaves = 6 (the wide form, for large graphs): at least six wavefronts
@@ -772,7 +776,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMi
   unsigned pulling = in[10];
   const unsigned due = in[11];
   unsigned rebuilt = in[12];
-  s.B = in[13] ? in[13] : (a.P.delta ? a.P.delta : 0xFFFFFFFFu);
+  s.B = in[13] ? in[13] : (a.P.delta && a.P.delta_after == 0 ? a.P.delta : 0xFFFFFFFFu);
+  s.dropped = in[14];
   if (phase >= SEQ_DONE) {
     if (lead) seq_store(out, phase, s, pulling, 0, rebuilt);
     return;
@@ -797,12 +802,16 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMi
     // delta-stepping: once no listed vertex lies below the bound, move it to
     // the end of the bucket holding the smallest listed distance (empty
     // buckets are skipped); pull steps relax without buckets
-    if (s.B != 0xFFFFFFFFu) {
+    // (buckets that engage late start at the bucket of the smallest
+    // listed distance)
+    if (a.P.delta && !s.dropped) {
       if (pulling || d.to_pull) {
         s.B = 0xFFFFFFFFu;
+        s.dropped = 1;
       } else {
         const unsigned lo = load_relaxed(&C->aux.v[(s.it + 1) % 3]);
-        if (lo != 0xFFFFFFFFu && lo >= s.B) {
+        const bool engage = s.B == 0xFFFFFFFFu && s.it + 1 >= a.P.delta_after;
+        if (lo != 0xFFFFFFFFu && (engage || (s.B != 0xFFFFFFFFu && lo >= s.B))) {
           const unsigned long long nb = ((unsigned long long)lo / a.P.delta + 1ull) * a.P.delta;
           s.B = nb >= 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned)nb;
         }

@@ -107,6 +107,7 @@ struct Params {
   int learned;                  // 1: the policy MLP decides (sx_policy.hpp)
   int bins_fixed;               // 1: the caller fixed t1 / t2
   unsigned delta;               // SSSP bucket width (0: no buckets)
+  int delta_after;              // iterations run before the buckets engage
 };
 
 struct TravArgs {

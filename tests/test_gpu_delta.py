@@ -132,3 +132,23 @@ def test_delta_same_as_plain_on_reordered_rmat(engine):
         x, _ = run(engine, g, sx.SX_SSSP, s, None, dg=dg, sssp_delta=delta)
         np.testing.assert_array_equal(x, ref)
     dg.close()
+
+
+def test_delta_auto_engages_late(engine):
+    """On a grid of 2^21+ vertices the automatic width engages after the
+    first 64 iterations, from the bucket of the smallest listed distance;
+    exact under every filter, and far fewer arcs than without buckets."""
+    g = gen.grid(1500, 0.1, seed=13, weights=(1, 1000))
+    assert g.n >= 1 << 21 and g.m < 8 * g.n
+    s = gen.max_degree_vertex(g)
+    ref = oracle.sssp_g(g, s)
+    dg = engine.load(g)
+    announce("delta grid-1500 without buckets")
+    x0, st0 = run(engine, g, sx.SX_SSSP, s, None, dg=dg)
+    np.testing.assert_array_equal(x0, ref)
+    for pname, pol in POLICIES[:4]:
+        announce(f"delta grid-1500 automatic width {pname}")
+        x, st = run(engine, g, sx.SX_SSSP, s, pol, dg=dg, sssp_delta=sx.SX_DELTA_AUTO)
+        np.testing.assert_array_equal(x, ref)
+        assert st["edges_inspected"] < st0["edges_inspected"] // 4, pname
+    dg.close()
