@@ -49,6 +49,8 @@ def lib():
                            ("sxo_sssp_rounds", [ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp, vp, ctypes.c_int32]),
                            ("sxo_kcore_bz", [ctypes.c_int32, vp, vp, vp, vp, vp]),
                            ("sxo_kcore_peel", [ctypes.c_int32, vp, vp, vp, vp, vp]),
+                           ("sxo_kcore_member", [ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32, vp]),
+                           ("sxo_wcc", [ctypes.c_int32, vp, vp, vp]),
                            ("sxo_pagerank", [ctypes.c_int32, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp])]:
             f = getattr(L, name)
             f.argtypes = args
@@ -119,6 +121,23 @@ def kcore_peel(n, offsets, indices, in_offsets=None, in_indices=None):
     return out
 
 
+def kcore_member(n, offsets, indices, k, in_offsets=None, in_indices=None):
+    """1 where the vertex lies in the k-core (Section 6), else 0."""
+    off, idx = _c(offsets, np.int32), _c(indices, np.int32)
+    ino, ini = _c(in_offsets, np.int32), _c(in_indices, np.int32)
+    out = np.empty(n, dtype=np.int32)
+    _check(lib().sxo_kcore_member(n, _p(off), _p(idx), _p(ino), _p(ini), int(k), _p(out)), "kcore_member")
+    return out
+
+
+def wcc(n, offsets, indices):
+    """Smallest vertex id of each vertex's connected component (union-find)."""
+    off, idx = _c(offsets, np.int32), _c(indices, np.int32)
+    out = np.empty(n, dtype=np.int32)
+    _check(lib().sxo_wcc(n, _p(off), _p(idx), _p(out)), "wcc")
+    return out
+
+
 def pagerank(n, offsets, in_offsets, in_indices, d=0.85, iters=20):
     off = _c(offsets, np.int32)
     ino, ini = _c(in_offsets, np.int32), _c(in_indices, np.int32)
@@ -141,6 +160,26 @@ def kcore_g(g):
     if g.directed:
         return kcore_bz(g.n, g.offsets, g.indices, g.in_offsets, g.in_indices)
     return kcore_bz(g.n, g.offsets, g.indices)
+
+
+def kcore_member_g(g, k):
+    if g.directed:
+        return kcore_member(g.n, g.offsets, g.indices, k, g.in_offsets, g.in_indices)
+    return kcore_member(g.n, g.offsets, g.indices, k)
+
+
+def wcc_g(g):
+    """Weak components: a directed graph's arcs are taken without direction."""
+    if g.directed:
+        # union of the out- and in-rows as one undirected arc list
+        src = np.concatenate([np.repeat(np.arange(g.n), np.diff(g.offsets)),
+                              np.repeat(np.arange(g.n), np.diff(g.in_offsets))])
+        dst = np.concatenate([g.indices, g.in_indices])
+        order = np.argsort(src, kind="stable")
+        o = np.zeros(g.n + 1, dtype=np.int64)
+        np.add.at(o, src + 1, 1)
+        return wcc(g.n, np.cumsum(o), dst[order])
+    return wcc(g.n, g.offsets, g.indices)
 
 
 def pagerank_g(g, d=0.85, iters=20):

@@ -19,6 +19,13 @@
  *            core(v) = largest k with v in the k-core.  Batagelj-Zaversnik
  *            bucket algorithm ("An O(m) algorithm for cores decomposition of
  *            networks", 2003) and naive level-by-level peeling.
+ *            Fixed-k membership, the paper's own k-core (Section 6, k = 16;
+ *            k = 32 in its run-time comparison): repeatedly delete every
+ *            vertex whose degree is below k; the survivors form the k-core.
+ *   WCC      Section 3.2 (connected components with a voting / minimum
+ *            combine): the label of a vertex is the smallest vertex id in
+ *            its weakly connected component (arcs taken without direction),
+ *            by union-find.
  *   PageRank Section 6 (pull, sum of in-neighbour contributions): 20
  *            synchronous iterations in fp64, x0 = 1/n,
  *            x'(v) = (1-d)/n + d * (sum_{u->v} x(u)/outdeg(u) + D/n),
@@ -287,6 +294,60 @@ int sxo_kcore_peel(int32_t n, const int32_t *off, const int32_t *idx,
         }
     }
     free(deg); free(alive); free(cur);
+    return 0;
+}
+
+/* Membership in the k-core for one k (Section 6): a FIFO queue of vertices
+ * whose degree fell below k; each is deleted once and lowers the degree of
+ * every neighbour still present.  member[v] = 1 for the survivors, else 0. */
+int sxo_kcore_member(int32_t n, const int32_t *off, const int32_t *idx,
+                     const int32_t *in_off, const int32_t *in_idx, int32_t k, int32_t *member) {
+    if (n < 0 || k < 0) return -1;
+    if (n == 0) return 0;
+    int32_t *deg = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!deg || !queue) { free(deg); free(queue); return -2; }
+    int64_t head = 0, tail = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        deg[v] = total_degree(off, in_off, v);
+        member[v] = 1;
+        if (deg[v] < k) { member[v] = 0; queue[tail++] = v; }
+    }
+    while (head < tail) {
+        int32_t v = queue[head++];
+        for (int pass = 0; pass < 2; ++pass) {
+            const int32_t *o = pass ? in_off : off, *x = pass ? in_idx : idx;
+            if (!o) continue;
+            for (int64_t e = o[v]; e < o[v + 1]; ++e) {
+                int32_t u = x[e];
+                if (!member[u]) continue;
+                if (--deg[u] < k) { member[u] = 0; queue[tail++] = u; }
+            }
+        }
+    }
+    free(deg); free(queue);
+    return 0;
+}
+
+/* ---------------------------------------------------------------- WCC --- */
+/* Union-find with path halving over every arc (CSR, and the CSC of a
+ * directed graph, which holds the same arcs reversed); the label of a
+ * component is its smallest vertex id (the root is always the smaller id). */
+static int32_t uf_find(int32_t *parent, int32_t v) {
+    while (parent[v] != v) { parent[v] = parent[parent[v]]; v = parent[v]; }
+    return v;
+}
+
+int sxo_wcc(int32_t n, const int32_t *off, const int32_t *idx, int32_t *label) {
+    if (n < 0) return -1;
+    for (int32_t v = 0; v < n; ++v) label[v] = v;
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+            int32_t a = uf_find(label, v), b = uf_find(label, idx[e]);
+            if (a < b) label[b] = a;
+            else if (b < a) label[a] = b;
+        }
+    for (int32_t v = 0; v < n; ++v) label[v] = uf_find(label, v);
     return 0;
 }
 

@@ -173,3 +173,34 @@ def all_graphs(n):
     pairs = list(itertools.combinations(range(n), 2))
     for mask in range(1 << len(pairs)):
         yield [pairs[i] for i in range(len(pairs)) if (mask >> i) & 1]
+
+
+def brute_kcore_member(n, offsets, indices, k, in_offsets=None, in_indices=None):
+    """Membership in the k-core straight from its definition: the union of
+    every vertex set S whose induced subgraph gives each vertex of S at least
+    k incident arcs inside S (in- plus out-arcs for a digraph).  Enumerates
+    all 2^n subsets."""
+    A = np.zeros((n, n), dtype=np.int64)
+    for v in range(n):
+        for e in range(offsets[v], offsets[v + 1]):
+            A[v, indices[e]] += 1
+    Ad = A + A.T if in_offsets is not None else A
+    member = np.zeros(n, dtype=np.int64)
+    for mask in range(1, 1 << n):
+        S = np.array([(mask >> i) & 1 for i in range(n)], dtype=bool)
+        if Ad[np.ix_(S, S)].sum(axis=1).min() >= k:
+            member[S] = 1
+    return member
+
+
+def closure_min_label(n, offsets, indices):
+    """Smallest vertex reachable from each vertex when arcs are taken in
+    both directions: Floyd-Warshall transitive closure of the symmetrised
+    adjacency, then the first reachable id per row."""
+    R = np.eye(n, dtype=bool)
+    for v in range(n):
+        for e in range(offsets[v], offsets[v + 1]):
+            R[v, indices[e]] = R[indices[e], v] = True
+    for k in range(n):
+        R = R | (R[:, k:k + 1] & R[k:k + 1, :])
+    return np.array([int(np.nonzero(R[v])[0][0]) for v in range(n)], dtype=np.int64)

@@ -253,6 +253,74 @@ def test_networkx_cross_check():
     assert np.array_equal(oracle.kcore_g(gu), np.array([ref[v] for v in range(gu.n)]))
 
 
+# ---------------------------------------- fixed-k k-core and components ----
+
+def test_exhaustive_5_vertex_member_and_wcc():
+    """All 1,024 graphs on 5 vertices: k-core membership for k = 0..5 against
+    subset enumeration, and component labels against the transitive closure."""
+    for edges in pins.all_graphs(5):
+        g = _g(5, edges)
+        for k in range(6):
+            assert np.array_equal(oracle.kcore_member(5, g.offsets, g.indices, k),
+                                  pins.brute_kcore_member(5, g.offsets, g.indices, k)), (edges, k)
+        assert np.array_equal(oracle.wcc(5, g.offsets, g.indices), pins.closure_min_label(5, g.offsets, g.indices))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_member_and_wcc_random_digraphs(seed):
+    """Directed graphs (degree = in + out; components ignore direction)."""
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(3, 12))
+    g = gen.random_graph(n, float(rng.uniform(0.1, 0.4)), seed=seed, directed=True)
+    for k in range(0, 7):
+        assert np.array_equal(oracle.kcore_member_g(g, k),
+                              pins.brute_kcore_member(n, g.offsets, g.indices, k, g.in_offsets, g.in_indices))
+    assert np.array_equal(oracle.wcc_g(g), pins.closure_min_label(n, g.offsets, g.indices))
+
+
+def test_member_and_wcc_closed_forms():
+    # K_6: every vertex has degree 5 -> in the k-core exactly for k <= 5
+    kn = _g(6, [(i, j) for i in range(6) for j in range(i + 1, 6)])
+    for k in range(8):
+        assert np.array_equal(oracle.kcore_member(6, kn.offsets, kn.indices, k), np.full(6, int(k <= 5)))
+    # cycle: the 2-core is the whole cycle, the 3-core empty; a pendant path
+    # hanging off it is peeled away for k = 2
+    cyc = _g(7, [(0, 1), (1, 2), (2, 3), (3, 0), (3, 4), (4, 5), (5, 6)])
+    assert np.array_equal(oracle.kcore_member(7, cyc.offsets, cyc.indices, 2), [1, 1, 1, 1, 0, 0, 0])
+    assert np.array_equal(oracle.kcore_member(7, cyc.offsets, cyc.indices, 3), np.zeros(7))
+    assert np.array_equal(oracle.kcore_member(7, cyc.offsets, cyc.indices, 1), np.ones(7))
+    # components: edgeless -> identity; two disjoint paths; a path is one label
+    assert np.array_equal(oracle.wcc(4, np.zeros(5, np.int32), np.zeros(0, np.int32)), [0, 1, 2, 3])
+    two = _g(7, [(6, 4), (4, 2), (5, 3), (3, 1), (1, 0)])
+    assert np.array_equal(oracle.wcc(7, two.offsets, two.indices), [0, 0, 2, 0, 2, 0, 2])
+    path = _g(50, [(i, i + 1) for i in range(49)])
+    assert np.array_equal(oracle.wcc(50, path.offsets, path.indices), np.zeros(50))
+
+
+def test_member_equals_decomposition_rmat16():
+    """On R-MAT s16 the fixed-k peel and the bucket decomposition (an
+    algorithm that never deletes below a fixed k) agree for every k."""
+    g = gen.rmat(16, seed=1)
+    c = oracle.kcore_g(g)
+    for k in (1, 2, 8, 16, 32, 64, int(c.max()), int(c.max()) + 1):
+        assert np.array_equal(oracle.kcore_member_g(g, k), (c >= k).astype(np.int32)), k
+
+
+def test_wcc_scipy_cross_check():
+    """Component partition against scipy.sparse.csgraph.connected_components
+    (a library routine: same partition, labels = smallest id)."""
+    sp = pytest.importorskip("scipy.sparse")
+    csg = pytest.importorskip("scipy.sparse.csgraph")
+    for g in (gen.rmat(14, seed=3), gen.grid(96, 0.45, seed=5), gen.random_graph(2000, 0.0008, seed=9)):
+        A = sp.csr_matrix((np.ones(g.m), g.indices, g.offsets), shape=(g.n, g.n))
+        nc, lab = csg.connected_components(A, directed=False)
+        mine = oracle.wcc_g(g)
+        first = np.full(nc, g.n)
+        np.minimum.at(first, lab, np.arange(g.n))
+        assert np.array_equal(mine, first[lab])
+        assert np.unique(mine).size == nc
+
+
 # ------------------------------------------------- planted mistakes fail ----
 
 def test_pins_catch_planted_mistakes():
@@ -284,6 +352,22 @@ def test_pins_catch_planted_mistakes():
     c[np.argmax(c)] += 1
     with pytest.raises(AssertionError):
         pins.kcore_certificate(gu.n, gu.offsets, gu.indices, c)
+    # k-core membership with "degree <= k" as the deletion rule fails the
+    # subset enumeration; component labels taken as the largest id fail the
+    # closure
+    g5 = _g(5, [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4)])
+    deg = np.diff(g5.offsets)
+    member = np.ones(5, dtype=np.int64)
+    changed = True
+    while changed:
+        changed = False
+        for v in range(5):
+            if member[v] and sum(member[u] for u in g5.indices[g5.offsets[v]:g5.offsets[v + 1]]) <= 2:
+                member[v] = 0
+                changed = True
+    assert not np.array_equal(member, pins.brute_kcore_member(5, g5.offsets, g5.indices, 2))
+    lab = pins.closure_min_label(5, g5.offsets, g5.indices)
+    assert not np.array_equal(np.full(5, 4), lab)
     # a BFS depth off by one fails the certificate
     d = oracle.bfs_g(gu, 0).copy()
     d[np.argmax(d)] += 1
