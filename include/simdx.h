@@ -7,8 +7,10 @@
  * The problem statement the calls follow (Section 2.1): a graph G = (V, E, w)
  * with vertex metadata ("the distance array") is computed on iteratively,
  * from a source until no vertex is updated.  An algorithm is the triple
- * Active / Compute / Combine of Section 3.2; this library ships four of them
- * (BFS, SSSP, k-core, PageRank, Section 6) and a program selects one.
+ * Active / Compute / Combine of Section 3.2; this library ships five of them
+ * (BFS, SSSP, k-core, PageRank of Section 6, and connected components, which
+ * Section 3.2 names among the algorithms of its Combine step) and a program
+ * selects one.
  *
  * Conventions shared by every call
  *  - Every call returns sx_status; SX_OK is 0, errors are negative.  Output
@@ -98,7 +100,7 @@ void sx_graph_destroy(sx_graph *g);
 sx_status sx_graph_info(const sx_graph *g, int32_t *n, int64_t *m, int32_t *directed, int32_t *weighted);
 
 /* ----------------------------------------------------------- programs --- */
-/* The four ACC programs (Section 3.2 for the Active/Compute/Combine triple,
+/* The five ACC programs (Section 3.2 for the Active/Compute/Combine triple,
  * Section 6 for the algorithms):
  *  SX_BFS      active = newly visited; compute = level + 1; combine = vote
  *              (any one update suffices).  Output int32 depth, -1 unreached.
@@ -110,11 +112,22 @@ sx_status sx_graph_info(const sx_graph *g, int32_t *n, int64_t *m, int32_t *dire
  *              the paper's fixed-k membership to the full decomposition:
  *              output int32 core number (v is in the k-core iff core >= k).
  *              Degree counts in- plus out-arcs for a directed graph.
+ *              With kcore_k = k > 0 the program computes the paper's own
+ *              k-core instead (Section 6): vertices of degree below k are
+ *              deleted until none is left, a neighbour already below k is not
+ *              decremented further, and the output is int32 membership, 1 for
+ *              the vertices of the k-core and 0 for the others.
  *  SX_PAGERANK all vertices active; compute = rank(u)/outdeg(u); combine =
  *              sum; pr_iters synchronous iterations with damping pr_damping,
  *              uniform start 1/n, rank of vertices without out-arcs spread
- *              uniformly.  Output float rank (FP32 arithmetic). */
-typedef enum { SX_BFS = 0, SX_SSSP = 1, SX_KCORE = 2, SX_PAGERANK = 3 } sx_algo;
+ *              uniformly.  Output float rank (FP32 arithmetic).
+ *  SX_WCC      connected components by minimum-label propagation: every
+ *              vertex starts active with its own id as label; compute =
+ *              label(v); combine = minimum.  Output int32 label = the
+ *              smallest vertex id of the vertex's component (unique, so
+ *              comparable bit for bit).  Undirected graphs only
+ *              (SX_EUNSUPPORTED otherwise); the source is ignored (pass -1). */
+typedef enum { SX_BFS = 0, SX_SSSP = 1, SX_KCORE = 2, SX_PAGERANK = 3, SX_WCC = 4 } sx_algo;
 
 /* sssp_delta: bucket width of delta-stepping for SX_SSSP (Section 3.3: the
  * vertices whose distances lie in the lowest non-empty bucket [B - delta, B)
@@ -135,6 +148,8 @@ typedef struct {
   float pr_damping;      /* PageRank damping d (0.85)                          */
   int32_t pr_iters;      /* PageRank iterations (20)                           */
   uint32_t sssp_delta;   /* SSSP bucket width (0 = none)                       */
+  int32_t kcore_k;       /* SX_KCORE: 0 = full decomposition (core numbers);
+                            k > 0 = membership in the k-core (1 / 0)          */
 } sx_algo_params;
 #define SX_DELTA_AUTO 0xFFFFFFFFu
 
@@ -154,8 +169,12 @@ void sx_program_destroy(sx_program *p);
  *  online_cap SX_FILTER_JIT only: online-filter capacity in entries per
  *             wavefront and bin (a workgroup of 8 wavefronts overflows past
  *             8 x online_cap entries in a bin); 0 = the workgroup's region
- *  fused      SX_FUSED (persistent kernels + software global barrier,
- *             Section 5) | SX_UNFUSED (one launch per phase and iteration,
+ *  fused      SX_FUSED (selective fusion, Section 5: one persistent kernel
+ *             per direction + software global barrier; a direction change
+ *             launches the other kernel) | SX_FUSED_ALL (all fusion, Table
+ *             table-compile: both directions in one persistent kernel that
+ *             switches in place; BFS, SSSP and WCC, other programs take
+ *             SX_FUSED) | SX_UNFUSED (one launch per phase and iteration,
  *             the host deciding between launches) | SX_SEQUENCED (one launch
  *             per phase, decisions taken on the device at the start of the
  *             next launch, launches enqueued ahead: the kernel boundary is
@@ -165,7 +184,7 @@ void sx_program_destroy(sx_program *p);
  *             sx_policy_load_mlp first)                                       */
 enum { SX_DIR_AUTO = 0, SX_DIR_PUSH = 1, SX_DIR_PULL = 2 };
 enum { SX_FILTER_JIT = 0, SX_FILTER_ONLINE = 1, SX_FILTER_BALLOT = 2 };
-enum { SX_FUSE_AUTO = 0, SX_FUSED = 1, SX_UNFUSED = 2, SX_SEQUENCED = 3 };
+enum { SX_FUSE_AUTO = 0, SX_FUSED = 1, SX_UNFUSED = 2, SX_SEQUENCED = 3, SX_FUSED_ALL = 4 };
 enum { SX_POLICY_HEURISTIC = 0, SX_POLICY_LEARNED = 1 };
 
 typedef struct {
@@ -177,6 +196,9 @@ typedef struct {
   int32_t fused;
   int32_t policy;
   int32_t grid_wgs;      /* persistent grid size; 0 = occupancy x CUs (Eq. 1) */
+  int32_t watchdog_us;   /* how long one wait at the software global barrier
+                            may last before the run fails with SX_EDEADLOCK,
+                            in microseconds of wall-clock time; 0 = 2 s      */
 } sx_policy;
 
 sx_status sx_program_set_policy(sx_program *p, const sx_policy *pol);
@@ -192,6 +214,18 @@ typedef struct {
   int64_t vertex_expansions; /* worklist entries processed                    */
   double device_ms;          /* stream time of the run (HIP events)           */
   int64_t scan_entries;      /* list entries read by k-core level scans       */
+  double barrier_wait_ms;    /* global-barrier stall: the time a workgroup
+                                waits for the others, averaged over the run's
+                                workgroups.  Persistent kernels: arrival to
+                                release at each software barrier.  Sequenced
+                                arrangement (the kernel boundary is the
+                                barrier): end of a workgroup's phase to the
+                                start of the same workgroup slot's next phase.
+                                Wall-clock stamps on the device; 0 for the
+                                one-phase arrangement                         */
+  int32_t policy_evals;      /* decisions the learned network took           */
+  float policy_x[8];         /* features and outputs of the last of them     */
+  float policy_y[4];
 } sx_run_stats;
 
 /* Run program p on graph g.  source: start vertex (BFS, SSSP), ignored (pass
@@ -202,6 +236,33 @@ typedef struct {
  * d_out), SX_EDEADLOCK, SX_EOVERFLOW, SX_EHIP. */
 sx_status sx_run(sx_program *p, const sx_graph *g, int32_t source, void *d_out,
                  void *hip_stream, sx_run_stats *stats);
+
+/* ------------------------------------------------ frontier inspection --- */
+/* Run BFS, SSSP or WCC for at most `iterations` iterations in the one-phase
+ * arrangement (SX_UNFUSED, whatever the program's policy says about fusion;
+ * direction, filter and bins as the policy says) and stop before iteration
+ * `iterations`, leaving the worklist that iteration would process in the
+ * graph's workspace for sx_frontier_get.  d_out holds the vertex state at
+ * that point.  Iteration 0 processes the source (WCC: every vertex).
+ * Errors: as sx_run; SX_EUNSUPPORTED for renumbered graphs. */
+sx_status sx_run_iterations(sx_program *p, const sx_graph *g, int32_t source, void *d_out,
+                            void *hip_stream, int32_t iterations, sx_run_stats *stats);
+
+/* The worklist left by the last sx_run_iterations on g, as the next push
+ * iteration reads it (Section 4): for each bin in turn (0 small, 1 medium, 2
+ * large), the workgroups' regions in workgroup order; a large vertex appears
+ * once.  vertices / bins: host arrays of cap entries (bins[i] = the bin of
+ * vertices[i]); *count = the list's length (may exceed cap: only cap entries
+ * are written).  *from_ballot (nullable) = 1 when the list was built by the
+ * ballot filter (then each bin is sorted and unique), 0 for the online
+ * filter (order of arrival).  words (nullable, nwords entries): the ballot
+ * filter's words of its last scan, OR-ed over the bins: bit j of word i
+ * stands for vertex 64 i + j.  SX_ESTATE when the run stopped before a pull
+ * iteration (no push list) or no such run was made.  Synchronises the
+ * stream. */
+sx_status sx_frontier_get(const sx_graph *g, int32_t *vertices, int32_t *bins, int32_t cap,
+                          int32_t *count, int32_t *from_ballot, uint64_t *words, int64_t nwords,
+                          void *hip_stream);
 
 /* Copy a vertex array (n elements of the algorithm's output type) from the
  * device to host memory; synchronises the stream. */
@@ -250,9 +311,12 @@ sx_status sx_batch_autotune(sx_ctx *ctx, const sx_query *queries, int32_t nq, co
 
 /* Library/build facts for the measurement harness: kernel register use and
  * persistent-grid sizing (the Eq. 1 analogue).  name: one of "bfs_fused",
- * "sssp_fused", "bfs_seq", "sssp_seq", "bfs_seq_wide", "sssp_seq_wide" (the
- * sequenced kernels for graphs of 2^25 arcs or more, built for three
- * workgroups per CU), "bfs_push_step", "bfs_pull_step", "sssp_push_step",
+ * "sssp_fused", "wcc_fused" (the push kernels of selective fusion),
+ * "bfs_fused_pull", "sssp_fused_pull", "wcc_fused_pull" (its pull kernels),
+ * "bfs_fused_all", "sssp_fused_all", "wcc_fused_all" (all fusion), "bfs_seq", "sssp_seq", "wcc_seq",
+ * "bfs_seq_wide", "sssp_seq_wide", "wcc_seq_wide" (the sequenced kernels for
+ * graphs of 2^25 arcs or more, built for three workgroups per CU),
+ * "bfs_push_step", "bfs_pull_step", "sssp_push_step",
  * "sssp_pull_step", "ballot_scan", "pull_scan", "kcore_fused", "kcore_seq",
  * "pagerank_fused", "batch".
  * Errors: SX_EINVAL (unknown name), SX_EHIP. */
@@ -285,9 +349,17 @@ sx_status sx_kernel_info_get(sx_ctx *ctx, const char *name, sx_kernel_info *out)
  * SX_MLP_NPARAMS. */
 sx_status sx_policy_load_mlp(sx_ctx *ctx, const float *params, int64_t nparams);
 
-/* Batch inference: d_x device [n][8] -> d_y device [n][4]. */
+/* Batch inference: d_x device [n][8] -> d_y device [n][4], one wavefront
+ * per sample through the same device function the engine's in-kernel
+ * decisions evaluate. */
 sx_status sx_mlp_forward(sx_ctx *ctx, const float *d_params, const float *d_x, int32_t n, float *d_y,
                          void *hip_stream);
+
+/* The same inference on the host, as the one-phase arrangement's host-side
+ * decisions evaluate it: host arrays params [SX_MLP_NPARAMS], x [n][8],
+ * y [n][4].  Pure host arithmetic (no device call).  SX_EINVAL on NULL or
+ * n < 0. */
+sx_status sx_mlp_forward_host(const float *params, const float *x, int32_t n, float *y);
 
 /* Mean loss over n samples and its gradient (device pointers).  d_target and
  * d_mask are [n][4]: outputs 0 and 1 take a binary cross-entropy on logits

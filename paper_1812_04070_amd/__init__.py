@@ -29,22 +29,23 @@ SX_OK, SX_EINVAL, SX_ENOMEM, SX_EHIP, SX_EUNSUPPORTED, SX_EDEADLOCK, SX_EOVERFLO
 # graph flags
 SX_UNDIRECTED, SX_DEVICE_PTRS, SX_VALIDATE, SX_REORDER = 1, 2, 4, 8
 # algorithms
-SX_BFS, SX_SSSP, SX_KCORE, SX_PAGERANK = 0, 1, 2, 3
+SX_BFS, SX_SSSP, SX_KCORE, SX_PAGERANK, SX_WCC = 0, 1, 2, 3, 4
 # policy enums
 SX_DIR_AUTO, SX_DIR_PUSH, SX_DIR_PULL = 0, 1, 2
 SX_FILTER_JIT, SX_FILTER_ONLINE, SX_FILTER_BALLOT = 0, 1, 2
-SX_FUSE_AUTO, SX_FUSED, SX_UNFUSED, SX_SEQUENCED = 0, 1, 2, 3
+SX_FUSE_AUTO, SX_FUSED, SX_UNFUSED, SX_SEQUENCED, SX_FUSED_ALL = 0, 1, 2, 3, 4
 SX_POLICY_HEURISTIC, SX_POLICY_LEARNED = 0, 1
 
-ALGOS = {"bfs": SX_BFS, "sssp": SX_SSSP, "kcore": SX_KCORE, "pagerank": SX_PAGERANK}
+ALGOS = {"bfs": SX_BFS, "sssp": SX_SSSP, "kcore": SX_KCORE, "pagerank": SX_PAGERANK, "wcc": SX_WCC}
 
 EXPORTED = [
     "sx_ctx_create", "sx_ctx_destroy", "sx_status_str", "sx_last_error",
     "sx_graph_load", "sx_graph_destroy", "sx_graph_info",
     "sx_program_register", "sx_program_destroy", "sx_program_set_policy",
     "sx_run", "sx_read_vertices", "sx_kernel_info_get", "sx_eq1_ctas",
-    "sx_policy_load_mlp", "sx_mlp_forward", "sx_mlp_loss_grad", "sx_mlp_adam",
+    "sx_policy_load_mlp", "sx_mlp_forward", "sx_mlp_forward_host", "sx_mlp_loss_grad", "sx_mlp_adam",
     "sx_policy_collect", "sx_run_batch", "sx_batch_autotune",
+    "sx_run_iterations", "sx_frontier_get",
 ]
 SX_POLICY_ARMS = 6
 ARM_THRESHOLDS = [None, (16, 256), (64, 256), (64, 1024), (256, 2048), None]
@@ -61,24 +62,31 @@ class sx_graph_desc(ctypes.Structure):
 
 class sx_algo_params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int), ("pr_damping", ctypes.c_float), ("pr_iters", ctypes.c_int32),
-                ("sssp_delta", ctypes.c_uint32)]
+                ("sssp_delta", ctypes.c_uint32), ("kcore_k", ctypes.c_int32)]
 
 
 class sx_policy(ctypes.Structure):
     _fields_ = [("direction", ctypes.c_int32), ("filter", ctypes.c_int32),
                 ("bin_small", ctypes.c_int32), ("bin_large", ctypes.c_int32),
                 ("online_cap", ctypes.c_int32), ("fused", ctypes.c_int32),
-                ("policy", ctypes.c_int32), ("grid_wgs", ctypes.c_int32)]
+                ("policy", ctypes.c_int32), ("grid_wgs", ctypes.c_int32),
+                ("watchdog_us", ctypes.c_int32)]
 
 
 class sx_run_stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("launches", ctypes.c_int32),
                 ("pull_iters", ctypes.c_int32), ("ballot_iters", ctypes.c_int32),
                 ("edges_inspected", ctypes.c_int64), ("vertex_expansions", ctypes.c_int64),
-                ("device_ms", ctypes.c_double), ("scan_entries", ctypes.c_int64)]
+                ("device_ms", ctypes.c_double), ("scan_entries", ctypes.c_int64),
+                ("barrier_wait_ms", ctypes.c_double), ("policy_evals", ctypes.c_int32),
+                ("policy_x", ctypes.c_float * 8), ("policy_y", ctypes.c_float * 4)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if isinstance(v, ctypes.Array) else v
+        return out
 
 
 class sx_query(ctypes.Structure):
@@ -126,6 +134,7 @@ def lib() -> ctypes.CDLL:
         "sx_eq1_ctas": ([ctypes.c_int32] * 4, ctypes.c_int32),
         "sx_policy_load_mlp": ([vp, vp, ctypes.c_int64], ctypes.c_int),
         "sx_mlp_forward": ([vp, vp, vp, ctypes.c_int32, vp, vp], ctypes.c_int),
+        "sx_mlp_forward_host": ([vp, vp, ctypes.c_int32, vp], ctypes.c_int),
         "sx_mlp_loss_grad": ([vp, vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp], ctypes.c_int),
         "sx_mlp_adam": ([vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                          ctypes.c_float, ctypes.c_float, vp], ctypes.c_int),
@@ -135,6 +144,9 @@ def lib() -> ctypes.CDLL:
                           P(sx_run_stats), P(ctypes.c_double)], ctypes.c_int),
         "sx_batch_autotune": ([vp, P(sx_query), ctypes.c_int32, P(sx_policy), vp, P(sx_batch_config),
                                P(ctypes.c_double)], ctypes.c_int),
+        "sx_run_iterations": ([vp, vp, ctypes.c_int32, vp, vp, ctypes.c_int32, P(sx_run_stats)], ctypes.c_int),
+        "sx_frontier_get": ([vp, vp, vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32), vp,
+                             ctypes.c_int64, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -200,9 +212,10 @@ def sx_graph_destroy(g) -> None:
 SX_DELTA_AUTO = 0xFFFFFFFF
 
 
-def sx_program_register(ctx, algo: int, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0):
+def sx_program_register(ctx, algo: int, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0,
+                        kcore_k: int = 0):
     h = ctypes.c_void_p()
-    p = sx_algo_params(algo, pr_damping, pr_iters, sssp_delta)
+    p = sx_algo_params(algo, pr_damping, pr_iters, sssp_delta, kcore_k)
     check(lib().sx_program_register(ctx, ctypes.byref(p), ctypes.byref(h)), "sx_program_register")
     return h
 
@@ -220,6 +233,29 @@ def sx_run(p, g, source: int, d_out_ptr: int, stream: int = 0) -> sx_run_stats:
     check(lib().sx_run(p, g, source, ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream),
                        ctypes.byref(st)), "sx_run")
     return st
+
+
+def sx_run_iterations(p, g, source: int, d_out_ptr: int, iterations: int, stream: int = 0) -> sx_run_stats:
+    st = sx_run_stats()
+    check(lib().sx_run_iterations(p, g, source, ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream),
+                                  iterations, ctypes.byref(st)), "sx_run_iterations")
+    return st
+
+
+def sx_frontier_get(g, cap: int, nwords: int = 0, stream: int = 0):
+    """(vertices, bins, from_ballot, words) of the list left by sx_run_iterations."""
+    v = np.zeros(max(cap, 1), dtype=np.int32)
+    b = np.zeros(max(cap, 1), dtype=np.int32)
+    w = np.zeros(max(nwords, 1), dtype=np.uint64)
+    cnt, fb = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(lib().sx_frontier_get(g, v.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p), cap,
+                                ctypes.byref(cnt), ctypes.byref(fb),
+                                w.ctypes.data_as(ctypes.c_void_p) if nwords else None, nwords,
+                                ctypes.c_void_p(stream)), "sx_frontier_get")
+    k = min(cnt.value, cap)
+    if cnt.value > cap:
+        raise ValueError(f"list of {cnt.value} entries exceeds cap {cap}")
+    return v[:k].copy(), b[:k].copy(), bool(fb.value), w[:nwords].copy()
 
 
 def sx_read_vertices(g, algo: int, d_out_ptr: int, host: np.ndarray, stream: int = 0) -> None:
@@ -246,6 +282,16 @@ def sx_policy_load_mlp(ctx, params: np.ndarray) -> None:
 def sx_mlp_forward(ctx, d_params: int, d_x: int, n: int, d_y: int, stream: int = 0) -> None:
     check(lib().sx_mlp_forward(ctx, ctypes.c_void_p(d_params), ctypes.c_void_p(d_x), n,
                                ctypes.c_void_p(d_y), ctypes.c_void_p(stream)), "sx_mlp_forward")
+
+
+def sx_mlp_forward_host(params: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """The network on the host (the one-phase arrangement's decisions)."""
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    xx = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 8)
+    y = np.empty((xx.shape[0], 4), dtype=np.float32)
+    check(lib().sx_mlp_forward_host(p.ctypes.data_as(ctypes.c_void_p), xx.ctypes.data_as(ctypes.c_void_p),
+                                    xx.shape[0], y.ctypes.data_as(ctypes.c_void_p)), "sx_mlp_forward_host")
+    return y
 
 
 def sx_mlp_loss_grad(ctx, d_params: int, d_x: int, d_t: int, d_mask: int, n: int, d_loss: int,
@@ -311,13 +357,15 @@ class Policy:
     fused: int = SX_FUSE_AUTO
     policy: int = SX_POLICY_HEURISTIC
     grid_wgs: int = 0
+    watchdog_us: int = 0
 
     def c(self) -> sx_policy:
         return sx_policy(self.direction, self.filter, self.bin_small, self.bin_large,
-                         self.online_cap, self.fused, self.policy, self.grid_wgs)
+                         self.online_cap, self.fused, self.policy, self.grid_wgs, self.watchdog_us)
 
 
-OUT_DTYPES = {SX_BFS: "int32", SX_SSSP: "uint32", SX_KCORE: "int32", SX_PAGERANK: "float32"}
+OUT_DTYPES = {SX_BFS: "int32", SX_SSSP: "uint32", SX_KCORE: "int32", SX_PAGERANK: "float32",
+              SX_WCC: "int32"}
 
 
 class DeviceGraph:
@@ -392,10 +440,11 @@ class Engine:
         import torch
         return torch.cuda.current_stream(self.device).cuda_stream
 
-    def program(self, algo: int, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0):
-        key = (algo, pr_damping, pr_iters, sssp_delta)
+    def program(self, algo: int, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0,
+                kcore_k: int = 0):
+        key = (algo, pr_damping, pr_iters, sssp_delta, kcore_k)
         if key not in self.programs:
-            self.programs[key] = sx_program_register(self.ctx, algo, pr_damping, pr_iters, sssp_delta)
+            self.programs[key] = sx_program_register(self.ctx, algo, pr_damping, pr_iters, sssp_delta, kcore_k)
         return self.programs[key]
 
     def load(self, g, validate: bool = False, reorder: bool = False) -> DeviceGraph:
@@ -404,11 +453,12 @@ class Engine:
         return DeviceGraph(self, g, validate, reorder)
 
     def run(self, dg: DeviceGraph, algo: int, source: int = -1, policy: Optional[Policy] = None,
-            out=None, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0):
+            out=None, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0, kcore_k: int = 0):
         """Run and return (torch device tensor, stats dict).  sssp_delta: SSSP
-        bucket width of delta-stepping (0 = none)."""
+        bucket width of delta-stepping (0 = none); kcore_k: membership in the
+        k-core instead of the decomposition (k > 0)."""
         import torch
-        p = self.program(algo, pr_damping, pr_iters, sssp_delta)
+        p = self.program(algo, pr_damping, pr_iters, sssp_delta, kcore_k)
         sx_program_set_policy(p, (policy or Policy()).c())
         if out is None:
             dt = {SX_PAGERANK: torch.float32}.get(algo, torch.int32)

@@ -125,23 +125,27 @@ SX_DEV VGrid hw_grid() { return VGrid{blockIdx.x, gridDim.x}; }
 // one monitor workgroup waits for all of them and then releases everybody).
 // Deadlock freedom comes from launching no more workgroups than can be
 // resident at once (the Eq. 1 analogue, computed from the occupancy API on
-// the host).  Each wait loop has a watchdog: when the spin budget runs out
-// it raises ctrl->error = SX_ERR_DEADLOCK and every workgroup leaves the
-// kernel at its next check.
+// the host).  Each wait loop has a watchdog: when a wait has lasted `budget`
+// ticks of the wall clock it raises ctrl->error = SX_ERR_DEADLOCK and every
+// workgroup leaves the kernel at its next check.
 //
 // Arrival is a plain release store to a private 128-byte line, so arrivals
 // never serialise on one address; the monitor's threads poll the flags in
 // parallel.  gen is the barrier generation, kept per workgroup in a register
-// and identical in all workgroups.
+// and identical in all workgroups.  The time each workgroup spends between
+// its arrival and its release is added to the statistics (barrier stall).
+SX_DEV unsigned long long wall_ticks() { return wall_clock64(); }
+
 struct GridBarrier {
   Ctrl *c;
   unsigned nblk, rank;
   unsigned gen;
+  unsigned long long budget;
 
-  SX_DEV GridBarrier(Ctrl *ctrl, unsigned start_gen)
-      : c(ctrl), nblk(gridDim.x), rank(blockIdx.x), gen(start_gen) {}
-  SX_DEV GridBarrier(Ctrl *ctrl, unsigned start_gen, const VGrid &vg)
-      : c(ctrl), nblk(vg.nb), rank(vg.bid), gen(start_gen) {}
+  SX_DEV GridBarrier(Ctrl *ctrl, unsigned start_gen, unsigned long long wd)
+      : c(ctrl), nblk(gridDim.x), rank(blockIdx.x), gen(start_gen), budget(wd) {}
+  SX_DEV GridBarrier(Ctrl *ctrl, unsigned start_gen, unsigned long long wd, const VGrid &vg)
+      : c(ctrl), nblk(vg.nb), rank(vg.bid), gen(start_gen), budget(wd) {}
 
   SX_DEV bool failed() const { return load_relaxed(&c->error.v[0]) != 0u; }
 
@@ -161,14 +165,14 @@ struct GridBarrier {
       return s_err == 0u;
     }
     __syncthreads();
+    const unsigned long long t0 = wall_ticks();
     bool ok = true;
     if (rank == 0) {
       for (unsigned b = 1 + threadIdx.x; b < nblk; b += blockDim.x) {
-        unsigned spins = 0;
         while (load_relaxed(&c->flags[b].v[0]) != target) {
           __builtin_amdgcn_s_sleep(2);
           if (failed()) { ok = false; break; }
-          if (++spins > kSpinLimit) {
+          if (wall_ticks() - t0 > budget) {
             store_relaxed(&c->error.v[0], (unsigned)SX_ERR_DEADLOCK);
             ok = false;
             break;
@@ -181,23 +185,45 @@ struct GridBarrier {
         __hip_atomic_store(&c->bar_gen.v[0], target, __ATOMIC_RELEASE, SX_AG);
     } else if (threadIdx.x == 0) {
       __hip_atomic_store(&c->flags[rank].v[0], target, __ATOMIC_RELEASE, SX_AG);
-      unsigned spins = 0;
       while (load_relaxed(&c->bar_gen.v[0]) != target) {
         __builtin_amdgcn_s_sleep(2);
         if (failed()) break;
-        if (++spins > kSpinLimit) {
+        if (wall_ticks() - t0 > budget) {
           store_relaxed(&c->error.v[0], (unsigned)SX_ERR_DEADLOCK);
           break;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    if (threadIdx.x == 0) s_err = load_relaxed(&c->error.v[0]) | (ok ? 0u : 1u);
+    if (threadIdx.x == 0) {
+      s_err = load_relaxed(&c->error.v[0]) | (ok ? 0u : 1u);
+      __hip_atomic_fetch_add((unsigned long long *)&c->statw[rank % kStatLines].v[4],
+                             wall_ticks() - t0, __ATOMIC_RELAXED, SX_AG);
+    }
     gen = target;
     __syncthreads();
     return ok && s_err == 0u;
   }
 };
+
+// Barrier stall of the sequenced arrangement, whose global barrier is the
+// kernel boundary: workgroup b of launch L+1 adds the time since workgroup b
+// of launch L ended (the wait for the slowest workgroup of launch L plus the
+// launch gap).  Called by thread 0 of every workgroup of a launch that runs a
+// phase; the first launch of a run finds no end time and adds nothing.
+SX_DEV void seq_stall_enter(Ctrl *c, unsigned bid) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long now = wall_ticks();
+  const unsigned long long last = load_relaxed((const unsigned long long *)&c->flags[bid].v[4]);
+  if (last && now > last)
+    __hip_atomic_fetch_add((unsigned long long *)&c->statw[bid % kStatLines].v[4], now - last,
+                           __ATOMIC_RELAXED, SX_AG);
+}
+// End of a launch that ran a phase (all threads of the workgroup call it).
+SX_DEV void seq_stall_leave(Ctrl *c, unsigned bid) {
+  __syncthreads();
+  if (threadIdx.x == 0) store_relaxed((unsigned long long *)&c->flags[bid].v[4], wall_ticks());
+}
 
 // Words of the control block that every workgroup reads at the start of a
 // launch: one wavefront loads the 128-byte line (and the error word) and
@@ -212,8 +238,19 @@ SX_DEV void fetch_line(const Line &l, const Ctrl *c, unsigned *dst /* 33 words o
 // run's initialisation kernel, which completes before the persistent kernel
 // starts on the same stream).
 SX_DEV void reset_barrier(Ctrl *c) {
-  for (int b = threadIdx.x; b < kMaxGrid; b += blockDim.x) c->flags[b].v[0] = 0u;
+  for (int b = threadIdx.x; b < kMaxGrid; b += blockDim.x) {
+    c->flags[b].v[0] = 0u;
+    c->flags[b].v[4] = 0u;
+    c->flags[b].v[5] = 0u;
+  }
   if (threadIdx.x == 0) c->bar_gen.v[0] = 0u;
+}
+
+// Zero the statistics lines (words 0-5 of each) and the policy line; called
+// by one workgroup of a run's initialisation kernel.
+SX_DEV void reset_stat_lines(Ctrl *c) {
+  for (int i = threadIdx.x; i < kStatLines * 6; i += blockDim.x) c->statw[i / 6].v[i % 6] = 0u;
+  if (threadIdx.x < 32) c->pol.v[threadIdx.x] = 0u;
 }
 
 }  // namespace sx

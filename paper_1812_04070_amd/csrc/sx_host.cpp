@@ -48,6 +48,7 @@ struct sx_ctx {
   int device;
   int cus;
   int cooperative;
+  double wall_khz = 100000.0;  // rate of the device's constant wall clock
   std::vector<float> mlp;  // learned-policy parameters (host copy)
   float *d_mlp = nullptr;  // and on the device
   // training scratch, grown on demand: per sample y[4], h[64], delta[68], loss
@@ -59,6 +60,11 @@ struct sx_ctx {
   int team_n = 0;
   long long team_m = 0;
   sx_batch_config tuned{0, 0, 0};
+  // batched mode: device query table, order, team workspace table, queue
+  // counter and statistics, grown on demand and kept; timing events
+  void *bq = nullptr, *bo = nullptr, *bw = nullptr, *bh = nullptr, *bs = nullptr;
+  int batch_cap_q = 0, batch_cap_t = 0;
+  hipEvent_t be0 = nullptr, be1 = nullptr;
 };
 
 struct sx_graph {
@@ -78,6 +84,9 @@ struct sx_graph {
   std::vector<int> h_inv;
   void *state = nullptr;
   long long weight_sum = -1;  // sum of the arc weights, once SX_DELTA_AUTO needed it
+  // where the lists of the next iteration sit after sx_run_iterations:
+  // record slot, region parity, run grid (-1: no such run yet)
+  int next_slot = -1, next_parity = 0, next_grid = 0;
 };
 
 struct sx_program {
@@ -120,10 +129,13 @@ sx_status sx_ctx_create(int hip_device, sx_ctx **out) {
   HIP_TRY(hipSetDevice(hip_device));
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
+  int khz = 0;
+  HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device));
   sx_ctx *c = new sx_ctx();
   c->device = hip_device;
   c->cus = prop.multiProcessorCount;
   c->cooperative = prop.cooperativeLaunch;
+  if (khz > 0) c->wall_khz = (double)khz;
   *out = c;
   return SX_OK;
 }
@@ -133,6 +145,10 @@ void sx_ctx_destroy(sx_ctx *c) {
   if (c->d_mlp) (void)hipFree(c->d_mlp);
   if (c->d_scratch) (void)hipFree(c->d_scratch);
   for (void *p : c->team_allocs) (void)hipFree(p);
+  for (void *p : {c->bq, c->bo, c->bw, c->bh, c->bs})
+    if (p) (void)hipFree(p);
+  if (c->be0) (void)hipEventDestroy(c->be0);
+  if (c->be1) (void)hipEventDestroy(c->be1);
   delete c;
 }
 
@@ -169,7 +185,13 @@ sx_status sx_mlp_forward(sx_ctx *ctx, const float *P, const float *X, int32_t n,
   if (!ctx || !P || (n > 0 && (!X || !Y))) return fail(SX_EINVAL, "NULL argument");
   if (n < 0) return fail(SX_EINVAL, "n < 0");
   HIP_TRY(hipSetDevice(ctx->device));
-  HIP_TRY(mlp_forward(P, X, n, Y, nullptr, (hipStream_t)hip_stream));
+  HIP_TRY(mlp_forward_wave(P, X, n, Y, (hipStream_t)hip_stream));
+  return SX_OK;
+}
+
+sx_status sx_mlp_forward_host(const float *P, const float *X, int32_t n, float *Y) {
+  if (!P || n < 0 || (n > 0 && (!X || !Y))) return fail(SX_EINVAL, "bad argument");
+  for (int32_t i = 0; i < n; ++i) mlp_eval_host(P, X + (size_t)i * kMlpIn, Y + (size_t)i * kMlpOut);
   return SX_OK;
 }
 
@@ -438,7 +460,8 @@ extern "C" sx_status sx_graph_info(const sx_graph *g, int32_t *n, int64_t *m, in
 // ----------------------------------------------------------- programs ---
 extern "C" sx_status sx_program_register(sx_ctx *ctx, const sx_algo_params *p, sx_program **out) {
   if (!ctx || !p || !out) return fail(SX_EINVAL, "NULL argument");
-  if (p->algo < SX_BFS || p->algo > SX_PAGERANK) return fail(SX_EINVAL, "unknown algorithm %d", (int)p->algo);
+  if (p->algo < SX_BFS || p->algo > SX_WCC) return fail(SX_EINVAL, "unknown algorithm %d", (int)p->algo);
+  if (p->algo == SX_KCORE && p->kcore_k < 0) return fail(SX_EINVAL, "kcore_k < 0");
   if (p->algo == SX_PAGERANK && (p->pr_iters < 0 || !(p->pr_damping >= 0.f && p->pr_damping <= 1.f)))
     return fail(SX_EINVAL, "bad PageRank parameters");
   sx_program *P = new sx_program();
@@ -455,7 +478,8 @@ extern "C" sx_status sx_program_set_policy(sx_program *p, const sx_policy *pol) 
   if (!p || !pol) return fail(SX_EINVAL, "NULL argument");
   if (pol->direction < 0 || pol->direction > 2) return fail(SX_EINVAL, "bad direction");
   if (pol->filter < 0 || pol->filter > 2) return fail(SX_EINVAL, "bad filter");
-  if (pol->fused < 0 || pol->fused > 3) return fail(SX_EINVAL, "bad fused");
+  if (pol->fused < 0 || pol->fused > 4) return fail(SX_EINVAL, "bad fused");
+  if (pol->watchdog_us < 0) return fail(SX_EINVAL, "watchdog_us < 0");
   if (pol->policy < 0 || pol->policy > 1) return fail(SX_EINVAL, "bad policy");
   if (pol->bin_small < 0 || pol->bin_large < 0 || pol->online_cap < 0 || pol->grid_wgs < 0)
     return fail(SX_EINVAL, "negative policy field");
@@ -530,6 +554,18 @@ static Params make_params(const sx_program *p, const sx_graph *G, int grid) {
   P.pr_iters = p->ap.pr_iters;
   P.learned = pol.policy == SX_POLICY_LEARNED ? 1 : 0;
   P.bins_fixed = (pol.bin_small > 0 || pol.bin_large > 0) ? 1 : 0;
+  P.kfix = p->ap.algo == SX_KCORE ? p->ap.kcore_k : 0;
+  P.watchdog = pol.watchdog_us > 0
+                   ? (unsigned long long)((double)pol.watchdog_us * p->ctx->wall_khz / 1000.0)
+                   : (unsigned long long)(2.0 * p->ctx->wall_khz * 1000.0);
+  if (p->ap.algo == SX_WCC) {
+    // every vertex starts active, so the first iteration pulls; a pull step
+    // reads every in-arc once without atomics, a push step the frontier's
+    // arcs with an atomic minimum per improvement: pull while the
+    // frontier's arcs exceed m / 2, push again below m / 8
+    P.alpha_w = 2.0f;
+    P.beta_w = 8.0f;
+  }
   (void)G;
   return P;
 }
@@ -606,13 +642,22 @@ static sx_status seq_drive(sx_graph *G, hipStream_t st, int first, int maxb, uns
   }
 }
 
-static void fill_stats(const Ctrl *c, int launches, float ms, sx_run_stats *stats) {
+// grid: workgroups of the run's phase kernels (the barrier stall is averaged
+// over them); khz: the device wall clock's rate.
+static void fill_stats(const Ctrl *c, int launches, float ms, int grid, double khz,
+                       sx_run_stats *stats) {
   if (!stats) return;
-  unsigned long long e = 0, x = 0;
+  memset(stats, 0, sizeof *stats);
+  unsigned long long e = 0, x = 0, wt = 0;
   for (int i = 0; i < kStatLines; ++i) {
     e += *(const unsigned long long *)&c->statw[i].v[0];
     x += *(const unsigned long long *)&c->statw[i].v[2];
+    wt += *(const unsigned long long *)&c->statw[i].v[4];
   }
+  stats->barrier_wait_ms = grid > 0 ? (double)wt / (double)grid / khz : 0.0;
+  stats->policy_evals = (int32_t)c->pol.v[0];
+  for (int k = 0; k < 8; ++k) memcpy(&stats->policy_x[k], &c->pol.v[1 + k], 4);
+  for (int k = 0; k < 4; ++k) memcpy(&stats->policy_y[k], &c->pol.v[9 + k], 4);
   stats->edges_inspected = (int64_t)e;
   stats->vertex_expansions = (int64_t)x;
   stats->ballot_iters = (int32_t)c->stats.v[4];
@@ -647,9 +692,15 @@ static sx_status read_totals(const Work &w, int slot, int grid, hipStream_t st,
 
 // The host decision of the one-phase loop: decide_core plus the learned
 // policy, evaluated exactly as the device does it.
+// Host-side record of the network's decisions (one-phase arrangement).
+struct HostPolicyLog {
+  int evals = 0;
+  float x[8] = {0}, y[4] = {0};
+};
+
 static Decision host_decide(const sx_ctx *ctx, const sx_policy &pol, Params &P, bool sssp,
                             const sx_graph *G, int it, bool pulling, const HostTotals &T,
-                            unsigned long long &mu, PolicyState &ps) {
+                            unsigned long long &mu, PolicyState &ps, HostPolicyLog *log = nullptr) {
   DecideIn in;
   in.nf = T.nf;
   in.mf = T.mf;
@@ -665,6 +716,11 @@ static Decision host_decide(const sx_ctx *ctx, const sx_policy &pol, Params &P, 
     policy_features(in.nf, in.mf, sssp ? (unsigned long long)G->g.m : mu, G->g.n, G->g.m, ps,
                     pulling, x);
     mlp_eval_host(ctx->mlp.data(), x, y);
+    if (log) {
+      ++log->evals;
+      memcpy(log->x, x, sizeof log->x);
+      memcpy(log->y, y, sizeof log->y);
+    }
     if (pol.direction == SX_DIR_AUTO) {
       if (!pulling) d.to_pull = y[0] > 0.f;
       else d.to_push = !(y[0] > 0.f);
@@ -706,23 +762,33 @@ static sx_status auto_delta(sx_graph *G, hipStream_t st, unsigned *delta) {
   return SX_OK;
 }
 
+// max_it > 0: stop the one-phase arrangement after that many iterations and
+// note where the next iteration's lists are (sx_run_iterations).
 static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out, hipStream_t st,
-                               sx_run_stats *stats) {
-  const int sssp = p->ap.algo == SX_SSSP;
+                               sx_run_stats *stats, int max_it = 0) {
+  const int algo = p->ap.algo == SX_SSSP ? ALG_SSSP : (p->ap.algo == SX_WCC ? ALG_WCC : ALG_BFS);
+  const bool wcc = algo == ALG_WCC;
+  // aggregation (minimum) programs decide with the SSSP rule
+  const bool aggr = algo != ALG_BFS;
   sx_ctx *ctx = p->ctx;
-  const bool fused = p->pol.fused == SX_FUSED;
-  const bool sequenced = p->pol.fused == SX_SEQUENCED || p->pol.fused == SX_FUSE_AUTO;
+  const bool fused = max_it == 0 && (p->pol.fused == SX_FUSED || p->pol.fused == SX_FUSED_ALL);
+  const int fk = p->pol.fused == SX_FUSED_ALL ? TK_FUSED_ALL : TK_FUSED;
+  const bool sequenced = max_it == 0 && (p->pol.fused == SX_SEQUENCED || p->pol.fused == SX_FUSE_AUTO);
   int grid;
   // large dense graphs take the wide sequenced kernel (three workgroups per CU)
   const int seq_kind =
       G->g.m >= kBigGraphArcs && G->g.m >= 8ll * G->g.n ? TK_SEQ_WIDE : TK_SEQ;
   if (sequenced) {
-    grid = plain_grid(ctx, trav_kernel(seq_kind, sssp));
+    grid = plain_grid(ctx, trav_kernel(seq_kind, algo));
     if (p->pol.grid_wgs > 0) grid = std::min(grid, p->pol.grid_wgs);
   } else if (fused) {
-    grid = persistent_grid(ctx, trav_kernel(TK_FUSED, sssp), p->pol.grid_wgs);
+    // the push and pull kernels of selective fusion share the run's lists,
+    // whose regions are laid out for one grid: both must fit it
+    grid = persistent_grid(ctx, trav_kernel(fk, algo), p->pol.grid_wgs);
+    if (fk == TK_FUSED)
+      grid = std::min(grid, persistent_grid(ctx, trav_kernel(TK_FUSED_PULL, algo), p->pol.grid_wgs));
   } else {
-    grid = plain_grid(ctx, trav_kernel(TK_PUSH_STEP, sssp));
+    grid = plain_grid(ctx, trav_kernel(TK_PUSH_STEP, algo));
     if (p->pol.grid_wgs > 0) grid = std::min(grid, p->pol.grid_wgs);
   }
   TravArgs a;
@@ -734,7 +800,7 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   a.src = src;
   a.mlp = ctx->d_mlp;
   if (a.P.learned && !ctx->d_mlp) return fail(SX_ESTATE, "learned policy without loaded MLP");
-  if (sssp && a.P.delta == SX_DELTA_AUTO) {
+  if (algo == ALG_SSSP && a.P.delta == SX_DELTA_AUTO) {
     sx_status s = auto_delta(G, st, &a.P.delta);
     if (s != SX_OK) return s;
     // a run that ends within this many iterations is not high-diameter:
@@ -742,26 +808,40 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
     // 4-6 arcs per vertex lost 5-13 % to buckets from the first iteration)
     a.P.delta_after = 64;
   }
+  // every WCC vertex starts active: unless the caller forces push, the first
+  // iteration pulls; a push start builds its lists with a ballot scan
+  const bool pull_first = p->pol.direction == SX_DIR_PULL || (wcc && p->pol.direction == SX_DIR_AUTO);
   int launches = 0;
   HIP_TRY(hipEventRecord(G->ev0, st));
   // unexplored arcs (BFS direction rule) are computed on the device
-  HIP_TRY(trav_init(a, sssp, 0ull, grid, st));
+  HIP_TRY(trav_init(a, algo, 0ull, grid, st, pull_first));
   ++launches;
   const Ctrl *fin = G->h_ctrl;
+  HostPolicyLog plog;
   if (sequenced) {
-    HIP_TRY(seq_start(G->w.ctrl, p->pol.direction == SX_DIR_PULL, st));
+    HIP_TRY(seq_start(G->w.ctrl, pull_first, wcc, st));
     sx_status s = seq_drive(
         G, st, 16, 64, (unsigned)(8 * (long long)G->g.n + 1024),
-        [&](unsigned L) { return trav_launch(seq_kind, sssp, a, (int)L, 0, grid, st); }, launches, &fin);
+        [&](unsigned L) { return trav_launch(seq_kind, algo, a, (int)L, 0, grid, st); }, launches, &fin);
     if (s != SX_OK) return s;
     HIP_TRY(hipEventRecord(G->ev1, st));
   } else if (fused) {
-    int pull_next = p->pol.direction == SX_DIR_PULL ? 1 : 0;
+    if (wcc && !pull_first) {
+      // iteration 0's lists (every vertex) by a ballot scan; state word 2
+      // tells the persistent kernel they are there
+      HIP_TRY(trav_launch(TK_BALLOT, algo, a, -1, 0, grid, st));
+      ++launches;
+    }
+    int pull_next = pull_first ? 1 : 0;
     for (int batch = 0;; ++batch) {
+      // all fusion switches direction inside its one kernel: launches after
+      // the run's end return at once
       for (int k = 0; k < 4; ++k) {
-        HIP_TRY(trav_launch(TK_FUSED, sssp, a, 0, pull_next, grid, st));
+        const int kind = fk == TK_FUSED_ALL ? fk : (pull_next ? TK_FUSED_PULL : TK_FUSED);
+        HIP_TRY(trav_launch(kind, algo, a, 0, 0, grid, st));
         ++launches;
         pull_next ^= 1;
+        if (fk == TK_FUSED_ALL) break;
       }
       HIP_TRY(hipEventRecord(G->ev1, st));
       sx_status s = read_ctrl(G, st);
@@ -769,23 +849,42 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
       s = ctrl_error(G->h_ctrl);
       if (s != SX_OK) return s;
       if (G->h_ctrl->state.v[0] == EXIT_DONE) break;
+      if (fk == TK_FUSED_ALL && G->h_ctrl->state.v[0] != EXIT_NONE)
+        return fail(SX_EHIP, "all-fused run ended with state %u", G->h_ctrl->state.v[0]);
       if (batch > 1000000) return fail(SX_EHIP, "run did not converge");
     }
   } else {
-    bool pulling = p->pol.direction == SX_DIR_PULL;
+    bool pulling = pull_first;
     bool rebuilt = false;
     PolicyState ps{0u, 0ull};
+    if (wcc && !pull_first) {
+      HIP_TRY(trav_launch(TK_BALLOT, algo, a, -1, 0, grid, st));
+      launches += 1;
+      rebuilt = true;
+    }
     sx_status s0 = read_ctrl(G, st);
     if (s0 != SX_OK) return s0;
     unsigned long long mu = *(const unsigned long long *)&G->h_ctrl->state.v[6];
     std::vector<RecSlot> buf;
+    G->next_slot = -1;
     for (int it = 0;; ++it) {
+      if (max_it > 0 && it >= max_it) {
+        // stop before iteration `it`: its lists are the online lists of the
+        // last step (slot it % 3) or a ballot rebuild (slot SLOT_SCAN); a
+        // pull iteration next has no push list
+        if (!pulling) {
+          G->next_slot = rebuilt ? SLOT_SCAN : it % 3;
+          G->next_parity = it & 1;
+          G->next_grid = grid;
+        }
+        break;
+      }
       if (!pulling) {
-        HIP_TRY(trav_launch(TK_PUSH_STEP, sssp, a, it, rebuilt ? 1 : 0, grid, st));
+        HIP_TRY(trav_launch(TK_PUSH_STEP, algo, a, it, rebuilt ? 1 : 0, grid, st));
         launches += 1;
       } else {
-        HIP_TRY(trav_launch(TK_PULL_SCAN, sssp, a, it, 0, grid, st));
-        HIP_TRY(trav_launch(TK_PULL_STEP, sssp, a, it, 0, grid, st));
+        HIP_TRY(trav_launch(TK_PULL_SCAN, algo, a, it, 0, grid, st));
+        HIP_TRY(trav_launch(TK_PULL_STEP, algo, a, it, 0, grid, st));
         launches += 2;
       }
       sx_status s = read_ctrl(G, st);
@@ -795,7 +894,7 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
       HostTotals T;
       s = read_totals(G->w, (it + 1) % 3, grid, st, buf, T);
       if (s != SX_OK) return s;
-      Decision d = host_decide(ctx, p->pol, a.P, sssp, G, it, pulling, T, mu, ps);
+      Decision d = host_decide(ctx, p->pol, a.P, aggr, G, it, pulling, T, mu, ps, &plog);
       if (d.done) break;
       bool rebuild = false;
       if (!pulling) {
@@ -807,7 +906,7 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
       }
       rebuilt = false;
       if (rebuild) {
-        HIP_TRY(trav_launch(TK_BALLOT, sssp, a, it, 0, grid, st));
+        HIP_TRY(trav_launch(TK_BALLOT, algo, a, it, 0, grid, st));
         launches += 1;
         rebuilt = true;
       }
@@ -819,7 +918,13 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   HIP_TRY(hipEventSynchronize(G->ev1));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
-  fill_stats(fin, launches, ms, stats);
+  fill_stats(fin, launches, ms, grid, ctx->wall_khz, stats);
+  if (stats && !sequenced && !fused) {
+    // the one-phase arrangement decides on the host
+    stats->policy_evals = plog.evals;
+    memcpy(stats->policy_x, plog.x, sizeof plog.x);
+    memcpy(stats->policy_y, plog.y, sizeof plog.y);
+  }
   return SX_OK;
 }
 
@@ -851,11 +956,12 @@ static sx_status run_kcore(sx_program *p, sx_graph *G, void *d_out, hipStream_t 
         G, st, 16, 16, (unsigned)(16 * (long long)G->g.n + 1024),
         [&](unsigned L) { return kcore_seq_launch(a, L, grid, st, false); }, launches, &fin);
     if (s != SX_OK) return s;
+    if (a.P.kfix) HIP_TRY(kcore_membership(a.core, G->g.n, st));
     HIP_TRY(hipEventRecord(G->ev1, st));
     HIP_TRY(hipEventSynchronize(G->ev1));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
-    fill_stats(fin, launches, ms, stats);
+    fill_stats(fin, launches, ms, grid, p->ctx->wall_khz, stats);
     return SX_OK;
   }
   for (;;) {
@@ -869,10 +975,14 @@ static sx_status run_kcore(sx_program *p, sx_graph *G, void *d_out, hipStream_t 
     if (G->h_ctrl->state.v[0] == EXIT_DONE) break;
     if (launches > 64) return fail(SX_EHIP, "k-core did not finish");
   }
+  if (a.P.kfix) {
+    HIP_TRY(kcore_membership(a.core, G->g.n, st));
+    HIP_TRY(hipEventRecord(G->ev1, st));
+  }
   HIP_TRY(hipEventSynchronize(G->ev1));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
-  fill_stats(G->h_ctrl, launches, ms, stats);
+  fill_stats(G->h_ctrl, launches, ms, grid, p->ctx->wall_khz, stats);
   return SX_OK;
 }
 
@@ -915,7 +1025,7 @@ static sx_status run_pagerank(sx_program *p, sx_graph *G, void *d_out, hipStream
   HIP_TRY(hipEventSynchronize(G->ev1));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
-  fill_stats(G->h_ctrl, 2, ms, stats);
+  fill_stats(G->h_ctrl, 2, ms, grid, p->ctx->wall_khz, stats);
   return SX_OK;
 }
 
@@ -1184,34 +1294,43 @@ extern "C" sx_status sx_run_batch(sx_ctx *ctx, const sx_query *q, int32_t nq, co
   std::sort(key.begin(), key.end());
   std::vector<int> order((size_t)nq);
   for (int i = 0; i < nq; ++i) order[i] = key[i].second;
-  struct Buf { void *p = nullptr; ~Buf() { if (p) (void)hipFree(p); } } bq, bo, bw, bh, bs;
-  HIP_TRY(hipMalloc(&bq.p, sizeof(BatchQuery) * nq));
-  HIP_TRY(hipMalloc(&bo.p, sizeof(int) * nq));
-  HIP_TRY(hipMalloc(&bw.p, sizeof(Work) * nteams));
-  HIP_TRY(hipMalloc(&bh.p, 256));
-  HIP_TRY(hipMalloc(&bs.p, sizeof(BatchStat) * nq));
-  HIP_TRY(hipMemcpyAsync(bq.p, hq.data(), sizeof(BatchQuery) * nq, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(bo.p, order.data(), sizeof(int) * nq, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(bw.p, ctx->team_work.data(), sizeof(Work) * nteams, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemsetAsync(bs.p, 0, sizeof(BatchStat) * nq, st));
-  b.q = (const BatchQuery *)bq.p;
-  b.order = (const int *)bo.p;
-  b.work = (const Work *)bw.p;
-  b.queue_head = (unsigned *)bh.p;
-  b.stats = (BatchStat *)bs.p;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  // device tables kept in the context and grown on demand, so a repeated
+  // batch allocates nothing
+  if (nq > ctx->batch_cap_q || nteams > ctx->batch_cap_t || !ctx->bh) {
+    for (void **pp : {&ctx->bq, &ctx->bo, &ctx->bw, &ctx->bh, &ctx->bs}) {
+      if (*pp) (void)hipFree(*pp);
+      *pp = nullptr;
+    }
+    ctx->batch_cap_q = ctx->batch_cap_t = 0;
+    const int cq = std::max(nq, 256), ct = std::max(nteams, kMaxGrid);
+    HIP_TRY(hipMalloc(&ctx->bq, sizeof(BatchQuery) * cq));
+    HIP_TRY(hipMalloc(&ctx->bo, sizeof(int) * cq));
+    HIP_TRY(hipMalloc(&ctx->bw, sizeof(Work) * ct));
+    HIP_TRY(hipMalloc(&ctx->bh, 256));
+    HIP_TRY(hipMalloc(&ctx->bs, sizeof(BatchStat) * cq));
+    ctx->batch_cap_q = cq;
+    ctx->batch_cap_t = ct;
+  }
+  if (!ctx->be0) HIP_TRY(hipEventCreate(&ctx->be0));
+  if (!ctx->be1) HIP_TRY(hipEventCreate(&ctx->be1));
+  HIP_TRY(hipMemcpyAsync(ctx->bq, hq.data(), sizeof(BatchQuery) * nq, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ctx->bo, order.data(), sizeof(int) * nq, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ctx->bw, ctx->team_work.data(), sizeof(Work) * nteams, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(ctx->bs, 0, sizeof(BatchStat) * nq, st));
+  b.q = (const BatchQuery *)ctx->bq;
+  b.order = (const int *)ctx->bo;
+  b.work = (const Work *)ctx->bw;
+  b.queue_head = (unsigned *)ctx->bh;
+  b.stats = (BatchStat *)ctx->bs;
+  hipEvent_t e0 = ctx->be0, e1 = ctx->be1;
   HIP_TRY(hipEventRecord(e0, st));
   HIP_TRY(batch_launch(b, grid, st));
   HIP_TRY(hipEventRecord(e1, st));
   HIP_TRY(hipEventSynchronize(e1));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   std::vector<BatchStat> hs((size_t)nq);
-  HIP_TRY(hipMemcpy(hs.data(), bs.p, sizeof(BatchStat) * nq, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hs.data(), ctx->bs, sizeof(BatchStat) * nq, hipMemcpyDeviceToHost));
   // team errors (watchdog) and per-query completion
   for (int t = 0; t < nteams; ++t) {
     unsigned err = 0;
@@ -1225,6 +1344,7 @@ extern "C" sx_status sx_run_batch(sx_ctx *ctx, const sx_query *q, int32_t nq, co
     if (hs[i].status != EXIT_DONE) return fail(SX_EHIP, "query %d did not finish (status %d)", i, hs[i].status);
   if (per_query)
     for (int i = 0; i < nq; ++i) {
+      memset(&per_query[i], 0, sizeof per_query[i]);
       per_query[i].iterations = hs[i].iterations;
       per_query[i].launches = 1;
       per_query[i].pull_iters = hs[i].pull_iters;
@@ -1280,6 +1400,14 @@ extern "C" sx_status sx_run(sx_program *p, const sx_graph *gc, int32_t source, v
     case SX_KCORE:
       s = run_kcore(p, G, state, st, stats);
       break;
+    case SX_WCC:
+      if (G->directed) return fail(SX_EUNSUPPORTED, "WCC on a directed graph");
+      if (n == 0) {
+        if (stats) memset(stats, 0, sizeof *stats);
+        return SX_OK;
+      }
+      s = run_traversal(p, G, 0, state, st, stats);
+      break;
     case SX_PAGERANK:
       s = run_pagerank(p, G, state, st, stats);
       break;
@@ -1297,6 +1425,82 @@ extern "C" sx_status sx_run(sx_program *p, const sx_graph *gc, int32_t source, v
   return SX_OK;
 }
 
+extern "C" sx_status sx_run_iterations(sx_program *p, const sx_graph *gc, int32_t source,
+                                       void *d_out, void *hip_stream, int32_t iterations,
+                                       sx_run_stats *stats) {
+  if (!p || !gc || !d_out) return fail(SX_EINVAL, "NULL argument");
+  if (iterations < 1) return fail(SX_EINVAL, "iterations must be positive");
+  sx_graph *G = const_cast<sx_graph *>(gc);
+  if (G->ctx != p->ctx) return fail(SX_EINVAL, "graph and program belong to different contexts");
+  if (p->ap.algo != SX_BFS && p->ap.algo != SX_SSSP && p->ap.algo != SX_WCC)
+    return fail(SX_EINVAL, "BFS, SSSP or WCC only");
+  if (G->reordered) return fail(SX_EUNSUPPORTED, "renumbered graph (SX_REORDER)");
+  const int n = G->g.n;
+  if (p->ap.algo == SX_WCC) {
+    if (G->directed) return fail(SX_EUNSUPPORTED, "WCC on a directed graph");
+    source = 0;
+  }
+  if (n == 0 || source < 0 || source >= n) return fail(SX_EINVAL, "source out of range");
+  if (p->ap.algo == SX_SSSP && !G->weighted) return fail(SX_EINVAL, "SSSP needs edge weights");
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  return run_traversal(p, G, source, d_out, (hipStream_t)hip_stream, stats, iterations);
+}
+
+extern "C" sx_status sx_frontier_get(const sx_graph *g, int32_t *vertices, int32_t *bins, int32_t cap,
+                                     int32_t *count, int32_t *from_ballot, uint64_t *words,
+                                     int64_t nwords, void *hip_stream) {
+  if (!g || !count || (cap > 0 && (!vertices || !bins)) || cap < 0 || nwords < 0 ||
+      (nwords > 0 && !words))
+    return fail(SX_EINVAL, "bad argument");
+  if (g->next_slot < 0) return fail(SX_ESTATE, "no push list: call sx_run_iterations first");
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(hipSetDevice(g->ctx->device));
+  const Work &w = g->w;
+  const int G = g->next_grid, par = g->next_parity;
+  std::vector<RecSlot> rec(1);
+  HIP_TRY(hipMemcpyAsync(rec.data(), w.rec + g->next_slot, sizeof(RecSlot), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const unsigned caps[NBINS] = {w.tot_s / (unsigned)G, w.tot_m / (unsigned)G, w.tot_l / (unsigned)G};
+  int32_t k = 0;
+  for (int b = 0; b < NBINS; ++b) {
+    for (int r = 0; r < G; ++r) {
+      const unsigned c = std::min(rec[0].cnt[b][r], caps[b]);
+      if (!c) continue;
+      if (b < BIN_LARGE) {
+        std::vector<int> h(c);
+        const int *src = (b == BIN_SMALL ? w.reg_s[par] : w.reg_m[par]) + (size_t)r * caps[b];
+        HIP_TRY(hipMemcpy(h.data(), src, sizeof(int) * c, hipMemcpyDeviceToHost));
+        for (unsigned i = 0; i < c; ++i) {
+          if (k < cap) { vertices[k] = h[i]; bins[k] = b; }
+          ++k;
+        }
+      } else {
+        std::vector<unsigned long long> h(c);
+        HIP_TRY(hipMemcpy(h.data(), w.reg_l[par] + (size_t)r * caps[b], sizeof(unsigned long long) * c,
+                          hipMemcpyDeviceToHost));
+        for (unsigned i = 0; i < c; ++i) {
+          if ((h[i] >> 32) != 0) continue;   // one entry per vertex: its first chunk
+          if (k < cap) { vertices[k] = (int32_t)(h[i] & 0xffffffffu); bins[k] = b; }
+          ++k;
+        }
+      }
+    }
+  }
+  *count = k;
+  if (from_ballot) *from_ballot = g->next_slot == SLOT_SCAN ? 1 : 0;
+  if (nwords > 0) {
+    const int64_t have = ((int64_t)g->g.n + 63) / 64;
+    const int64_t nw = std::min(nwords, have);
+    std::vector<unsigned long long> acc((size_t)nw, 0ull), h((size_t)nw);
+    for (int b = 0; b < NBINS; ++b) {
+      HIP_TRY(hipMemcpy(h.data(), w.bits[b], sizeof(unsigned long long) * nw, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < nw; ++i) acc[i] |= h[i];
+    }
+    for (int64_t i = 0; i < nwords; ++i) words[i] = i < nw ? acc[i] : 0ull;
+  }
+  return SX_OK;
+}
+
 extern "C" sx_status sx_read_vertices(const sx_graph *g, sx_algo algo, const void *d_out,
                                       void *host_out, void *hip_stream) {
   if (!g || !d_out || !host_out) return fail(SX_EINVAL, "NULL argument");
@@ -1311,8 +1515,17 @@ extern "C" sx_status sx_kernel_info_get(sx_ctx *ctx, const char *name, sx_kernel
   if (!ctx || !name || !out) return fail(SX_EINVAL, "NULL argument");
   struct Named { const char *name; const void *k; bool persistent; };
   const Named table[] = {
-      {"bfs_fused", trav_kernel(TK_FUSED, 0), true},
-      {"sssp_fused", trav_kernel(TK_FUSED, 1), true},
+      {"bfs_fused", trav_kernel(TK_FUSED, ALG_BFS), true},
+      {"sssp_fused", trav_kernel(TK_FUSED, ALG_SSSP), true},
+      {"wcc_fused", trav_kernel(TK_FUSED, ALG_WCC), true},
+      {"bfs_fused_pull", trav_kernel(TK_FUSED_PULL, ALG_BFS), true},
+      {"sssp_fused_pull", trav_kernel(TK_FUSED_PULL, ALG_SSSP), true},
+      {"wcc_fused_pull", trav_kernel(TK_FUSED_PULL, ALG_WCC), true},
+      {"bfs_fused_all", trav_kernel(TK_FUSED_ALL, ALG_BFS), true},
+      {"sssp_fused_all", trav_kernel(TK_FUSED_ALL, ALG_SSSP), true},
+      {"wcc_fused_all", trav_kernel(TK_FUSED_ALL, ALG_WCC), true},
+      {"wcc_seq", trav_kernel(TK_SEQ, ALG_WCC), false},
+      {"wcc_seq_wide", trav_kernel(TK_SEQ_WIDE, ALG_WCC), false},
       {"bfs_seq", trav_kernel(TK_SEQ, 0), false},
       {"sssp_seq", trav_kernel(TK_SEQ, 1), false},
       {"bfs_seq_wide", trav_kernel(TK_SEQ_WIDE, 0), false},

@@ -472,7 +472,8 @@ SX_DEV int after_scan(const VGrid &vg, const KArgs &a, KState &q, const Totals &
                       const Totals &TA, LdsK &lds) {
   q.alive_arcs = TA.mf;
   if (T.nf > 0) return 1;
-  if (TA.nf == 0) return -1;
+  // fixed k: a scan that finds nothing to delete ends the run
+  if (TA.nf == 0 || a.P.kfix) return -1;
   // empty level: jump to the smallest surviving degree
   const unsigned mind = alive_min_degree(vg, a.w, q.s & 1, lds);
   q.k = (int)mind > q.k + 1 ? (int)mind : q.k + 1;
@@ -518,7 +519,7 @@ __global__ void __launch_bounds__(kBlock) k_kcore_fused(KArgs a) {
   __shared__ LdsK lds;
   Ctrl *C = a.w.ctrl;
   const VGrid vg = hw_grid();
-  GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]));
+  GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]), a.P.watchdog);
   fetch_line(C->aux, C, lds.sq);
   KState q;
   q.k = (int)lds.sq[AUX_K];
@@ -572,6 +573,7 @@ __global__ void __launch_bounds__(kBlock) k_kcore_fused(KArgs a) {
       V = kview(vg, a.w, q.j % 3, regions(a.w, q.j & 1, vg.nb), lds, ref);
       have = true;
       q.from_scan = false;
+      if (V.nf == 0 && a.P.kfix) { save(EXIT_DONE); return; }
       if (V.nf == 0) { ++q.k; kind = 0; continue; }
       if (V.ovf || a.P.filter == 2) { kind = 0; continue; }   // rebuild by a scan at the same k
       pull = pull_step(q, V, a.P);
@@ -587,8 +589,8 @@ __global__ void __launch_bounds__(kBlock) k_kcore_fused(KArgs a) {
 // launch L (a peel) appended to the next list.
 enum : unsigned { KP_SCAN = 0, KP_PEEL = 1, KP_DONE = 6, KP_ERROR = 7, KP_LIMIT = 8 };
 
-__global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
-  __shared__ LdsK lds;
+// Returns whether the launch ran a phase of an active run.
+SX_DEV bool kcore_seq_body(const KArgs &a, unsigned L, LdsK &lds) {
   Ctrl *C = a.w.ctrl;
   const VGrid vg = hw_grid();
   Line &out = C->seq[(L + 1) & 1];
@@ -613,9 +615,10 @@ __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
       store_relaxed((unsigned long long *)&out.v[6], q.alive_arcs);
     }
   };
-  if (phase >= KP_DONE) { save(phase); return; }
-  if (lds.sq[32]) { due = 0; save(KP_ERROR); return; }
-  if ((long long)q.s + q.j > 4ll * a.g.n + 64) { due = 0; save(KP_LIMIT); return; }
+  if (phase >= KP_DONE) { save(phase); return false; }
+  if (lds.sq[32]) { due = 0; save(KP_ERROR); return false; }
+  if ((long long)q.s + q.j > 4ll * a.g.n + 64) { due = 0; save(KP_LIMIT); return false; }
+  seq_stall_enter(C, vg.bid);
   ViewRef ref;
   Totals V;
   bool have = false, pull = false;
@@ -627,17 +630,19 @@ __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
       if (lead) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
       due = 0;
       save(KP_ERROR);
-      return;
+      return true;
     }
     const int r = after_scan(vg, a, q, V, TA, lds);
     due = 0;
-    if (r < 0) { save(KP_DONE); return; }
+    if (r < 0) { save(KP_DONE); return true; }
     if (r == 0) phase = KP_SCAN;
     else { phase = KP_PEEL; q.from_scan = true; pull = pull_step(q, V, a.P); }
   } else if (due == 2 && lds.sq[30] != L) {
     // the peel appended nothing (no workgroup stamped the line): next level
+    // (fixed k: the level is exhausted, the run is done)
     q.from_scan = false;
     due = 0;
+    if (a.P.kfix) { save(KP_DONE); return true; }
     ++q.k;
     phase = KP_SCAN;
   } else if (due == 2) {
@@ -645,6 +650,7 @@ __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
     have = true;
     q.from_scan = false;
     due = 0;
+    if (V.nf == 0 && a.P.kfix) { save(KP_DONE); return true; }
     if (V.nf == 0) { ++q.k; phase = KP_SCAN; }
     else if (V.ovf || a.P.filter == 2) phase = KP_SCAN;
     else { phase = KP_PEEL; pull = pull_step(q, V, a.P); }
@@ -666,15 +672,39 @@ __global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
     due = 2;
     save(KP_PEEL);
   }
+  return true;
 }
 
-__global__ void k_kcore_seq_start(Ctrl *C) {
-  if (threadIdx.x < 32) C->seq[0].v[threadIdx.x] = 0u;   // first scan of level 0
+__global__ void __launch_bounds__(kBlock) k_kcore_seq(KArgs a, unsigned L) {
+  __shared__ LdsK lds;
+  if (kcore_seq_body(a, L, lds)) seq_stall_leave(a.w.ctrl, blockIdx.x);
+}
+
+// first scan at level k0 (0: the decomposition; k - 1 for membership in the
+// k-core)
+__global__ void k_kcore_seq_start(Ctrl *C, unsigned k0) {
+  if (threadIdx.x < 32) C->seq[0].v[threadIdx.x] = threadIdx.x == 1 ? k0 : 0u;
 }
 
 hipError_t kcore_seq_launch(const KArgs &a, unsigned L, int grid, hipStream_t s, bool start) {
-  if (start) hipLaunchKernelGGL(k_kcore_seq_start, dim3(1), dim3(64), 0, s, a.w.ctrl);
+  if (start)
+    hipLaunchKernelGGL(k_kcore_seq_start, dim3(1), dim3(64), 0, s, a.w.ctrl,
+                       a.P.kfix > 0 ? (unsigned)(a.P.kfix - 1) : 0u);
   else hipLaunchKernelGGL(k_kcore_seq, dim3(grid), dim3(kBlock), 0, s, a, L);
+  return hipGetLastError();
+}
+
+__global__ void k_kcore_member(int *core, int n) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (long long)gridDim.x * blockDim.x)
+    core[v] = core[v] == -1 ? 1 : 0;
+}
+
+hipError_t kcore_membership(int *core, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long grid = ((long long)n + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_kcore_member, dim3((unsigned)grid), dim3(256), 0, s, core, n);
   return hipGetLastError();
 }
 
@@ -710,10 +740,11 @@ __global__ void __launch_bounds__(kBlock) k_kcore_init(KArgs a) {
   if (vg.bid == 0) reset_barrier(C);
   if (vg.bid == 0 && threadIdx.x == 0) {
     for (int i = 0; i < 32; ++i) { C->state.v[i] = 0; C->stats.v[i] = 0; C->aux.v[i] = 0; }
+    // fixed k: the first scan is at level k - 1
+    if (a.P.kfix > 0) C->aux.v[AUX_K] = (unsigned)(a.P.kfix - 1);
     C->error.v[0] = 0;
   }
-  if (vg.bid == 1 || vg.nb == 1)
-    for (int i = threadIdx.x; i < kStatLines * 4; i += blockDim.x) C->statw[i / 4].v[i % 4] = 0u;
+  if (vg.bid == 1 || vg.nb == 1) reset_stat_lines(C);
 }
 
 hipError_t kcore_launch(const KArgs &a, int grid, hipStream_t s, bool init) {

@@ -161,6 +161,38 @@ __global__ void __launch_bounds__(256) k_mlp_adam(float *__restrict__ P, const f
   P[q] -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// Batch inference through the function the engine's decisions call
+// (mlp_eval_wave): weights staged in LDS, one wavefront per sample.
+__global__ void __launch_bounds__(256) k_mlp_forward_wave(const float *__restrict__ P,
+                                                          const float *__restrict__ X, int n,
+                                                          float *__restrict__ Y) {
+  __shared__ __attribute__((aligned(16))) float p[kMlpParams + 4];
+  for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) p[i] = P[i];
+  __syncthreads();
+  const int waves = (int)(gridDim.x * blockDim.x / 64);
+  for (int s = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); s < n; s += waves) {
+    float x[kMlpIn], y[kMlpOut];
+#pragma unroll
+    for (int i = 0; i < kMlpIn; ++i) x[i] = X[(size_t)s * kMlpIn + i];
+    mlp_eval_wave(p, x, y);
+    if (lane_id() < kMlpOut) {
+      float v = y[0];
+      if (lane_id() == 1) v = y[1];
+      else if (lane_id() == 2) v = y[2];
+      else if (lane_id() == 3) v = y[3];
+      Y[(size_t)s * kMlpOut + lane_id()] = v;
+    }
+  }
+}
+
+hipError_t mlp_forward_wave(const float *P, const float *X, int n, float *Y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int grid = (n + 3) / 4;
+  if (grid > 2048) grid = 2048;
+  hipLaunchKernelGGL(k_mlp_forward_wave, dim3(grid), dim3(256), 0, s, P, X, n, Y);
+  return hipGetLastError();
+}
+
 hipError_t mlp_forward(const float *P, const float *X, int n, float *Y, float *H, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mlp_forward, dim3((n + 255) / 256), dim3(256), 0, s, P, X, n, Y, H);

@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) k_pr_fused(PrArgs a) {
   __shared__ LdsPr lds;
   Ctrl *C = a.w.ctrl;
   const VGrid vg = hw_grid();
-  GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]));
+  GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]), a.P.watchdog);
   pr_lists(a, lds);
   if (!bar.sync()) return;
   ViewRef L;
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_pr_init(PrArgs a) {
     C->error.v[0] = 0;
   }
   if (blockIdx.x == 1 || gridDim.x == 1)
-    for (int i = threadIdx.x; i < kStatLines * 4; i += blockDim.x) a.w.ctrl->statw[i / 4].v[i % 4] = 0u;
+    reset_stat_lines(a.w.ctrl);
 }
 
 hipError_t pagerank_launch(const PrArgs &a, int grid, hipStream_t s) {

@@ -8,9 +8,12 @@
 // PageRank s24 55 -> 45 ms).  Runs then compute in the new numbering; the
 // source is mapped in and the result is mapped back into the caller's array.
 //
-// The two sorts are rocPRIM's (through hipCUB): a radix sort of (degree,
-// vertex) and a segmented radix sort of the rows, both deterministic.
-#include <hipcub/hipcub.hpp>
+// The scan and the two sorts are rocPRIM's: an exclusive scan of the row
+// lengths, a radix sort of (degree, vertex) and a segmented radix sort of the
+// rows, both sorts deterministic.
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "sx_kernels.hpp"
 #include "sx_device.hpp"
@@ -95,10 +98,10 @@ static hipError_t reorder_rows(const int *off, const int *idx, const unsigned *w
   hipLaunchKernelGGL(k_rk_rowlen, dim3(rk_grid(n + 1)), dim3(kRkBlock), 0, s, off, perm, n, len);
   RK_TRY(hipGetLastError());
   size_t bytes = 0;
-  RK_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, len, noff, n + 1, s));
+  RK_TRY(rocprim::exclusive_scan(nullptr, bytes, len, noff, 0, (size_t)n + 1, rocprim::plus<int>(), s));
   void *scratch = nullptr;
   RK_TRY(tmp(&scratch, bytes));
-  RK_TRY(hipcub::DeviceScan::ExclusiveSum(scratch, bytes, len, noff, n + 1, s));
+  RK_TRY(rocprim::exclusive_scan(scratch, bytes, len, noff, 0, (size_t)n + 1, rocprim::plus<int>(), s));
   if (m == 0) return hipSuccess;
   int *kin = nullptr;
   unsigned *vin = nullptr;
@@ -110,17 +113,17 @@ static hipError_t reorder_rows(const int *off, const int *idx, const unsigned *w
   const int bits = 32 - __builtin_clz((unsigned)(n > 1 ? n - 1 : 1));
   bytes = 0;
   if (w) {
-    RK_TRY(hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, bytes, kin, nidx, vin, nw, (int)m, n,
-                                                      noff, noff + 1, 0, bits, s));
+    RK_TRY(rocprim::segmented_radix_sort_pairs(nullptr, bytes, kin, nidx, vin, nw, (unsigned)m,
+                                               (unsigned)n, noff, noff + 1, 0, bits, s));
     RK_TRY(tmp(&scratch, bytes));
-    RK_TRY(hipcub::DeviceSegmentedRadixSort::SortPairs(scratch, bytes, kin, nidx, vin, nw, (int)m, n,
-                                                      noff, noff + 1, 0, bits, s));
+    RK_TRY(rocprim::segmented_radix_sort_pairs(scratch, bytes, kin, nidx, vin, nw, (unsigned)m,
+                                               (unsigned)n, noff, noff + 1, 0, bits, s));
   } else {
-    RK_TRY(hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, bytes, kin, nidx, (int)m, n, noff,
-                                                     noff + 1, 0, bits, s));
+    RK_TRY(rocprim::segmented_radix_sort_keys(nullptr, bytes, kin, nidx, (unsigned)m, (unsigned)n,
+                                              noff, noff + 1, 0, bits, s));
     RK_TRY(tmp(&scratch, bytes));
-    RK_TRY(hipcub::DeviceSegmentedRadixSort::SortKeys(scratch, bytes, kin, nidx, (int)m, n, noff,
-                                                     noff + 1, 0, bits, s));
+    RK_TRY(rocprim::segmented_radix_sort_keys(scratch, bytes, kin, nidx, (unsigned)m, (unsigned)n,
+                                              noff, noff + 1, 0, bits, s));
   }
   return hipSuccess;
 }
@@ -142,10 +145,10 @@ hipError_t reorder_build(const DevGraph &g, const RkAlloc &own, const RkAlloc &t
                        g.directed ? g.in_off : (const int *)nullptr, n, key, ids);
     RK_TRY(hipGetLastError());
     size_t bytes = 0;
-    RK_TRY(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, bytes, key, key_s, ids, perm, n, 0, 32, s));
+    RK_TRY(rocprim::radix_sort_pairs_desc(nullptr, bytes, key, key_s, ids, perm, (unsigned)n, 0, 32, s));
     void *scratch = nullptr;
     RK_TRY(tmp(&scratch, bytes));
-    RK_TRY(hipcub::DeviceRadixSort::SortPairsDescending(scratch, bytes, key, key_s, ids, perm, n, 0, 32, s));
+    RK_TRY(rocprim::radix_sort_pairs_desc(scratch, bytes, key, key_s, ids, perm, (unsigned)n, 0, 32, s));
     hipLaunchKernelGGL(k_rk_inverse, dim3(rk_grid(n)), dim3(kRkBlock), 0, s, perm, inv, n);
     RK_TRY(hipGetLastError());
   }

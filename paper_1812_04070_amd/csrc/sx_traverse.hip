@@ -14,6 +14,10 @@
 //         tech-compute(a)).  Compute: dist(v) + w(v,u).  Combine: minimum
 //         (aggregation): push lowers dist(u) with an atomic minimum, pull
 //         reduces over the in-arcs and the single owner writes, no atomics.
+//   WCC   (connected components, Section 3.2) Active: label lowered in the
+//         previous iteration; every vertex at the start, with its own id as
+//         label.  Compute: label(v).  Combine: minimum, as for SSSP.  At the
+//         fixpoint every vertex holds the smallest id of its component.
 //
 // The same phases run in four arrangements:
 //   fused      persistent kernels, one per direction, iterating until the
@@ -40,6 +44,7 @@ namespace sx {
 // ------------------------------------------------------------- ACC ops ---
 struct BfsOps {
   static constexpr bool kVote = true;
+  static constexpr bool kWeighted = false;
   int *depth;
   int it;
   // push Compute + Combine for kIlp arcs v->u per lane; act[r]: u becomes
@@ -63,6 +68,7 @@ struct BfsOps {
 
 struct SsspOps {
   static constexpr bool kVote = false;
+  static constexpr bool kWeighted = true;
   unsigned *dist;
   int *stamp;
   int it;
@@ -102,7 +108,63 @@ struct SsspOps {
   SX_DEV bool pull_candidate(int v) const { (void)v; return true; }
 };
 
+// Minimum-label propagation: the SSSP relaxation with a zero arc weight (the
+// label a vertex offers is its own), so labels never overflow.
+struct WccOps {
+  static constexpr bool kVote = false;
+  static constexpr bool kWeighted = false;
+  unsigned *dist;               // labels
+  int *stamp;
+  int it;
+  SX_DEV void push(const int *v, const int *u, const int *arc, const bool *ok, const DevGraph &g,
+                   unsigned &err, bool *act, unsigned &lowest) const {
+    (void)arc; (void)g; (void)err; (void)lowest;
+    unsigned lv[kIlp], lu[kIlp], old[kIlp];
+    bool tr[kIlp];
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) {
+      lv[r] = ok[r] ? dist[v[r]] : 0u;
+      lu[r] = ok[r] ? dist[u[r]] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) {
+      tr[r] = ok[r] && lv[r] < lu[r];
+      old[r] = tr[r] ? atomic_min_u32(&dist[u[r]], lv[r]) : 0u;
+    }
+    int st[kIlp];
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) {
+      tr[r] = tr[r] && lv[r] < old[r];
+      st[r] = tr[r] ? atomic_exch_i32(&stamp[u[r]], it + 1) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kIlp; ++r) act[r] = tr[r] && st[r] != it + 1;
+  }
+  SX_DEV bool next_active(int v) const { return stamp[v] == it + 1; }
+  SX_DEV bool in_frontier(int v) const { return stamp[v] == it; }
+  SX_DEV bool pull_candidate(int v) const { (void)v; return true; }
+};
+
 SX_DEV int degree_of(const int *off, int v) { return off[v + 1] - off[v]; }
+
+// What a frontier neighbour u offers v over arc `arc` in a pull step: its
+// distance plus the arc weight (SSSP; err on a sum that reaches infinity) or
+// its label (WCC).
+template <class Ops>
+SX_DEV unsigned pull_offer(const unsigned *dist, const DevGraph &g, int u, int arc, unsigned &err) {
+  const unsigned du = dist[u];
+  if constexpr (!Ops::kWeighted) {
+    (void)g; (void)arc; (void)err;
+    return du;
+  } else {
+    const unsigned c = du + g.in_w[arc];
+    if (c < du || c == 0xFFFFFFFFu) {
+      err = SX_ERR_OVERFLOW;
+      return 0xFFFFFFFFu;
+    }
+    return c;
+  }
+}
 
 struct LdsTrav {
   int small[kWaves][192];
@@ -291,6 +353,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
   unsigned *dist = (unsigned *)a.state_i;
   WaveStats st;
   long long edges = 0;
+  unsigned err = 0;
   const int lane = lane_id();
   const unsigned gw = vg.bid * kWaves + wave_in_wg();
   const unsigned nw = vg.nb * kWaves;
@@ -313,7 +376,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
         if (fbit(fb, u)) {
           hit = true;
           if (!Ops::kVote) {
-            const unsigned c = dist[u] + g.in_w[arc];
+            const unsigned c = pull_offer<Ops>(dist, g, u, arc, err);
             best = c < best ? c : best;
           }
         }
@@ -359,7 +422,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
         if (fbit(fb, u)) {
           hit = true;
           if (!Ops::kVote) {
-            const unsigned c = dist[u] + g.in_w[arc];
+            const unsigned c = pull_offer<Ops>(dist, g, u, arc, err);
             best = c < best ? c : best;
           }
         }
@@ -417,7 +480,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
 #pragma unroll
             for (int j = 0; j < 4; ++j)
               if (h[j]) {
-                const unsigned cc = dist[u[j]] + g.in_w[arc + j];
+                const unsigned cc = pull_offer<Ops>(dist, g, u[j], arc + j, err);
                 best = cc < best ? cc : best;
               }
             edges += 4;
@@ -426,7 +489,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
             ++edges;
             const int u1 = g.in_idx[arc];
             if (fbit(fb, u1)) {
-              const unsigned cc = dist[u1] + g.in_w[arc];
+              const unsigned cc = pull_offer<Ops>(dist, g, u1, arc, err);
               best = cc < best ? cc : best;
             }
           }
@@ -441,6 +504,7 @@ SX_PHASE void pull_phase(const VGrid &vg, const TravArgs &a, const Params &P, in
     bins_append(act, v, act ? out_deg(v, d) : 0, NR, vg.bid, P, P.chunk, lds.bins, st);
   }
   bins_end(lds.bins, st, a.w.rec + ((it + 1) % 3), vg.bid);
+  if (err) raise_error(a.w.ctrl, err);
   add_stats(a.w.ctrl, vg.bid, edges, vg.bid == 0 ? (unsigned long long)cs + cm + cl : 0ull, lds.red);
   if (vg.bid == 0 && threadIdx.x == 0) atomic_add_u32(&a.w.ctrl->stats.v[5], 1u);
 }
@@ -484,7 +548,7 @@ struct LdsPolicy {
 // ballot rebuild: the online lists are incomplete.
 template <class Ops>
 SX_DEV Decision decide(const TravArgs &a, RunState &s, bool pulling, const Totals &T,
-                       LdsPolicy *pol, bool stage = false) {
+                       LdsPolicy *pol, bool lead, bool stage = false) {
   DecideIn in;
   in.nf = T.nf;
   in.mf = T.mf;
@@ -509,6 +573,13 @@ SX_DEV Decision decide(const TravArgs &a, RunState &s, bool pulling, const Total
       mlp_eval_wave(pol->p, x, y);
       if (lane_id() == 0)
         for (int k = 0; k < kMlpOut; ++k) pol->y[k] = y[k];
+      // the last evaluation of the run goes to the statistics (workgroup 0)
+      if (lane_id() == 0 && lead) {
+        Line &pl = a.w.ctrl->pol;
+        for (int k = 0; k < kMlpIn; ++k) store_relaxed(&pl.v[1 + k], __float_as_uint(x[k]));
+        for (int k = 0; k < kMlpOut; ++k) store_relaxed(&pl.v[1 + kMlpIn + k], __float_as_uint(y[k]));
+        store_relaxed(&pl.v[0], load_relaxed(&pl.v[0]) + 1u);
+      }
     }
     __syncthreads();
     const float y0 = pol->y[0], y1 = pol->y[1], y2 = pol->y[2], y3 = pol->y[3];
@@ -535,6 +606,10 @@ SX_DEV BfsOps make_ops<BfsOps>(const TravArgs &a, int it) { return BfsOps{a.stat
 template <>
 SX_DEV SsspOps make_ops<SsspOps>(const TravArgs &a, int it) {
   return SsspOps{(unsigned *)a.state_i, a.w.stamp, it};
+}
+template <>
+SX_DEV WccOps make_ops<WccOps>(const TravArgs &a, int it) {
+  return WccOps{(unsigned *)a.state_i, a.w.stamp, it};
 }
 
 // Stage the network's weights in LDS (all threads; a barrier must follow
@@ -579,102 +654,125 @@ SX_DEV bool entry_done(Ctrl *C) {
 
 // ------------------------------------------------ one query, in a loop ---
 // The iteration loop of one query over a (virtual) grid synchronised by
-// `bar`.  The fused kernels run one direction each (`both` = false: leave
-// the loop to switch kernels); the batched kernel runs both (`both` = true:
-// switch in place).  Returns the exit reason.
-template <class Ops>
+// `bar`.  kDir 0 / 1: the push / pull kernel of selective fusion -- only that
+// direction's phases are compiled in, and a direction change leaves the loop
+// (EXIT_SWITCH) so that the host launches the other kernel; kDir 2: both
+// directions, switching in place (all fusion and the batched kernel).
+// Returns the exit reason.
+template <class Ops, int kDir>
 SX_DEV int run_loop(const VGrid &vg, const TravArgs &a, GridBarrier &bar, LdsTrav &lds,
-                    LdsPolicy &pol, RunState &s, bool &pulling, bool &rebuilt, bool both) {
+                    LdsPolicy &pol, RunState &s, bool &pulling, bool &rebuilt) {
+  constexpr bool both = kDir == 2;
   Ctrl *C = a.w.ctrl;
   ViewRef ref;
   Totals T;
-  if (!pulling) {
-    // the lists of s.it: online (slot it % 3) unless a scan rebuilt them; an
-    // online list that overflowed (appended by a pull iteration) is rebuilt
-    if (!rebuilt) {
-      T = make_view(vg, a, s.it % 3, s.it & 1, lds, ref);
-      if (T.ovf) {
-        Ops ops = make_ops<Ops>(a, s.it - 1);
-        ballot_next(vg, a, s.P, ops, s.it - 1, lds);
-        if (!bar.sync()) return EXIT_ERROR;
-        rebuilt = true;
+  if constexpr (kDir != 1) {
+    if (!pulling) {
+      // the lists of s.it: online (slot it % 3) unless a scan rebuilt them;
+      // an online list that overflowed (appended by a pull iteration) is
+      // rebuilt
+      if (!rebuilt) {
+        T = make_view(vg, a, s.it % 3, s.it & 1, lds, ref);
+        if (T.ovf) {
+          Ops ops = make_ops<Ops>(a, s.it - 1);
+          ballot_next(vg, a, s.P, ops, s.it - 1, lds);
+          if (!bar.sync()) return EXIT_ERROR;
+          rebuilt = true;
+        }
       }
-    }
-    if (rebuilt) {
-      T = make_view(vg, a, SLOT_SCAN, s.it & 1, lds, ref);
-      if (!scan_fits(a, T)) return EXIT_ERROR;
+      if (rebuilt) {
+        T = make_view(vg, a, SLOT_SCAN, s.it & 1, lds, ref);
+        if (!scan_fits(a, T)) return EXIT_ERROR;
+      }
     }
   }
   for (;;) {
     if (!pulling) {
-      if (vg.bid == 0 && threadIdx.x == 0) atomic_add_u32(&C->stats.v[6], 1u);
-      Ops ops = make_ops<Ops>(a, s.it);
-      push_phase(vg, a, s.P, ops, s.it, ref, T, lds);
-      if (!bar.sync()) return EXIT_ERROR;
-      T = make_view(vg, a, (s.it + 1) % 3, (s.it + 1) & 1, lds, ref);
-      Decision d = decide<Ops>(a, s, false, T, &pol);
-      rebuilt = false;
-      if (d.done) { ++s.it; return s.it >= a.P.max_iters ? EXIT_LIMIT : EXIT_DONE; }
-      if (d.to_pull) {
-        ++s.it;
-        pulling = true;
-        if (!both) return EXIT_SWITCH;
-        continue;
-      }
-      if (d.ballot) {
-        ballot_next(vg, a, s.P, ops, s.it, lds);
+      if constexpr (kDir == 1) {
+        return EXIT_SWITCH;
+      } else {
+        if (vg.bid == 0 && threadIdx.x == 0) atomic_add_u32(&C->stats.v[6], 1u);
+        Ops ops = make_ops<Ops>(a, s.it);
+        push_phase(vg, a, s.P, ops, s.it, ref, T, lds);
         if (!bar.sync()) return EXIT_ERROR;
-        T = make_view(vg, a, SLOT_SCAN, (s.it + 1) & 1, lds, ref);
-        if (!scan_fits(a, T)) return EXIT_ERROR;
-        rebuilt = true;
-      }
-      ++s.it;
-    } else {
-      if (vg.bid == 0 && threadIdx.x == 0) atomic_add_u32(&C->stats.v[6], 1u);
-      Ops ops = make_ops<Ops>(a, s.it);
-      pull_scan(vg, a, s.P, ops, s.it, lds);
-      if (!bar.sync()) return EXIT_ERROR;
-      T = make_view(vg, a, SLOT_SCAN, s.it & 1, lds, ref);
-      if (!scan_fits(a, T)) return EXIT_ERROR;
-      pull_phase<Ops>(vg, a, s.P, s.it, ref, T, lds);
-      if (!bar.sync()) return EXIT_ERROR;
-      T = make_view(vg, a, (s.it + 1) % 3, (s.it + 1) & 1, lds, ref);
-      Decision d = decide<Ops>(a, s, true, T, &pol);
-      if (d.done) { ++s.it; return s.it >= a.P.max_iters ? EXIT_LIMIT : EXIT_DONE; }
-      ++s.it;
-      if (d.to_push) {
-        pulling = false;
+        T = make_view(vg, a, (s.it + 1) % 3, (s.it + 1) & 1, lds, ref);
+        Decision d = decide<Ops>(a, s, false, T, &pol, vg.bid == 0);
         rebuilt = false;
-        if (T.ovf) {
-          Ops o2 = make_ops<Ops>(a, s.it - 1);
-          ballot_next(vg, a, s.P, o2, s.it - 1, lds);
+        if (d.done) { ++s.it; return s.it >= a.P.max_iters ? EXIT_LIMIT : EXIT_DONE; }
+        if (d.to_pull) {
+          ++s.it;
+          pulling = true;
+          if (!both) return EXIT_SWITCH;
+          continue;
+        }
+        if (d.ballot) {
+          ballot_next(vg, a, s.P, ops, s.it, lds);
           if (!bar.sync()) return EXIT_ERROR;
-          T = make_view(vg, a, SLOT_SCAN, s.it & 1, lds, ref);
+          T = make_view(vg, a, SLOT_SCAN, (s.it + 1) & 1, lds, ref);
           if (!scan_fits(a, T)) return EXIT_ERROR;
           rebuilt = true;
         }
-        if (!both) return EXIT_SWITCH;
+        ++s.it;
+      }
+    } else {
+      if constexpr (kDir == 0) {
+        return EXIT_SWITCH;
+      } else {
+        if (vg.bid == 0 && threadIdx.x == 0) atomic_add_u32(&C->stats.v[6], 1u);
+        Ops ops = make_ops<Ops>(a, s.it);
+        pull_scan(vg, a, s.P, ops, s.it, lds);
+        if (!bar.sync()) return EXIT_ERROR;
+        T = make_view(vg, a, SLOT_SCAN, s.it & 1, lds, ref);
+        if (!scan_fits(a, T)) return EXIT_ERROR;
+        pull_phase<Ops>(vg, a, s.P, s.it, ref, T, lds);
+        if (!bar.sync()) return EXIT_ERROR;
+        T = make_view(vg, a, (s.it + 1) % 3, (s.it + 1) & 1, lds, ref);
+        Decision d = decide<Ops>(a, s, true, T, &pol, vg.bid == 0);
+        if (d.done) { ++s.it; return s.it >= a.P.max_iters ? EXIT_LIMIT : EXIT_DONE; }
+        ++s.it;
+        if (d.to_push) {
+          pulling = false;
+          rebuilt = false;
+          if (T.ovf) {
+            Ops o2 = make_ops<Ops>(a, s.it - 1);
+            ballot_next(vg, a, s.P, o2, s.it - 1, lds);
+            if (!bar.sync()) return EXIT_ERROR;
+            T = make_view(vg, a, SLOT_SCAN, s.it & 1, lds, ref);
+            if (!scan_fits(a, T)) return EXIT_ERROR;
+            rebuilt = true;
+          }
+          if (!both) return EXIT_SWITCH;
+        }
       }
     }
   }
 }
 
 // -------------------------------------------------- persistent kernels ---
-template <class Ops>
-__global__ void __launch_bounds__(kBlock) k_fused(TravArgs a, int pull) {
+// kMode 0 / 1: selective fusion, the paper's design (Section 5, Table
+// table-compile): one persistent kernel per direction, each holding only
+// its own direction's phases; a direction change exits the kernel and the
+// host launches the other one.  kMode 2: all fusion, both directions in one
+// persistent kernel that switches in place (the loop the batched kernel
+// runs), at the register cost of both directions' code in one kernel.
+template <class Ops, int kMode>
+__global__ void __launch_bounds__(kBlock) k_fused(TravArgs a) {
   __shared__ LdsTrav lds;
   __shared__ LdsPolicy pol;
   Ctrl *C = a.w.ctrl;
   const VGrid vg = hw_grid();
-  GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]));
+  GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]), a.P.watchdog);
   if (entry_done(C) || bar.failed()) return;
   RunState s;
   bool rebuilt;
   load_state(a, s, rebuilt);
   load_policy(a, pol);
-  bool pulling = pull != 0;
-  const int r = run_loop<Ops>(vg, a, bar, lds, pol, s, pulling, rebuilt, false);
+  // the direction the run is in: state word 3 (1 = pulling), kept across
+  // the launches of a run
+  bool pulling = load_relaxed(&C->state.v[3]) != 0;
+  const int r = run_loop<Ops, kMode>(vg, a, bar, lds, pol, s, pulling, rebuilt);
   finish(vg, C, r, s, rebuilt);
+  if (vg.bid == 0 && threadIdx.x == 0) store_relaxed(&C->state.v[3], pulling ? 1u : 0u);
 }
 
 // ------------------------------------------------ one-phase kernels ---
@@ -755,10 +853,9 @@ SX_DEV void seq_store(Line &l, unsigned phase, const RunState &s, unsigned pulli
 // into throughput (R-MAT s22 SSSP 3.39 -> 3.09 ms).  The spills lengthen
 // each phase's critical path, so graphs with small frontiers and thousands
 // of iterations use kMinWaves = 1 (the compiler's own choice, no spills).
-template <class Ops, int kMinWaves>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMinWaves))) k_seq(TravArgs a, unsigned L) {
-  __shared__ LdsTrav lds;
-  __shared__ LdsPolicy pol;
+// Returns whether the launch ran a phase of an active run.
+template <class Ops>
+SX_DEV bool seq_body(const TravArgs &a, unsigned L, LdsTrav &lds, LdsPolicy &pol) {
   Ctrl *C = a.w.ctrl;
   const VGrid vg = hw_grid();
   Line &out = C->seq[(L + 1) & 1];
@@ -780,12 +877,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMi
   s.dropped = in[14];
   if (phase >= SEQ_DONE) {
     if (lead) seq_store(out, phase, s, pulling, 0, rebuilt);
-    return;
+    return false;
   }
   if (in[32]) {
     if (lead) seq_store(out, SEQ_ERROR, s, pulling, 0, rebuilt);
-    return;
+    return false;
   }
+  seq_stall_enter(C, vg.bid);
   ViewRef ref;
   Totals T;
   bool have_view = false;
@@ -793,11 +891,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMi
     T = make_view(vg, a, (s.it + 1) % 3, (s.it + 1) & 1, lds, ref);
     // one launch per phase: the weights are staged only by a launch whose
     // decision evaluates the network
-    Decision d = decide<Ops>(a, s, pulling != 0, T, &pol, true);
+    Decision d = decide<Ops>(a, s, pulling != 0, T, &pol, vg.bid == 0, true);
     if (d.done) {
       ++s.it;
       if (lead) seq_store(out, s.it >= a.P.max_iters ? SEQ_LIMIT : SEQ_DONE, s, pulling, 0, 0);
-      return;
+      return true;
     }
     // delta-stepping: once no listed vertex lies below the bound, move it to
     // the end of the bucket holding the smallest listed distance (empty
@@ -864,14 +962,25 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMi
   // a capacity error leaves `out` unwritten: the next launch sees the error
   if (lead && load_relaxed(&C->error.v[0]) == SX_ERR_CAPACITY)
     seq_store(out, SEQ_ERROR, s, pulling, 0, rebuilt);
+  return true;
 }
 
-// first state of a sequenced run (after k_trav_init)
-__global__ void k_seq_start(Ctrl *C, unsigned pull_first) {
+template <class Ops, int kMinWaves>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMinWaves))) k_seq(TravArgs a, unsigned L) {
+  __shared__ LdsTrav lds;
+  __shared__ LdsPolicy pol;
+  if (seq_body<Ops>(a, L, lds, pol)) seq_stall_leave(a.w.ctrl, blockIdx.x);
+}
+
+// first state of a sequenced run (after k_trav_init).  all_active: every
+// vertex is active in iteration 0 (WCC), so a push start first builds the
+// lists of iteration 0 by a ballot scan (iteration -1's next lists).
+__global__ void k_seq_start(Ctrl *C, unsigned pull_first, unsigned all_active) {
   if (threadIdx.x == 0) {
     Line &l = C->seq[0];
     for (int i = 0; i < 32; ++i) l.v[i] = 0u;
-    l.v[0] = pull_first ? PH_PULL_SCAN : PH_PUSH;
+    l.v[0] = pull_first ? PH_PULL_SCAN : (all_active ? PH_BALLOT : PH_PUSH);
+    if (!pull_first && all_active) l.v[1] = 0xFFFFFFFFu;
     l.v[10] = pull_first;
     *(unsigned long long *)&l.v[2] = *(unsigned long long *)&C->state.v[6];
     // delta-stepping: smallest distance set by each step (three rotating words)
@@ -881,12 +990,15 @@ __global__ void k_seq_start(Ctrl *C, unsigned pull_first) {
 
 // ------------------------------------------------------------ set-up ---
 // Vertex state: BFS depth -1 (source 0); SSSP distance infinity (source 0)
-// and stamp -1 (source 0).
-SX_DEV void init_state(const VGrid &vg, const TravArgs &a, bool sssp) {
+// and stamp -1 (source 0); WCC label = own id and stamp 0 (all active).
+SX_DEV void init_state(const VGrid &vg, const TravArgs &a, bool sssp, bool wcc = false) {
   const int n = a.g.n;
   const long long tid = (long long)vg.bid * kBlock + threadIdx.x, nt = (long long)vg.nb * kBlock;
   for (long long v = tid; v < n; v += nt) {
-    if (sssp) {
+    if (wcc) {
+      a.state_i[v] = (int)v;
+      a.w.stamp[v] = 0;
+    } else if (sssp) {
       ((unsigned *)a.state_i)[v] = v == a.src ? 0u : 0xFFFFFFFFu;
       a.w.stamp[v] = v == a.src ? 0 : -1;
     } else {
@@ -919,10 +1031,14 @@ SX_DEV void init_source(const TravArgs &a, unsigned G) {
   }
 }
 
-// Run set-up: vertex state, a fresh control block, the source list.
+// Run set-up: vertex state, a fresh control block, the source list (WCC:
+// none; its first lists come from a ballot scan or a pull step, and the
+// persistent and one-phase arrangements are told so by state word 2).
 // Launched with any grid of at least 2 workgroups; G = the run's grid.
-__global__ void k_trav_init(TravArgs a, int is_sssp, unsigned long long mu0, unsigned G) {
-  init_state(hw_grid(), a, is_sssp != 0);
+__global__ void k_trav_init(TravArgs a, int algo, unsigned long long mu0, unsigned G,
+                            unsigned pull_first) {
+  const bool wcc = algo == ALG_WCC;
+  init_state(hw_grid(), a, algo == ALG_SSSP, wcc);
   Ctrl *C = a.w.ctrl;
   if (blockIdx.x == 0) reset_barrier(C);
   if (blockIdx.x == 0 && threadIdx.x < 64) {
@@ -931,12 +1047,13 @@ __global__ void k_trav_init(TravArgs a, int is_sssp, unsigned long long mu0, uns
       C->error.v[0] = 0;
       // arcs not yet explored: all but the source's
       *(unsigned long long *)&C->state.v[6] =
-          mu0 ? mu0 : (unsigned long long)(a.g.m - degree_of(a.g.off, a.src));
+          wcc ? 0ull : (mu0 ? mu0 : (unsigned long long)(a.g.m - degree_of(a.g.off, a.src)));
+      if (wcc) C->state.v[2] = 1u;
+      C->state.v[3] = pull_first;
     }
-    init_source(a, G);
+    if (!wcc) init_source(a, G);
   }
-  if (blockIdx.x == 1)
-    for (int i = threadIdx.x; i < kStatLines * 4; i += blockDim.x) C->statw[i / 4].v[i % 4] = 0u;
+  if (blockIdx.x == 1) reset_stat_lines(C);
 }
 
 // ------------------------------------------------- batched queries ---
@@ -959,7 +1076,7 @@ SX_DEV bool batch_query(const VGrid &vg, const TravArgs &a, GridBarrier &bar, Ld
   s.ps.reached = 0;
   s.P = a.P;
   bool pulling = a.P.direction == 2, rebuilt = false;
-  const int r = run_loop<Ops>(vg, a, bar, lds, pol, s, pulling, rebuilt, true);
+  const int r = run_loop<Ops, 2>(vg, a, bar, lds, pol, s, pulling, rebuilt);
   finish(vg, a.w.ctrl, r, s, false);
   if (r == EXIT_ERROR) return false;
   return bar.sync();
@@ -975,7 +1092,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   if (team >= (unsigned)b.nteams) return;
   const Work w = b.work[team];
   Ctrl *C = w.ctrl;
-  GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]), vg);
+  GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]), b.P.watchdog, vg);
   TravArgs a;
   a.w = w;
   a.P = b.P;
@@ -1036,7 +1153,7 @@ __global__ void k_batch_reset(BatchArgs b) {
   if (team >= (unsigned)b.nteams) return;
   Ctrl *C = b.work[team].ctrl;
   reset_barrier(C);
-  for (int i = threadIdx.x; i < kStatLines * 4; i += blockDim.x) C->statw[i / 4].v[i % 4] = 0u;
+  reset_stat_lines(C);
   if (threadIdx.x == 0) C->error.v[0] = 0u;
   if (team == 0 && threadIdx.x == 0) *b.queue_head = 0u;
 }
@@ -1046,62 +1163,68 @@ __global__ void k_batch_reset(BatchArgs b) {
 // ------------------------------------------------------ host launchers ---
 namespace sx {
 
-const void *trav_kernel(int kind, int sssp) {
+// Kernel of kind `kind` for algorithm `algo` (ALG_BFS / ALG_SSSP / ALG_WCC).
+template <class Ops>
+static const void *trav_kernel_t(int kind) {
   switch (kind) {
-    case TK_FUSED: return sssp ? (const void *)k_fused<SsspOps> : (const void *)k_fused<BfsOps>;
-    case TK_PUSH_STEP: return sssp ? (const void *)k_push_step<SsspOps> : (const void *)k_push_step<BfsOps>;
-    case TK_BALLOT: return sssp ? (const void *)k_ballot<SsspOps> : (const void *)k_ballot<BfsOps>;
-    case TK_PULL_SCAN: return sssp ? (const void *)k_pull_scan<SsspOps> : (const void *)k_pull_scan<BfsOps>;
-    case TK_PULL_STEP: return sssp ? (const void *)k_pull_step<SsspOps> : (const void *)k_pull_step<BfsOps>;
-    case TK_SEQ: return sssp ? (const void *)k_seq<SsspOps, 1> : (const void *)k_seq<BfsOps, 1>;
-    case TK_SEQ_WIDE: return sssp ? (const void *)k_seq<SsspOps, 6> : (const void *)k_seq<BfsOps, 6>;
+    case TK_FUSED: return (const void *)k_fused<Ops, 0>;
+    case TK_FUSED_PULL: return (const void *)k_fused<Ops, 1>;
+    case TK_FUSED_ALL: return (const void *)k_fused<Ops, 2>;
+    case TK_PUSH_STEP: return (const void *)k_push_step<Ops>;
+    case TK_BALLOT: return (const void *)k_ballot<Ops>;
+    case TK_PULL_SCAN: return (const void *)k_pull_scan<Ops>;
+    case TK_PULL_STEP: return (const void *)k_pull_step<Ops>;
+    case TK_SEQ: return (const void *)k_seq<Ops, 1>;
+    case TK_SEQ_WIDE: return (const void *)k_seq<Ops, 6>;
     default: return nullptr;
   }
 }
 
-hipError_t trav_launch(int kind, int sssp, const TravArgs &a, int it, int arg, int grid,
-                       hipStream_t s) {
+const void *trav_kernel(int kind, int algo) {
+  switch (algo) {
+    case ALG_BFS: return trav_kernel_t<BfsOps>(kind);
+    case ALG_SSSP: return trav_kernel_t<SsspOps>(kind);
+    case ALG_WCC: return trav_kernel_t<WccOps>(kind);
+    default: return nullptr;
+  }
+}
+
+template <class Ops>
+static hipError_t trav_launch_t(int kind, const TravArgs &a, int it, int arg, int grid,
+                                hipStream_t s) {
   const dim3 g(grid), b(kBlock);
   switch (kind) {
-    case TK_FUSED:
-      if (sssp) hipLaunchKernelGGL(k_fused<SsspOps>, g, b, 0, s, a, arg);
-      else hipLaunchKernelGGL(k_fused<BfsOps>, g, b, 0, s, a, arg);
-      break;
-    case TK_PUSH_STEP:
-      if (sssp) hipLaunchKernelGGL(k_push_step<SsspOps>, g, b, 0, s, a, it, arg);
-      else hipLaunchKernelGGL(k_push_step<BfsOps>, g, b, 0, s, a, it, arg);
-      break;
-    case TK_BALLOT:
-      if (sssp) hipLaunchKernelGGL(k_ballot<SsspOps>, g, b, 0, s, a, it);
-      else hipLaunchKernelGGL(k_ballot<BfsOps>, g, b, 0, s, a, it);
-      break;
-    case TK_PULL_SCAN:
-      if (sssp) hipLaunchKernelGGL(k_pull_scan<SsspOps>, g, b, 0, s, a, it);
-      else hipLaunchKernelGGL(k_pull_scan<BfsOps>, g, b, 0, s, a, it);
-      break;
-    case TK_PULL_STEP:
-      if (sssp) hipLaunchKernelGGL(k_pull_step<SsspOps>, g, b, 0, s, a, it);
-      else hipLaunchKernelGGL(k_pull_step<BfsOps>, g, b, 0, s, a, it);
-      break;
-    case TK_SEQ:
-      if (sssp) hipLaunchKernelGGL((k_seq<SsspOps, 1>), g, b, 0, s, a, (unsigned)it);
-      else hipLaunchKernelGGL((k_seq<BfsOps, 1>), g, b, 0, s, a, (unsigned)it);
-      break;
-    case TK_SEQ_WIDE:
-      if (sssp) hipLaunchKernelGGL((k_seq<SsspOps, 6>), g, b, 0, s, a, (unsigned)it);
-      else hipLaunchKernelGGL((k_seq<BfsOps, 6>), g, b, 0, s, a, (unsigned)it);
-      break;
+    case TK_FUSED: hipLaunchKernelGGL((k_fused<Ops, 0>), g, b, 0, s, a); break;
+    case TK_FUSED_PULL: hipLaunchKernelGGL((k_fused<Ops, 1>), g, b, 0, s, a); break;
+    case TK_FUSED_ALL: hipLaunchKernelGGL((k_fused<Ops, 2>), g, b, 0, s, a); break;
+    case TK_PUSH_STEP: hipLaunchKernelGGL(k_push_step<Ops>, g, b, 0, s, a, it, arg); break;
+    case TK_BALLOT: hipLaunchKernelGGL(k_ballot<Ops>, g, b, 0, s, a, it); break;
+    case TK_PULL_SCAN: hipLaunchKernelGGL(k_pull_scan<Ops>, g, b, 0, s, a, it); break;
+    case TK_PULL_STEP: hipLaunchKernelGGL(k_pull_step<Ops>, g, b, 0, s, a, it); break;
+    case TK_SEQ: hipLaunchKernelGGL((k_seq<Ops, 1>), g, b, 0, s, a, (unsigned)it); break;
+    case TK_SEQ_WIDE: hipLaunchKernelGGL((k_seq<Ops, 6>), g, b, 0, s, a, (unsigned)it); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t trav_init(const TravArgs &a, int sssp, unsigned long long mu0, int run_grid,
-                     hipStream_t s) {
+hipError_t trav_launch(int kind, int algo, const TravArgs &a, int it, int arg, int grid,
+                       hipStream_t s) {
+  switch (algo) {
+    case ALG_BFS: return trav_launch_t<BfsOps>(kind, a, it, arg, grid, s);
+    case ALG_SSSP: return trav_launch_t<SsspOps>(kind, a, it, arg, grid, s);
+    case ALG_WCC: return trav_launch_t<WccOps>(kind, a, it, arg, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t trav_init(const TravArgs &a, int algo, unsigned long long mu0, int run_grid,
+                     hipStream_t s, bool pull_first) {
   int grid = (a.g.n + kBlock - 1) / kBlock;
   if (grid < 2) grid = 2;
   if (grid > 4096) grid = 4096;
-  hipLaunchKernelGGL(k_trav_init, dim3(grid), dim3(kBlock), 0, s, a, sssp, mu0, (unsigned)run_grid);
+  hipLaunchKernelGGL(k_trav_init, dim3(grid), dim3(kBlock), 0, s, a, algo, mu0, (unsigned)run_grid,
+                     pull_first ? 1u : 0u);
   return hipGetLastError();
 }
 
@@ -1127,8 +1250,9 @@ hipError_t weight_sum(const unsigned *w, long long m, unsigned long long *out, h
   return hipGetLastError();
 }
 
-hipError_t seq_start(Ctrl *c, bool pull_first, hipStream_t s) {
-  hipLaunchKernelGGL(k_seq_start, dim3(1), dim3(64), 0, s, c, pull_first ? 1u : 0u);
+hipError_t seq_start(Ctrl *c, bool pull_first, bool all_active, hipStream_t s) {
+  hipLaunchKernelGGL(k_seq_start, dim3(1), dim3(64), 0, s, c, pull_first ? 1u : 0u,
+                     all_active ? 1u : 0u);
   return hipGetLastError();
 }
 

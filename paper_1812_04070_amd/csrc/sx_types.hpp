@@ -10,7 +10,9 @@ namespace sx {
 constexpr int kBlock = 512;              // threads per workgroup (8 wavefronts)
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxGrid = 1024;           // upper bound on workgroups per grid
-constexpr unsigned kSpinLimit = 1u << 22; // watchdog: polls of ~128 cycles each
+// watchdog of the software global barrier: how long one wait may last, in
+// ticks of the constant-rate wall clock (s_memrealtime, 100 MHz on gfx950)
+constexpr unsigned long long kWatchdogTicks = 200000000ull;   // 2 s
 constexpr int kStatLines = 64;           // statistics spread over 64 lines
 
 // SX_ERR_CAPACITY: a list built by a ballot scan did not fit its regions
@@ -51,11 +53,18 @@ struct Ctrl {
   Line stats;                   // u32 [4] ballot scans, [5] pull iterations,
                                 // [6] iterations; u64 [8] k-core scan entries
   Line aux;                     // algorithm scratch
+  Line pol;                     // learned policy: [0] network evaluations,
+                                // [1..8] features and [9..12] outputs of the
+                                // last evaluation (float bits)
   Line seq[2];                  // sequenced mode: run state handed from launch
                                 // L (reads seq[L&1]) to launch L+1
   Line statw[kStatLines];       // u64 [0] arcs inspected, [2] worklist entries
-                                // processed; workgroup b adds into line b % 64
-  Line flags[kMaxGrid];         // barrier arrival words, one line per workgroup
+                                // processed, [4] wall-clock ticks workgroups
+                                // spent waiting at global barriers; workgroup
+                                // b adds into line b % 64
+  Line flags[kMaxGrid];         // per workgroup: [0] barrier arrival word,
+                                // [4,5] wall clock at the end of its last
+                                // launch (sequenced arrangement)
 };
 
 // Device-resident graph (CSR, optional CSC) and engine workspace pointers.
@@ -108,6 +117,9 @@ struct Params {
   int bins_fixed;               // 1: the caller fixed t1 / t2
   unsigned delta;               // SSSP bucket width (0: no buckets)
   int delta_after;              // iterations run before the buckets engage
+  int kfix;                     // k-core: 0 full decomposition, k > 0
+                                // membership in the k-core only
+  unsigned long long watchdog;  // barrier wait budget (wall-clock ticks)
 };
 
 struct TravArgs {

@@ -103,3 +103,22 @@ def test_struct_layouts_match_binding(tmp_path):
         for field, _ in st._fields_:
             assert int(got[f"{name}.{field}"]) == getattr(st, field).offset, f"{name}.{field}"
     assert int(got["SX_DELTA_AUTO"]) == sx.SX_DELTA_AUTO
+
+
+def test_host_inference_matches_oracle():
+    """sx_mlp_forward_host (the network as the one-phase arrangement's host
+    decisions evaluate it) against the FP64 oracle's forward pass."""
+    if not os.path.exists(LIB):
+        pytest.skip("libsimdx.so not built")
+    import numpy as np
+    import paper_1812_04070_amd as sx
+    from oracle import mlp
+    rng = np.random.default_rng(4)
+    for seed, scale in [(0, 1.0), (1, 3.0), (2, 0.2)]:
+        p = (mlp.init_params(seed) * scale).astype(np.float32)
+        p[mlp.NPARAMS - 4:] = rng.normal(size=4)
+        x = rng.normal(size=(300, 8)).astype(np.float32)
+        y = sx.sx_mlp_forward_host(p, x)
+        ref, _ = mlp.forward(p.astype(np.float64), x.astype(np.float64))
+        np.testing.assert_allclose(y, ref, rtol=1e-5, atol=1e-5 * np.abs(ref).max())
+    assert sx.lib().sx_mlp_forward_host(None, None, 1, None) == sx.SX_EINVAL

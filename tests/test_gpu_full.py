@@ -42,10 +42,25 @@ def test_rmat22(engine):
     np.testing.assert_array_equal(c, oracle.kcore_g(g))
     # the forced arms give the same bytes at full size too
     for name, pol in [("push-only", sx.Policy(direction=sx.SX_DIR_PUSH)),
-                      ("unfused", sx.Policy(fused=sx.SX_UNFUSED))]:
+                      ("unfused", sx.Policy(fused=sx.SX_UNFUSED)),
+                      ("fused", sx.Policy(fused=sx.SX_FUSED)),
+                      ("fused-all", sx.Policy(fused=sx.SX_FUSED_ALL))]:
         announce(f"rmat22 bfs {name}")
         d2, _ = run(engine, g, sx.SX_BFS, src, pol, dg=dg)
         np.testing.assert_array_equal(d2, ref_d)
+        if name.startswith("fused"):
+            announce(f"rmat22 sssp {name}")
+            x2, _ = run(engine, g, sx.SX_SSSP, src, pol, dg=dg)
+            np.testing.assert_array_equal(x2, x)
+    for k in (16, 32):
+        announce(f"rmat22 kcore membership k={k}")
+        out, _ = engine.run(dg, sx.SX_KCORE, -1, kcore_k=k)
+        np.testing.assert_array_equal(engine.to_host(dg, sx.SX_KCORE, out), oracle.kcore_member_g(g, k))
+        np.testing.assert_array_equal(engine.to_host(dg, sx.SX_KCORE, out), (c >= k).astype(np.int32))
+    announce("rmat22 wcc")
+    lab, _ = run(engine, g, sx.SX_WCC, -1, dg=dg)
+    ref_w = oracle.wcc_g(g)
+    np.testing.assert_array_equal(lab, ref_w)
     dg.close()
     # the degree-renumbered load that bench.py times
     dr = engine.load(g, reorder=True)
@@ -53,6 +68,7 @@ def test_rmat22(engine):
     np.testing.assert_array_equal(run(engine, g, sx.SX_BFS, src, dg=dr)[0], ref_d)
     np.testing.assert_array_equal(run(engine, g, sx.SX_SSSP, src, dg=dr)[0], x)
     np.testing.assert_array_equal(run(engine, g, sx.SX_KCORE, dg=dr)[0], c)
+    np.testing.assert_array_equal(run(engine, g, sx.SX_WCC, -1, dg=dr)[0], ref_w)
     dr.close()
 
 
@@ -71,6 +87,15 @@ def test_grid4096(engine):
     x, st_auto = run(engine, g, sx.SX_SSSP, 0, dg=dg, sssp_delta=sx.SX_DELTA_AUTO)
     np.testing.assert_array_equal(x, ref)
     assert st_auto["edges_inspected"] < st["edges_inspected"] // 10
+    announce("grid4096 bfs / sssp persistent (fused) arrangement")
+    d2, st_f = run(engine, g, sx.SX_BFS, 0, sx.Policy(fused=sx.SX_FUSED), dg=dg)
+    np.testing.assert_array_equal(d2, d)
+    assert st_f["barrier_wait_ms"] > 0
+    x2, _ = run(engine, g, sx.SX_SSSP, 0, sx.Policy(fused=sx.SX_FUSED), dg=dg)
+    np.testing.assert_array_equal(x2, ref)
+    announce("grid4096 wcc")
+    lab, _ = run(engine, g, sx.SX_WCC, -1, dg=dg)
+    np.testing.assert_array_equal(lab, oracle.wcc_g(g))
     dg.close()
 
 
