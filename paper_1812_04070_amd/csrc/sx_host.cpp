@@ -799,6 +799,7 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   a.state_i = (int *)d_out;
   a.src = src;
   a.mlp = ctx->d_mlp;
+  a.wcc_inv = wcc && G->reordered ? G->d_inv : nullptr;
   if (a.P.learned && !ctx->d_mlp) return fail(SX_ESTATE, "learned policy without loaded MLP");
   if (algo == ALG_SSSP && a.P.delta == SX_DELTA_AUTO) {
     sx_status s = auto_delta(G, st, &a.P.delta);

@@ -990,14 +990,16 @@ __global__ void k_seq_start(Ctrl *C, unsigned pull_first, unsigned all_active) {
 
 // ------------------------------------------------------------ set-up ---
 // Vertex state: BFS depth -1 (source 0); SSSP distance infinity (source 0)
-// and stamp -1 (source 0); WCC label = own id and stamp 0 (all active).
+// and stamp -1 (source 0); WCC label = own id (the caller's id on a
+// renumbered graph) and stamp 0 (all active).
 SX_DEV void init_state(const VGrid &vg, const TravArgs &a, bool sssp, bool wcc = false) {
   const int n = a.g.n;
   const long long tid = (long long)vg.bid * kBlock + threadIdx.x, nt = (long long)vg.nb * kBlock;
   for (long long v = tid; v < n; v += nt) {
     if (wcc) {
-      a.state_i[v] = (int)v;
-      a.w.stamp[v] = 0;
+      const int at = a.wcc_inv ? a.wcc_inv[v] : (int)v;
+      a.state_i[at] = (int)v;
+      a.w.stamp[at] = 0;
     } else if (sssp) {
       ((unsigned *)a.state_i)[v] = v == a.src ? 0u : 0xFFFFFFFFu;
       a.w.stamp[v] = v == a.src ? 0 : -1;
@@ -1097,6 +1099,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   a.w = w;
   a.P = b.P;
   a.mlp = b.mlp;
+  a.wcc_inv = nullptr;
   load_policy(a, pol);
   for (;;) {
     if (vg.bid == 0 && threadIdx.x == 0)

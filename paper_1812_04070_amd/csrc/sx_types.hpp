@@ -129,6 +129,10 @@ struct TravArgs {
   int *state_i;                 // BFS depth (int32) or SSSP dist (uint32) array
   int src;
   const float *mlp;             // policy parameters (device) when P.learned
+  // WCC on a renumbered graph: old id -> new id; vertex inv[v] starts with
+  // label v (its id in the caller's numbering), so that the minimum label of
+  // a component is its smallest original id.  NULL: label = own id.
+  const int *wcc_inv;
 };
 
 // Batched queries (see k_batch).
