@@ -237,6 +237,37 @@ typedef struct {
 sx_status sx_run(sx_program *p, const sx_graph *g, int32_t source, void *d_out,
                  void *hip_stream, sx_run_stats *stats);
 
+/* -------------------------------------------- no-allocation variant --- */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sx_run for
+ * BFS, SSSP or WCC on a graph the caller already holds in device memory,
+ * described by d (SX_DEVICE_PTRS required; SX_UNDIRECTED as for
+ * sx_graph_load; SX_REORDER and SX_VALIDATE not accepted), with the engine's
+ * worklists, ballot words, stamps and control block carved from one static
+ * device array of 256 MiB per device (a file-scope __device__ array, held
+ * from the first sx_ctx_create on the device until the process ends)
+ * instead of a graph workspace.  Same kernels, policies (except SX_UNFUSED,
+ * rejected with SX_EUNSUPPORTED), results and statistics as sx_run on the
+ * same graph loaded with SX_DEVICE_PTRS.  The call allocates nothing: the
+ * context's pinned control-block mirrors and events come from
+ * sx_ctx_create.
+ * Size limit: the workspace takes about 53 n + 32 KiB G + 16 (G + 1)
+ * (m / 2048 + 1) + 300 KiB bytes for a grid of G workgroups (the
+ * program's grid, at most policy grid_wgs when that is set; 512 by default
+ * on MI355X); a graph that needs more than 256 MiB fails with SX_EINVAL and
+ * a message giving the bytes it needs (R-MAT scale 20, 16 M arcs: about
+ * 140 MiB at 512 workgroups).
+ * Concurrency: every call on a device shares that device's array and every
+ * call through one context shares its mirrors: calls that overlap on one
+ * GPU race (serialise them, e.g. on one stream from one thread).  The array
+ * keeps the last call's contents; the call clears what must start at zero
+ * (the control block) with a kernel on the stream.
+ * Errors: as sx_run; SX_EINVAL also for a missing SX_DEVICE_PTRS or an
+ * oversize graph; SX_EUNSUPPORTED for other algorithms, SX_UNFUSED,
+ * SX_REORDER and directed WCC. */
+sx_status sx_run_static(sx_program *p, const sx_graph_desc *d, int32_t source, void *d_out,
+                        void *hip_stream, sx_run_stats *stats);
+
 /* ------------------------------------------------ frontier inspection --- */
 /* Run BFS, SSSP or WCC for at most `iterations` iterations in the one-phase
  * arrangement (SX_UNFUSED, whatever the program's policy says about fusion;

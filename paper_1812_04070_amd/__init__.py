@@ -45,7 +45,7 @@ EXPORTED = [
     "sx_run", "sx_read_vertices", "sx_kernel_info_get", "sx_eq1_ctas",
     "sx_policy_load_mlp", "sx_mlp_forward", "sx_mlp_forward_host", "sx_mlp_loss_grad", "sx_mlp_adam",
     "sx_policy_collect", "sx_run_batch", "sx_batch_autotune",
-    "sx_run_iterations", "sx_frontier_get",
+    "sx_run_iterations", "sx_frontier_get", "sx_run_static",
 ]
 SX_POLICY_ARMS = 6
 ARM_THRESHOLDS = [None, (16, 256), (64, 256), (64, 1024), (256, 2048), None]
@@ -129,6 +129,7 @@ def lib() -> ctypes.CDLL:
         "sx_program_destroy": ([vp], None),
         "sx_program_set_policy": ([vp, P(sx_policy)], ctypes.c_int),
         "sx_run": ([vp, vp, ctypes.c_int32, vp, vp, P(sx_run_stats)], ctypes.c_int),
+        "sx_run_static": ([vp, P(sx_graph_desc), ctypes.c_int32, vp, vp, P(sx_run_stats)], ctypes.c_int),
         "sx_read_vertices": ([vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "sx_kernel_info_get": ([vp, ctypes.c_char_p, P(sx_kernel_info)], ctypes.c_int),
         "sx_eq1_ctas": ([ctypes.c_int32] * 4, ctypes.c_int32),
@@ -232,6 +233,13 @@ def sx_run(p, g, source: int, d_out_ptr: int, stream: int = 0) -> sx_run_stats:
     st = sx_run_stats()
     check(lib().sx_run(p, g, source, ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream),
                        ctypes.byref(st)), "sx_run")
+    return st
+
+
+def sx_run_static(p, desc: sx_graph_desc, source: int, d_out_ptr: int, stream: int = 0) -> sx_run_stats:
+    st = sx_run_stats()
+    check(lib().sx_run_static(p, ctypes.byref(desc), source, d_out_ptr, stream, ctypes.byref(st)),
+          "sx_run_static")
     return st
 
 
@@ -403,6 +411,12 @@ class DeviceGraph:
             _validate_host(g)
         torch.cuda.synchronize(dev)
         self.handle = sx_graph_load(engine.ctx, desc, engine.stream())
+        # the same borrowed arrays, as sx_run_static takes them
+        self.desc = sx_graph_desc(self.n, self.m, ptr("offsets"), ptr("indices"), ptr("weights"),
+                                  ptr("in_offsets") if self.directed else None,
+                                  ptr("in_indices") if self.directed else None,
+                                  ptr("in_weights") if self.directed else None,
+                                  flags & ~SX_REORDER)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -464,6 +478,19 @@ class Engine:
             dt = {SX_PAGERANK: torch.float32}.get(algo, torch.int32)
             out = torch.empty(max(dg.n, 1), dtype=dt, device=self.device)
         st = sx_run(p, dg.handle, source, out.data_ptr(), self.stream())
+        return out[:dg.n], st.as_dict()
+
+    def run_static(self, dg: DeviceGraph, algo: int, source: int = -1, policy: Optional[Policy] = None,
+                   out=None, sssp_delta: int = 0):
+        """sx_run_static on dg's device arrays: the run's workspace is the
+        library's static array (nothing allocated by the call); returns
+        (torch device tensor, stats dict) like run()."""
+        import torch
+        p = self.program(algo, sssp_delta=sssp_delta)
+        sx_program_set_policy(p, (policy or Policy()).c())
+        if out is None:
+            out = torch.empty(max(dg.n, 1), dtype=torch.int32, device=self.device)
+        st = sx_run_static(p, dg.desc, source, out.data_ptr(), self.stream())
         return out[:dg.n], st.as_dict()
 
     def to_host(self, dg: DeviceGraph, algo: int, out) -> np.ndarray:

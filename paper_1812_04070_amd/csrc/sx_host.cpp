@@ -44,6 +44,22 @@ static sx_status fail(sx_status s, const char *fmt, ...) {
                   __LINE__);                                                                \
   } while (0)
 
+// Workspace of sx_run_static, for callers that cannot allocate device
+// memory: one array per device, held until the process ends.  Host code
+// never passes the array's name to a kernel (it is a host-side stand-in):
+// the device address comes from hipGetSymbolAddress, per device, in
+// sx_ctx_create.
+static constexpr size_t kStaticScratchBytes = 256ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// Zero `words` 32-bit words (the control block of a static-workspace run;
+// a kernel rather than hipMemsetAsync, so that the call can be captured).
+__global__ void k_static_clear(unsigned *p, unsigned long long words) {
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (unsigned long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 struct sx_ctx {
   int device;
   int cus;
@@ -65,6 +81,12 @@ struct sx_ctx {
   void *bq = nullptr, *bo = nullptr, *bw = nullptr, *bh = nullptr, *bs = nullptr;
   int batch_cap_q = 0, batch_cap_t = 0;
   hipEvent_t be0 = nullptr, be1 = nullptr;
+  // sx_run_static: this device's static workspace (from
+  // hipGetSymbolAddress), pinned control-block mirrors and events, all set
+  // up here so that the call itself allocates nothing
+  unsigned char *d_static = nullptr;
+  Ctrl *hs_ctrl[2] = {nullptr, nullptr};
+  hipEvent_t sev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 struct sx_graph {
@@ -131,11 +153,26 @@ sx_status sx_ctx_create(int hip_device, sx_ctx **out) {
   HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
   int khz = 0;
   HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device));
+  // the static workspace's address on this device (each device holds its
+  // own copy of the array), with the device current
+  void *sp = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
+  if (!sp) return fail(SX_EHIP, "hipGetSymbolAddress returned no address for the static workspace");
   sx_ctx *c = new sx_ctx();
   c->device = hip_device;
   c->cus = prop.multiProcessorCount;
   c->cooperative = prop.cooperativeLaunch;
   if (khz > 0) c->wall_khz = (double)khz;
+  c->d_static = (unsigned char *)sp;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 2 && e == hipSuccess; ++i)
+    e = hipHostMalloc((void **)&c->hs_ctrl[i], sizeof(Ctrl), hipHostMallocDefault);
+  for (int i = 0; i < 4 && e == hipSuccess; ++i)
+    e = i < 2 ? hipEventCreate(&c->sev[i]) : hipEventCreateWithFlags(&c->sev[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    sx_ctx_destroy(c);
+    return fail(SX_EHIP, "context set-up: %s", hipGetErrorString(e));
+  }
   *out = c;
   return SX_OK;
 }
@@ -149,6 +186,10 @@ void sx_ctx_destroy(sx_ctx *c) {
     if (p) (void)hipFree(p);
   if (c->be0) (void)hipEventDestroy(c->be0);
   if (c->be1) (void)hipEventDestroy(c->be1);
+  for (Ctrl *h : c->hs_ctrl)
+    if (h) (void)hipHostFree(h);
+  for (hipEvent_t e : c->sev)
+    if (e) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -762,24 +803,25 @@ static sx_status auto_delta(sx_graph *G, hipStream_t st, unsigned *delta) {
   return SX_OK;
 }
 
-// max_it > 0: stop the one-phase arrangement after that many iterations and
-// note where the next iteration's lists are (sx_run_iterations).
-static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out, hipStream_t st,
-                               sx_run_stats *stats, int max_it = 0) {
-  const int algo = p->ap.algo == SX_SSSP ? ALG_SSSP : (p->ap.algo == SX_WCC ? ALG_WCC : ALG_BFS);
-  const bool wcc = algo == ALG_WCC;
-  // aggregation (minimum) programs decide with the SSSP rule
-  const bool aggr = algo != ALG_BFS;
+static int trav_algo(const sx_program *p) {
+  return p->ap.algo == SX_SSSP ? ALG_SSSP : (p->ap.algo == SX_WCC ? ALG_WCC : ALG_BFS);
+}
+
+// large dense graphs take the wide sequenced kernel (three workgroups per CU)
+static int trav_seq_kind(const sx_graph *G) {
+  return G->g.m >= kBigGraphArcs && G->g.m >= 8ll * G->g.n ? TK_SEQ_WIDE : TK_SEQ;
+}
+
+// Workgroups of a traversal run's phase kernels under the program's policy.
+static int traversal_grid(sx_program *p, const sx_graph *G, int max_it) {
+  const int algo = trav_algo(p);
   sx_ctx *ctx = p->ctx;
   const bool fused = max_it == 0 && (p->pol.fused == SX_FUSED || p->pol.fused == SX_FUSED_ALL);
   const int fk = p->pol.fused == SX_FUSED_ALL ? TK_FUSED_ALL : TK_FUSED;
   const bool sequenced = max_it == 0 && (p->pol.fused == SX_SEQUENCED || p->pol.fused == SX_FUSE_AUTO);
   int grid;
-  // large dense graphs take the wide sequenced kernel (three workgroups per CU)
-  const int seq_kind =
-      G->g.m >= kBigGraphArcs && G->g.m >= 8ll * G->g.n ? TK_SEQ_WIDE : TK_SEQ;
   if (sequenced) {
-    grid = plain_grid(ctx, trav_kernel(seq_kind, algo));
+    grid = plain_grid(ctx, trav_kernel(trav_seq_kind(G), algo));
     if (p->pol.grid_wgs > 0) grid = std::min(grid, p->pol.grid_wgs);
   } else if (fused) {
     // the push and pull kernels of selective fusion share the run's lists,
@@ -791,6 +833,23 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
     grid = plain_grid(ctx, trav_kernel(TK_PUSH_STEP, algo));
     if (p->pol.grid_wgs > 0) grid = std::min(grid, p->pol.grid_wgs);
   }
+  return grid;
+}
+
+// max_it > 0: stop the one-phase arrangement after that many iterations and
+// note where the next iteration's lists are (sx_run_iterations).
+static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out, hipStream_t st,
+                               sx_run_stats *stats, int max_it = 0) {
+  const int algo = trav_algo(p);
+  const bool wcc = algo == ALG_WCC;
+  // aggregation (minimum) programs decide with the SSSP rule
+  const bool aggr = algo != ALG_BFS;
+  sx_ctx *ctx = p->ctx;
+  const bool fused = max_it == 0 && (p->pol.fused == SX_FUSED || p->pol.fused == SX_FUSED_ALL);
+  const int fk = p->pol.fused == SX_FUSED_ALL ? TK_FUSED_ALL : TK_FUSED;
+  const bool sequenced = max_it == 0 && (p->pol.fused == SX_SEQUENCED || p->pol.fused == SX_FUSE_AUTO);
+  const int seq_kind = trav_seq_kind(G);
+  const int grid = traversal_grid(p, G, max_it);
   TravArgs a;
   memset(&a, 0, sizeof a);
   a.g = G->g;
@@ -1424,6 +1483,94 @@ extern "C" sx_status sx_run(sx_program *p, const sx_graph *gc, int32_t source, v
   HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
   if (stats) stats->device_ms += ms;
   return SX_OK;
+}
+
+// BFS / SSSP / WCC on a graph the caller holds in device memory, with the
+// engine's workspace carved from the static array instead of allocated: the
+// same kernels and host loop as sx_run on a graph loaded with
+// SX_DEVICE_PTRS.  Nothing here allocates; the context's pinned mirrors and
+// events were made by sx_ctx_create.
+extern "C" sx_status sx_run_static(sx_program *p, const sx_graph_desc *d, int32_t source,
+                                   void *d_out, void *hip_stream, sx_run_stats *stats) {
+  if (!p || !d || !d_out) return fail(SX_EINVAL, "NULL argument");
+  sx_ctx *ctx = p->ctx;
+  if (!ctx->d_static) return fail(SX_ESTATE, "static workspace not set up");
+  const int algo = p->ap.algo;
+  if (algo != SX_BFS && algo != SX_SSSP && algo != SX_WCC)
+    return fail(SX_EUNSUPPORTED, "sx_run_static runs BFS, SSSP or WCC only");
+  if (p->pol.fused == SX_UNFUSED)
+    return fail(SX_EUNSUPPORTED, "sx_run_static: the one-phase arrangement keeps host buffers");
+  if (!(d->flags & SX_DEVICE_PTRS)) return fail(SX_EINVAL, "sx_run_static needs SX_DEVICE_PTRS");
+  if (d->flags & SX_REORDER) return fail(SX_EUNSUPPORTED, "sx_run_static: no renumbering (SX_REORDER)");
+  const bool undirected = (d->flags & SX_UNDIRECTED) != 0;
+  if (d->n < 0) return fail(SX_EINVAL, "n < 0");
+  if (d->m < 0 || d->m >= (int64_t)INT32_MAX) return fail(SX_EINVAL, "m = %lld out of range", (long long)d->m);
+  if (!d->offsets || (d->m > 0 && !d->indices)) return fail(SX_EINVAL, "missing CSR arrays");
+  if (undirected && (d->in_offsets || d->in_indices))
+    return fail(SX_EINVAL, "undirected graph with in-neighbour arrays");
+  if (!undirected && (!d->in_offsets || (d->m > 0 && !d->in_indices)))
+    return fail(SX_EINVAL, "directed graph needs in_offsets / in_indices (CSC)");
+  if (!undirected && d->weights && !d->in_weights)
+    return fail(SX_EINVAL, "directed weighted graph needs in_weights");
+  if (algo == SX_WCC && !undirected) return fail(SX_EUNSUPPORTED, "WCC on a directed graph");
+  if (algo == SX_WCC && d->n == 0) {
+    if (stats) memset(stats, 0, sizeof *stats);
+    return SX_OK;
+  }
+  if (algo != SX_WCC) {
+    if (d->n == 0) return fail(SX_EINVAL, "empty graph has no source");
+    if (source < 0 || source >= d->n) return fail(SX_EINVAL, "source %d out of range [0, %d)", source, d->n);
+    if (algo == SX_SSSP && !d->weights && d->m > 0) return fail(SX_EINVAL, "SSSP needs edge weights");
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  // a graph object on the stack that borrows everything
+  sx_graph G;
+  G.ctx = ctx;
+  DevGraph &g = G.g;
+  g.n = d->n;
+  g.m = d->m;
+  g.directed = !undirected;
+  g.off = d->offsets;
+  g.idx = d->indices;
+  g.w = d->weights;
+  g.in_off = undirected ? d->offsets : d->in_offsets;
+  g.in_idx = undirected ? d->indices : d->in_indices;
+  g.in_w = undirected ? d->weights : d->in_weights;
+  G.weighted = d->weights != nullptr || d->m == 0;
+  G.directed = !undirected;
+  G.h_ctrl = ctx->hs_ctrl[0];
+  G.h_ctrl2 = ctx->hs_ctrl[1];
+  G.ev0 = ctx->sev[0];
+  G.ev1 = ctx->sev[1];
+  G.evb[0] = ctx->sev[2];
+  G.evb[1] = ctx->sev[3];
+  // workspace laid out for the run's grid (not for the largest grid, as a
+  // loaded graph's is), bump-allocated in 256-byte steps
+  const int grid = traversal_grid(p, &G, 0);
+  size_t used = 0;
+  auto carve = [&](void **ptr, size_t bytes) -> sx_status {
+    const size_t b = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    if (used + b > kStaticScratchBytes) {
+      *ptr = nullptr;
+      used += b;
+      return SX_OK;  // keep counting: the total is reported below
+    }
+    *ptr = ctx->d_static + used;
+    used += b;
+    return SX_OK;
+  };
+  sx_status s = work_alloc(carve, d->n, d->m, !undirected, grid, false, G.w);
+  if (s != SX_OK) return s;
+  if (used > kStaticScratchBytes)
+    return fail(SX_EINVAL,
+                "sx_run_static: the graph needs %zu bytes of workspace at a grid of %d workgroups; the "
+                "static workspace holds %zu",
+                used, grid, kStaticScratchBytes);
+  const unsigned long long words = sizeof(Ctrl) / 4;
+  hipLaunchKernelGGL(k_static_clear, dim3(64), dim3(256), 0, st, (unsigned *)G.w.ctrl, words);
+  HIP_TRY(hipGetLastError());
+  return run_traversal(p, &G, source, d_out, st, stats);
 }
 
 extern "C" sx_status sx_run_iterations(sx_program *p, const sx_graph *gc, int32_t source,
