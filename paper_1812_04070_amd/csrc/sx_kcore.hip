@@ -471,9 +471,12 @@ struct KState {
 SX_DEV int after_scan(const VGrid &vg, const KArgs &a, KState &q, const Totals &T,
                       const Totals &TA, LdsK &lds) {
   q.alive_arcs = TA.mf;
+  // no survivors: the frontier's core numbers are set (by the scan), and
+  // nobody is left to receive its decrements
+  if (TA.nf == 0) return -1;
   if (T.nf > 0) return 1;
   // fixed k: a scan that finds nothing to delete ends the run
-  if (TA.nf == 0 || a.P.kfix) return -1;
+  if (a.P.kfix) return -1;
   // empty level: jump to the smallest surviving degree
   const unsigned mind = alive_min_degree(vg, a.w, q.s & 1, lds);
   q.k = (int)mind > q.k + 1 ? (int)mind : q.k + 1;

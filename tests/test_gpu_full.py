@@ -121,3 +121,38 @@ def test_rmat24_directed(engine):
     assert rel_l1(r2, ref) <= 1e-6
     np.testing.assert_array_equal(run(engine, g, sx.SX_KCORE, dg=dr)[0], ref_c)
     dr.close()
+
+
+def _trained_params():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(sx.__file__), "policy_mlp.json")
+    with open(path) as f:
+        return np.asarray(json.load(f)["params"], dtype=np.float32)
+
+
+@pytest.mark.timeout(600)
+def test_batch_workload_full(engine):
+    """The batched workload at its full size (48 R-MAT graphs of scales 12-20,
+    16 grids of sides 256-2048, 256 BFS/SSSP queries) in one launch, with the
+    heuristic and with the trained policy: every query's output equals the
+    oracle's."""
+    import torch
+    graphs, queries = gen.batch_workload()
+    dgs = [engine.load(g) for g in graphs]
+    algo = {"bfs": sx.SX_BFS, "sssp": sx.SX_SSSP}
+    refs = [oracle.bfs_g(graphs[gi], s) if a == "bfs" else oracle.sssp_g(graphs[gi], s)
+            for gi, a, s in queries]
+    outs = [torch.empty(graphs[gi].n, dtype=torch.int32, device=engine.device) for gi, _, _ in queries]
+    qs = [(dgs[gi].handle, algo[a], s, o.data_ptr()) for (gi, a, s), o in zip(queries, outs)]
+    sx.sx_policy_load_mlp(engine.ctx, _trained_params())
+    for pname, pol in [("heuristic", sx.Policy()), ("learned", sx.Policy(policy=sx.SX_POLICY_LEARNED))]:
+        for o in outs:
+            o.fill_(-7)
+        announce(f"batch workload full {pname}")
+        ms, _ = sx.sx_run_batch(engine.ctx, qs, pol.c(), sx.sx_batch_config(32, 0, 0), engine.stream())
+        assert ms > 0
+        for (gi, a, s), o, r in zip(queries, outs, refs):
+            np.testing.assert_array_equal(engine.to_host(dgs[gi], algo[a], o), r)
+    for d in dgs:
+        d.close()
