@@ -7,7 +7,7 @@ never does; it shares no code with it.
 Serial, plain implementations (``oracle.c``) of what the paper's method
 computes: queue BFS, Dijkstra / worklist Bellman-Ford / synchronous rounds for
 SSSP, Batagelj-Zaversnik and naive peeling for the k-core decomposition, fp64
-PageRank; plus (``mlp.py``) the fp64 forward and backward pass of the policy
+PageRank, fp64 belief propagation on a binary pairwise MRF; plus (``mlp.py``) the fp64 forward and backward pass of the policy
 network.  Each function cites the paper passage it follows.
 """
 from __future__ import annotations
@@ -28,7 +28,7 @@ def build(verbose: bool = False) -> str:
     """Compile the oracle (serial C, -O2, one thread)."""
     src = os.path.join(_HERE, "oracle.c")
     tmp = LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", src, "-o", tmp]
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", src, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
@@ -51,7 +51,8 @@ def lib():
                            ("sxo_kcore_peel", [ctypes.c_int32, vp, vp, vp, vp, vp]),
                            ("sxo_kcore_member", [ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32, vp]),
                            ("sxo_wcc", [ctypes.c_int32, vp, vp, vp]),
-                           ("sxo_pagerank", [ctypes.c_int32, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp])]:
+                           ("sxo_pagerank", [ctypes.c_int32, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp]),
+                           ("sxo_bp", [ctypes.c_int32, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp])]:
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int
@@ -186,3 +187,23 @@ def pagerank_g(g, d=0.85, iters=20):
     if g.directed:
         return pagerank(g.n, g.offsets, g.in_offsets, g.in_indices, d, iters)
     return pagerank(g.n, g.offsets, g.offsets, g.indices, d, iters)
+
+
+def bp(n, offsets, indices, weights, prior, kappa=0.5, iters=10):
+    """Belief propagation (Section 6, sum-product on a binary pairwise MRF;
+    Section 3.2, all vertices active, updates summed): b(v, 1) after `iters`
+    synchronous iterations from the priors, fp64 (see sxo_bp in oracle.c for
+    the potentials)."""
+    off = _c(offsets, np.int32)
+    idx = _c(indices, np.int32)
+    w = _c(weights, np.uint32)
+    pr = _c(prior, np.float64)
+    out = np.empty(max(n, 1), dtype=np.float64)
+    _check(lib().sxo_bp(n, _p(off), _p(idx), _p(w), _p(pr), float(kappa), int(iters), _p(out)), "sxo_bp")
+    return out[:n]
+
+
+def bp_g(g, prior, kappa=0.5, iters=10):
+    if g.directed:
+        raise ValueError("belief propagation runs on undirected graphs")
+    return bp(g.n, g.offsets, g.indices, g.weights, prior, kappa, iters)

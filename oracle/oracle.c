@@ -30,10 +30,18 @@
  *            synchronous iterations in fp64, x0 = 1/n,
  *            x'(v) = (1-d)/n + d * (sum_{u->v} x(u)/outdeg(u) + D/n),
  *            D = sum of x over vertices without out-arcs.
+ *   BP       Section 6 ("Belief propagation": sum-product message passing on
+ *            a Markov random field, the vertex's probability as its state)
+ *            and Section 3.2 (every vertex active, updates summed): a binary
+ *            pairwise MRF, synchronous iterations in fp64 of
+ *              b'(v, x) ~ phi_v(x) * prod_{u in N(v)} m_{u->v}(x),
+ *              m_{u->v}(x) = sum_y psi_uv(y, x) * b(u, y),
+ *            starting from b = phi; products taken as sums of logarithms.
  *
  * Graph layout: CSR int32 offsets[n+1] / indices[m] (out-arcs); directed
  * graphs also pass the CSC (in-arcs).  Undirected graphs store both arcs.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -378,5 +386,55 @@ int sxo_pagerank(int32_t n, const int32_t *off, const int32_t *in_off, const int
     }
     memcpy(x_out, x, sizeof(double) * (size_t)n);
     free(x); free(y);
+    return 0;
+}
+
+/* ---------------------------------------------------- belief propagation --- */
+/* Binary pairwise MRF over an undirected graph (both arcs stored).  Vertex v
+ * has the prior phi_v(1) = prior[v], phi_v(0) = 1 - prior[v].  The edge
+ * {u, v} carries the potential psi_uv(x, y) = s_uv when x == y and 1 - s_uv
+ * otherwise, with
+ *   s_uv     = (1 + kappa * theta_uv / max(deg u, deg v)) / 2,
+ *   theta_uv = (((w_uv - 1) mod 64) - 31.5) / 31.5   (1 when w is NULL),
+ * the coupling sign and strength taken from the arc weight (weights in
+ * [1, 64] span [-1, 1]).  One iteration: every vertex's belief is its prior
+ * times the product over its neighbours u of the message
+ *   m_{u->v}(x) = sum_y psi_uv(y, x) b(u, y),
+ * normalised to sum to 1 (Section 6: sum-product message passing with the
+ * vertex probability as the metadata; Section 3.2: all vertices active, the
+ * per-neighbour terms summed -- here the logarithms of the messages).
+ * belief[v] = b(v, 1) after `iters` iterations (b = phi before the first). */
+int sxo_bp(int32_t n, const int32_t *off, const int32_t *idx, const uint32_t *w, const double *prior,
+           double kappa, int32_t iters, double *belief) {
+    if (n < 0 || iters < 0) return -1;
+    if (n == 0) return 0;
+    double *b = (double *)malloc(sizeof(double) * (size_t)n);
+    double *nb = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!b || !nb) { free(b); free(nb); return -2; }
+    for (int32_t v = 0; v < n; ++v) {
+        if (!(prior[v] > 0.0 && prior[v] < 1.0)) { free(b); free(nb); return -3; }
+        b[v] = prior[v];
+    }
+    for (int32_t t = 0; t < iters; ++t) {
+        for (int32_t v = 0; v < n; ++v) {
+            double l1 = log(prior[v]), l0 = log(1.0 - prior[v]);
+            const int64_t dv = off[v + 1] - off[v];
+            for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+                const int32_t u = idx[e];
+                const int64_t du = off[u + 1] - off[u];
+                const double theta = w ? ((double)((w[e] - 1u) % 64u) - 31.5) / 31.5 : 1.0;
+                const double s = 0.5 * (1.0 + kappa * theta / (double)(du > dv ? du : dv));
+                const double m1 = s * b[u] + (1.0 - s) * (1.0 - b[u]);
+                const double m0 = (1.0 - s) * b[u] + s * (1.0 - b[u]);
+                l1 += log(m1);
+                l0 += log(m0);
+            }
+            /* normalise: b(v, 1) = e^l1 / (e^l0 + e^l1) */
+            nb[v] = 1.0 / (1.0 + exp(l0 - l1));
+        }
+        double *t2 = b; b = nb; nb = t2;
+    }
+    memcpy(belief, b, sizeof(double) * (size_t)n);
+    free(b); free(nb);
     return 0;
 }

@@ -205,6 +205,14 @@ def from_edges(n: int, edges: Sequence[Tuple[int, int]], weights: Optional[Seque
     return g
 
 
+def bp_priors(n: int, seed: int, lo: float = 0.1, hi: float = 0.9) -> np.ndarray:
+    """Prior marginals P(x_v = 1) of a binary MRF over n vertices: float32,
+    uniform in [lo, hi] from a seeded numpy Generator (the belief-propagation
+    workloads' unary potentials)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=n).astype(np.float32)
+
+
 def max_degree_vertex(g: Graph) -> int:
     """Source vertex used by the workloads: highest out-degree, ties to the lowest id."""
     if g.n == 0:

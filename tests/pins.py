@@ -204,3 +204,52 @@ def closure_min_label(n, offsets, indices):
     for k in range(n):
         R = R | (R[:, k:k + 1] & R[k:k + 1, :])
     return np.array([int(np.nonzero(R[v])[0][0]) for v in range(n)], dtype=np.int64)
+
+
+# ------------------------------------------------- belief propagation ----
+
+def bp_potential(w_e, du, dv, kappa):
+    """Agreement probability s of the pairwise potential of edge {u, v}
+    (psi(x, y) = s if x == y else 1 - s): the binary MRF the belief
+    propagation workloads define, coupling sign and strength from the arc
+    weight (weights 1..64 span -1..1), scaled by the larger endpoint degree."""
+    theta = 1.0 if w_e is None else ((int(w_e) - 1) % 64 - 31.5) / 31.5
+    return 0.5 * (1.0 + kappa * theta / max(du, dv))
+
+
+def bp_star_marginals(n, offsets, indices, weights, prior, kappa):
+    """For every vertex v, the exact marginal P(x_v = 1) of the MRF restricted
+    to v's star (v, its neighbours, the edges {v, u}), with every vertex's
+    prior as its unary potential, by enumerating all 2^(deg + 1) joint
+    states.  One synchronous sum-product iteration from the priors must give
+    exactly these values: a neighbour's message is then built from its prior
+    alone, as in the star."""
+    deg = np.diff(np.asarray(offsets, dtype=np.int64))
+    out = np.empty(n)
+    for v in range(n):
+        nb = [(int(indices[e]), None if weights is None else int(weights[e]))
+              for e in range(offsets[v], offsets[v + 1])]
+        z = np.zeros(2)
+        for xs in itertools.product((0, 1), repeat=len(nb) + 1):
+            xv = xs[0]
+            p = prior[v] if xv == 1 else 1.0 - prior[v]
+            for (u, we), xu in zip(nb, xs[1:]):
+                p *= prior[u] if xu == 1 else 1.0 - prior[u]
+                s = bp_potential(we, deg[u], deg[v], kappa)
+                p *= s if xu == xv else 1.0 - s
+            z[xv] += p
+        out[v] = z[1] / z.sum()
+    return out
+
+
+def bp_uniform_cycle(n_iter, p0, c):
+    """Belief of every vertex of a cycle whose vertices share the prior p0 and
+    whose edges share the potential (1 + c) / 2 (by symmetry all beliefs stay
+    equal): in the q = 2b - 1 coordinates one sum-product iteration is
+    q' = tanh(atanh(q0) + 2 atanh(c q)) (the message ratio of an edge is
+    (1 + c q) / (1 - c q) = exp(2 atanh(c q))), q0 = 2 p0 - 1."""
+    q0 = 2.0 * p0 - 1.0
+    q = q0
+    for _ in range(n_iter):
+        q = np.tanh(np.arctanh(q0) + 2.0 * np.arctanh(c * q))
+    return 0.5 * (1.0 + q)

@@ -321,6 +321,78 @@ def test_wcc_scipy_cross_check():
         assert np.unique(mine).size == nc
 
 
+# ------------------------------------------------- belief propagation ----
+
+def _bp_graphs():
+    return [gen.random_graph(9, 0.4, seed=1, weights=(1, 64)),
+            gen.random_graph(12, 0.25, seed=2, weights=(1, 64)),
+            gen.random_graph(10, 0.5, seed=3),                       # unweighted: theta = 1
+            gen.from_edges(6, [(0, i) for i in range(1, 6)], [1, 17, 32, 33, 64]),
+            gen.from_edges(5, [(0, 1), (2, 3)], [5, 60])]             # vertex 4 isolated
+
+
+def test_bp_no_coupling_keeps_priors():
+    """kappa = 0 makes every potential uniform (s = 1/2): every message is
+    constant, so the beliefs stay the priors; zero iterations return them."""
+    for i, g in enumerate(_bp_graphs()):
+        pr = gen.bp_priors(g.n, seed=i).astype(np.float64)
+        for it in (0, 1, 5):
+            np.testing.assert_allclose(oracle.bp_g(g, pr, kappa=0.0, iters=it), pr, rtol=0, atol=1e-15)
+        np.testing.assert_array_equal(oracle.bp_g(g, pr, kappa=0.5, iters=0), pr)
+
+
+def test_bp_first_iteration_is_exact_on_stars():
+    """One iteration from the priors equals, at every vertex, the exact
+    marginal of the MRF restricted to its star, by enumeration of all joint
+    states (Section 6: sum-product message passing)."""
+    for i, g in enumerate(_bp_graphs()):
+        pr = gen.bp_priors(g.n, seed=10 + i).astype(np.float64)
+        for kappa in (0.3, 0.9):
+            got = oracle.bp_g(g, pr, kappa=kappa, iters=1)
+            ref = pins.bp_star_marginals(g.n, g.offsets, g.indices, g.weights, pr, kappa)
+            np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14)
+
+
+def test_bp_uniform_cycle_closed_form():
+    """A cycle with one prior and one edge weight keeps all beliefs equal and
+    follows the scalar tanh recurrence (an identity of the message ratio, not
+    the oracle's product of messages)."""
+    n = 7
+    for w, kappa, p0 in ((64, 0.9, 0.8), (1, 0.5, 0.3), (40, 0.7, 0.55)):
+        g = gen.from_edges(n, [(i, (i + 1) % n) for i in range(n)], [w] * n)
+        pr = np.full(n, p0)
+        theta = ((w - 1) % 64 - 31.5) / 31.5
+        c = kappa * theta / 2.0
+        for it in (1, 2, 6, 20):
+            got = oracle.bp_g(g, pr, kappa=kappa, iters=it)
+            np.testing.assert_allclose(got, np.full(n, pins.bp_uniform_cycle(it, p0, c)), rtol=1e-12)
+
+
+def test_bp_relabelling_and_components():
+    """Renumbering the vertices renumbers the beliefs; a disjoint union gives
+    each part the beliefs it has alone (no mixing of indices or operands)."""
+    g = gen.random_graph(11, 0.35, seed=5, weights=(1, 64))
+    pr = gen.bp_priors(g.n, seed=5).astype(np.float64)
+    ref = oracle.bp_g(g, pr, kappa=0.8, iters=7)
+    perm = np.random.default_rng(3).permutation(g.n)        # old -> new
+    src = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    keep = src < g.indices
+    gp = gen.from_edges(g.n, np.stack([perm[src[keep]], perm[g.indices[keep]]], 1), g.weights[keep])
+    prp = np.empty(g.n)
+    prp[perm] = pr
+    np.testing.assert_allclose(oracle.bp_g(gp, prp, kappa=0.8, iters=7)[perm], ref, rtol=1e-13)
+    h = gen.random_graph(6, 0.5, seed=8, weights=(1, 64))
+    ph = gen.bp_priors(h.n, seed=8).astype(np.float64)
+    srch = np.repeat(np.arange(h.n), np.diff(h.offsets))
+    kh = srch < h.indices
+    u = gen.from_edges(g.n + h.n, np.concatenate([np.stack([src[keep], g.indices[keep]], 1),
+                                                  np.stack([srch[kh] + g.n, h.indices[kh] + g.n], 1)]),
+                       np.concatenate([g.weights[keep], h.weights[kh]]))
+    bu = oracle.bp_g(u, np.concatenate([pr, ph]), kappa=0.8, iters=7)
+    np.testing.assert_allclose(bu[:g.n], ref, rtol=1e-13)
+    np.testing.assert_allclose(bu[g.n:], oracle.bp_g(h, ph, kappa=0.8, iters=7), rtol=1e-13)
+
+
 # ------------------------------------------------- planted mistakes fail ----
 
 def test_pins_catch_planted_mistakes():
@@ -373,3 +445,27 @@ def test_pins_catch_planted_mistakes():
     d[np.argmax(d)] += 1
     with pytest.raises(AssertionError):
         pins.bfs_certificate(gu.n, gu.offsets, gu.indices, 0, d)
+    # belief propagation: dropping the prior, flipping the coupling's sign or
+    # scaling by the receiving vertex's degree only each fail the star check
+    gb = gen.from_edges(6, [(0, 1), (0, 2), (0, 3), (3, 4), (4, 5), (1, 2)], [3, 50, 64, 20, 9, 41])
+    pb = gen.bp_priors(gb.n, seed=21).astype(np.float64)
+    star = pins.bp_star_marginals(gb.n, gb.offsets, gb.indices, gb.weights, pb, 0.9)
+    deg = np.diff(gb.offsets)
+
+    def one_iteration(no_prior=False, flip=False, own_degree=False):
+        out = np.empty(gb.n)
+        for v in range(gb.n):
+            l1 = 0.0 if no_prior else np.log(pb[v])
+            l0 = 0.0 if no_prior else np.log(1 - pb[v])
+            for e in range(gb.offsets[v], gb.offsets[v + 1]):
+                u = gb.indices[e]
+                th = ((int(gb.weights[e]) - 1) % 64 - 31.5) / 31.5 * (-1 if flip else 1)
+                s = 0.5 * (1 + 0.9 * th / (deg[v] if own_degree else max(deg[u], deg[v])))
+                l1 += np.log(s * pb[u] + (1 - s) * (1 - pb[u]))
+                l0 += np.log((1 - s) * pb[u] + s * (1 - pb[u]))
+            out[v] = 1 / (1 + np.exp(l0 - l1))
+        return out
+
+    np.testing.assert_allclose(one_iteration(), star, rtol=1e-12)
+    for mutant in (dict(no_prior=True), dict(flip=True), dict(own_degree=True)):
+        assert not np.allclose(one_iteration(**mutant), star, rtol=1e-9), mutant
