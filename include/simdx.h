@@ -100,7 +100,7 @@ void sx_graph_destroy(sx_graph *g);
 sx_status sx_graph_info(const sx_graph *g, int32_t *n, int64_t *m, int32_t *directed, int32_t *weighted);
 
 /* ----------------------------------------------------------- programs --- */
-/* The five ACC programs (Section 3.2 for the Active/Compute/Combine triple,
+/* The six ACC programs (Section 3.2 for the Active/Compute/Combine triple,
  * Section 6 for the algorithms):
  *  SX_BFS      active = newly visited; compute = level + 1; combine = vote
  *              (any one update suffices).  Output int32 depth, -1 unreached.
@@ -126,8 +126,22 @@ sx_status sx_graph_info(const sx_graph *g, int32_t *n, int64_t *m, int32_t *dire
  *              label(v); combine = minimum.  Output int32 label = the
  *              smallest vertex id of the vertex's component (unique, so
  *              comparable bit for bit).  Undirected graphs only
- *              (SX_EUNSUPPORTED otherwise); the source is ignored (pass -1). */
-typedef enum { SX_BFS = 0, SX_SSSP = 1, SX_KCORE = 2, SX_PAGERANK = 3, SX_WCC = 4 } sx_algo;
+ *              (SX_EUNSUPPORTED otherwise); the source is ignored (pass -1).
+ *  SX_BP       belief propagation (Section 6: sum-product message passing,
+ *              the vertex probability as metadata; Section 3.2: every vertex
+ *              active, updates summed) on a binary pairwise Markov random
+ *              field over an undirected graph: vertex v has the prior
+ *              phi_v(1) = p_v, edge {u, v} the potential psi(x, y) = s_uv
+ *              when x == y and 1 - s_uv otherwise, s_uv = (1 + bp_kappa *
+ *              theta_uv / max(deg u, deg v)) / 2, theta_uv = (((w_uv - 1)
+ *              mod 64) - 31.5) / 31.5 (arc weights 1..64 span -1..1; 1 on an
+ *              unweighted graph).  bp_iters synchronous iterations
+ *              b'(v, x) ~ phi_v(x) prod_{u in N(v)} sum_y psi(y, x) b(u, y)
+ *              from b = phi.  d_out holds the priors p_v (float, each in
+ *              (0, 1), else SX_EINVAL) on entry and the beliefs b(v, 1) on
+ *              return (FP32 arithmetic, compensated sums).  Undirected
+ *              graphs only (SX_EUNSUPPORTED otherwise); pass source -1. */
+typedef enum { SX_BFS = 0, SX_SSSP = 1, SX_KCORE = 2, SX_PAGERANK = 3, SX_WCC = 4, SX_BP = 5 } sx_algo;
 
 /* sssp_delta: bucket width of delta-stepping for SX_SSSP (Section 3.3: the
  * vertices whose distances lie in the lowest non-empty bucket [B - delta, B)
@@ -150,6 +164,10 @@ typedef struct {
   uint32_t sssp_delta;   /* SSSP bucket width (0 = none)                       */
   int32_t kcore_k;       /* SX_KCORE: 0 = full decomposition (core numbers);
                             k > 0 = membership in the k-core (1 / 0)          */
+  float bp_kappa;        /* SX_BP: coupling scale, 0 <= bp_kappa < 1 (0 leaves
+                            every potential uniform; the synchronous update is
+                            a contraction with factor about bp_kappa)        */
+  int32_t bp_iters;      /* SX_BP: iterations (0 returns the priors)          */
 } sx_algo_params;
 #define SX_DELTA_AUTO 0xFFFFFFFFu
 

@@ -29,14 +29,15 @@ SX_OK, SX_EINVAL, SX_ENOMEM, SX_EHIP, SX_EUNSUPPORTED, SX_EDEADLOCK, SX_EOVERFLO
 # graph flags
 SX_UNDIRECTED, SX_DEVICE_PTRS, SX_VALIDATE, SX_REORDER = 1, 2, 4, 8
 # algorithms
-SX_BFS, SX_SSSP, SX_KCORE, SX_PAGERANK, SX_WCC = 0, 1, 2, 3, 4
+SX_BFS, SX_SSSP, SX_KCORE, SX_PAGERANK, SX_WCC, SX_BP = 0, 1, 2, 3, 4, 5
 # policy enums
 SX_DIR_AUTO, SX_DIR_PUSH, SX_DIR_PULL = 0, 1, 2
 SX_FILTER_JIT, SX_FILTER_ONLINE, SX_FILTER_BALLOT = 0, 1, 2
 SX_FUSE_AUTO, SX_FUSED, SX_UNFUSED, SX_SEQUENCED, SX_FUSED_ALL = 0, 1, 2, 3, 4
 SX_POLICY_HEURISTIC, SX_POLICY_LEARNED = 0, 1
 
-ALGOS = {"bfs": SX_BFS, "sssp": SX_SSSP, "kcore": SX_KCORE, "pagerank": SX_PAGERANK, "wcc": SX_WCC}
+ALGOS = {"bfs": SX_BFS, "sssp": SX_SSSP, "kcore": SX_KCORE, "pagerank": SX_PAGERANK, "wcc": SX_WCC,
+         "bp": SX_BP}
 
 EXPORTED = [
     "sx_ctx_create", "sx_ctx_destroy", "sx_status_str", "sx_last_error",
@@ -62,7 +63,8 @@ class sx_graph_desc(ctypes.Structure):
 
 class sx_algo_params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int), ("pr_damping", ctypes.c_float), ("pr_iters", ctypes.c_int32),
-                ("sssp_delta", ctypes.c_uint32), ("kcore_k", ctypes.c_int32)]
+                ("sssp_delta", ctypes.c_uint32), ("kcore_k", ctypes.c_int32),
+                ("bp_kappa", ctypes.c_float), ("bp_iters", ctypes.c_int32)]
 
 
 class sx_policy(ctypes.Structure):
@@ -214,9 +216,9 @@ SX_DELTA_AUTO = 0xFFFFFFFF
 
 
 def sx_program_register(ctx, algo: int, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0,
-                        kcore_k: int = 0):
+                        kcore_k: int = 0, bp_kappa: float = 0.5, bp_iters: int = 10):
     h = ctypes.c_void_p()
-    p = sx_algo_params(algo, pr_damping, pr_iters, sssp_delta, kcore_k)
+    p = sx_algo_params(algo, pr_damping, pr_iters, sssp_delta, kcore_k, bp_kappa, bp_iters)
     check(lib().sx_program_register(ctx, ctypes.byref(p), ctypes.byref(h)), "sx_program_register")
     return h
 
@@ -373,7 +375,7 @@ class Policy:
 
 
 OUT_DTYPES = {SX_BFS: "int32", SX_SSSP: "uint32", SX_KCORE: "int32", SX_PAGERANK: "float32",
-              SX_WCC: "int32"}
+              SX_WCC: "int32", SX_BP: "float32"}
 
 
 class DeviceGraph:
@@ -455,10 +457,11 @@ class Engine:
         return torch.cuda.current_stream(self.device).cuda_stream
 
     def program(self, algo: int, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0,
-                kcore_k: int = 0):
-        key = (algo, pr_damping, pr_iters, sssp_delta, kcore_k)
+                kcore_k: int = 0, bp_kappa: float = 0.5, bp_iters: int = 10):
+        key = (algo, pr_damping, pr_iters, sssp_delta, kcore_k, bp_kappa, bp_iters)
         if key not in self.programs:
-            self.programs[key] = sx_program_register(self.ctx, algo, pr_damping, pr_iters, sssp_delta, kcore_k)
+            self.programs[key] = sx_program_register(self.ctx, algo, pr_damping, pr_iters, sssp_delta, kcore_k,
+                                                     bp_kappa, bp_iters)
         return self.programs[key]
 
     def load(self, g, validate: bool = False, reorder: bool = False) -> DeviceGraph:
@@ -467,13 +470,25 @@ class Engine:
         return DeviceGraph(self, g, validate, reorder)
 
     def run(self, dg: DeviceGraph, algo: int, source: int = -1, policy: Optional[Policy] = None,
-            out=None, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0, kcore_k: int = 0):
+            out=None, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0, kcore_k: int = 0,
+            prior=None, bp_kappa: float = 0.5, bp_iters: int = 10):
         """Run and return (torch device tensor, stats dict).  sssp_delta: SSSP
         bucket width of delta-stepping (0 = none); kcore_k: membership in the
-        k-core instead of the decomposition (k > 0)."""
+        k-core instead of the decomposition (k > 0).  SX_BP: `prior` (n
+        floats in (0, 1), host or device) is copied into the output array,
+        which the run turns into the beliefs (or pass `out` already holding
+        the priors)."""
         import torch
-        p = self.program(algo, pr_damping, pr_iters, sssp_delta, kcore_k)
+        p = self.program(algo, pr_damping, pr_iters, sssp_delta, kcore_k, bp_kappa, bp_iters)
         sx_program_set_policy(p, (policy or Policy()).c())
+        if algo == SX_BP and prior is not None:
+            t = torch.as_tensor(np.ascontiguousarray(prior, dtype=np.float32)
+                                if isinstance(prior, np.ndarray) else prior)
+            out = t.to(device=self.device, dtype=torch.float32).clone() if out is None else out.copy_(t)
+            if dg.n == 0:
+                out = torch.empty(1, dtype=torch.float32, device=self.device)
+        elif algo == SX_BP and out is None:
+            raise ValueError("SX_BP needs the priors (prior= or out=)")
         if out is None:
             dt = {SX_PAGERANK: torch.float32}.get(algo, torch.int32)
             out = torch.empty(max(dg.n, 1), dtype=dt, device=self.device)

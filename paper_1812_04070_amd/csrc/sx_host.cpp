@@ -352,6 +352,8 @@ static sx_status work_alloc(Alloc al, long long n, long long m, bool directed, i
     ALLOC(w.alive_min, 4 * 2 * kMaxGrid);
     ALLOC(w.deg, 4 * nn);
     ALLOC(w.dang, 4 * 4 * kMaxGrid);
+    ALLOC(w.bph, 4 * nn);
+    for (int p = 0; p < 2; ++p) ALLOC(w.bpq[p], 8 * nn);
   }
 #undef ALLOC
   return SX_OK;
@@ -501,7 +503,9 @@ extern "C" sx_status sx_graph_info(const sx_graph *g, int32_t *n, int64_t *m, in
 // ----------------------------------------------------------- programs ---
 extern "C" sx_status sx_program_register(sx_ctx *ctx, const sx_algo_params *p, sx_program **out) {
   if (!ctx || !p || !out) return fail(SX_EINVAL, "NULL argument");
-  if (p->algo < SX_BFS || p->algo > SX_WCC) return fail(SX_EINVAL, "unknown algorithm %d", (int)p->algo);
+  if (p->algo < SX_BFS || p->algo > SX_BP) return fail(SX_EINVAL, "unknown algorithm %d", (int)p->algo);
+  if (p->algo == SX_BP && (p->bp_iters < 0 || !(p->bp_kappa >= 0.f && p->bp_kappa < 1.f)))
+    return fail(SX_EINVAL, "bad belief-propagation parameters (bp_iters >= 0, 0 <= bp_kappa < 1)");
   if (p->algo == SX_KCORE && p->kcore_k < 0) return fail(SX_EINVAL, "kcore_k < 0");
   if (p->algo == SX_PAGERANK && (p->pr_iters < 0 || !(p->pr_damping >= 0.f && p->pr_damping <= 1.f)))
     return fail(SX_EINVAL, "bad PageRank parameters");
@@ -624,6 +628,8 @@ static sx_status ctrl_error(const Ctrl *c) {
   if (c->error.v[0] == SX_ERR_OVERFLOW) return fail(SX_EOVERFLOW, "distance reached 0xFFFFFFFF");
   if (c->error.v[0] == SX_ERR_CAPACITY)
     return fail(SX_EHIP, "a scanned worklist exceeded its regions (engine bug)");
+  if (c->error.v[0] == SX_ERR_INPUT)
+    return fail(SX_EINVAL, "an input value is outside its domain (belief-propagation prior not in (0, 1))");
   if (c->error.v[0]) return fail(SX_EHIP, "device error %u", c->error.v[0]);
   return SX_OK;
 }
@@ -1089,6 +1095,38 @@ static sx_status run_pagerank(sx_program *p, sx_graph *G, void *d_out, hipStream
   return SX_OK;
 }
 
+// ------------------------------------------------- belief propagation ---
+static sx_status run_bp(sx_program *p, sx_graph *G, void *d_belief, hipStream_t st, sx_run_stats *stats) {
+  const int n = G->g.n;
+  if (n == 0 || p->ap.bp_iters == 0) {
+    if (stats) memset(stats, 0, sizeof *stats);
+    return SX_OK;
+  }
+  const int grid = persistent_grid(p->ctx, bp_kernel(), p->pol.grid_wgs);
+  BpArgs a;
+  memset(&a, 0, sizeof a);
+  a.g = G->g;
+  a.w = G->w;
+  a.P = make_params(p, G, grid);
+  // a workgroup takes a whole vertex (no chunks), as in PageRank
+  if (p->pol.bin_large <= 0) a.P.t2 = std::max(a.P.t1, 2048);
+  a.belief = (float *)d_belief;
+  a.kappa = p->ap.bp_kappa;
+  a.iters = p->ap.bp_iters;
+  HIP_TRY(hipEventRecord(G->ev0, st));
+  HIP_TRY(bp_launch(a, grid, st));
+  HIP_TRY(hipEventRecord(G->ev1, st));
+  sx_status s = read_ctrl(G, st);
+  if (s != SX_OK) return s;
+  s = ctrl_error(G->h_ctrl);
+  if (s != SX_OK) return s;
+  HIP_TRY(hipEventSynchronize(G->ev1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
+  fill_stats(G->h_ctrl, 4, ms, grid, p->ctx->wall_khz, stats);
+  return SX_OK;
+}
+
 // ------------------------------------------------ policy data collection ---
 namespace {
 struct Snapshot {
@@ -1470,6 +1508,12 @@ extern "C" sx_status sx_run(sx_program *p, const sx_graph *gc, int32_t source, v
       break;
     case SX_PAGERANK:
       s = run_pagerank(p, G, state, st, stats);
+      break;
+    case SX_BP:
+      if (G->directed) return fail(SX_EUNSUPPORTED, "belief propagation on a directed graph");
+      // the priors arrive in d_out, in the caller's numbering
+      if (G->reordered && n > 0) HIP_TRY(reorder_permute(d_out, G->d_inv, G->state, n, st));
+      s = run_bp(p, G, state, st, stats);
       break;
     default:
       return fail(SX_EINVAL, "unknown algorithm");

@@ -39,6 +39,9 @@ const void *kcore_seq_kernel();
 hipError_t pagerank_launch(const PrArgs &a, int grid, hipStream_t s);
 const void *pagerank_kernel();
 
+hipError_t bp_launch(const BpArgs &a, int grid, hipStream_t s);
+const void *bp_kernel();
+
 // Degree-ordered renumbering (graph loading option).  `own` allocates
 // device memory that the graph keeps, `tmp` memory freed after the build.
 // out: the renumbered graph; *d_inv / h_inv[n]: old id -> new id.
@@ -47,6 +50,8 @@ hipError_t reorder_build(const DevGraph &g, const RkAlloc &own, const RkAlloc &t
                          DevGraph &out, int **d_inv, int *h_inv);
 // out[v] = in[inv[v]] for 4-byte elements
 hipError_t reorder_unpermute(const void *in, const int *inv, void *out, int n, hipStream_t s);
+// out[inv[v]] = in[v] for 4-byte elements
+hipError_t reorder_permute(const void *in, const int *inv, void *out, int n, hipStream_t s);
 
 hipError_t mlp_forward(const float *P, const float *X, int n, float *Y, float *H, hipStream_t s);
 // the in-kernel inference (mlp_eval_wave, one wavefront per sample)

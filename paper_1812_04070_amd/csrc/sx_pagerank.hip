@@ -24,45 +24,6 @@
 namespace sx {
 
 
-struct CSum {
-  float s, c;
-};
-// Knuth's TwoSum: s + x = t + e exactly
-SX_DEV void cadd(CSum &a, float x) {
-  const float t = a.s + x;
-  const float z = t - a.s;
-  const float e = (a.s - (t - z)) + (x - z);
-  a.s = t;
-  a.c += e;
-}
-SX_DEV CSum cmerge(CSum a, CSum b) {
-  CSum r{a.s, a.c + b.c};
-  cadd(r, b.s);
-  return r;
-}
-SX_DEV CSum wave_merge(CSum a) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    CSum b{__shfl_xor(a.s, o), __shfl_xor(a.c, o)};
-    a = cmerge(a, b);
-  }
-  return a;
-}
-// fixed-order workgroup merge; result valid in every thread
-SX_DEV CSum wg_merge(CSum a, float *lds /* 2*kWaves */) {
-  a = wave_merge(a);
-  __syncthreads();
-  if (lane_id() == 0) {
-    lds[2 * wave_in_wg()] = a.s;
-    lds[2 * wave_in_wg() + 1] = a.c;
-  }
-  __syncthreads();
-  CSum r{lds[0], lds[1]};
-  for (int w = 1; w < kWaves; ++w) r = cmerge(r, CSum{lds[2 * w], lds[2 * w + 1]});
-  __syncthreads();
-  return r;
-}
-
 struct LdsPr {
   LdsView view;
   LdsBallot ball;

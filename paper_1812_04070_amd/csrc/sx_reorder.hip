@@ -74,6 +74,13 @@ __global__ void k_rk_unpermute(const unsigned *in, const int *inv, unsigned *out
     out[v] = in[inv[v]];
 }
 
+// out[inv[v]] = in[v]: an input in the caller's numbering into the new one
+__global__ void k_rk_permute(const unsigned *in, const int *inv, unsigned *out, int n) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (long long)gridDim.x * blockDim.x)
+    out[inv[v]] = in[v];
+}
+
 constexpr int kRkBlock = 256;
 
 int rk_grid(long long items) {
@@ -185,6 +192,13 @@ hipError_t reorder_build(const DevGraph &g, const RkAlloc &own, const RkAlloc &t
 hipError_t reorder_unpermute(const void *in, const int *inv, void *out, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rk_unpermute, dim3(rk_grid(n)), dim3(kRkBlock), 0, s, (const unsigned *)in, inv,
+                     (unsigned *)out, n);
+  return hipGetLastError();
+}
+
+hipError_t reorder_permute(const void *in, const int *inv, void *out, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rk_permute, dim3(rk_grid(n)), dim3(kRkBlock), 0, s, (const unsigned *)in, inv,
                      (unsigned *)out, n);
   return hipGetLastError();
 }

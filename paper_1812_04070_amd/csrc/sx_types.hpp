@@ -17,7 +17,10 @@ constexpr int kStatLines = 64;           // statistics spread over 64 lines
 
 // SX_ERR_CAPACITY: a list built by a ballot scan did not fit its regions
 // (the host sizes them so that this cannot happen)
-enum : unsigned { SX_ERR_NONE = 0, SX_ERR_DEADLOCK = 1, SX_ERR_OVERFLOW = 2, SX_ERR_CAPACITY = 3 };
+// SX_ERR_INPUT: an input value outside its domain (a belief-propagation
+// prior not in (0, 1))
+enum : unsigned { SX_ERR_NONE = 0, SX_ERR_DEADLOCK = 1, SX_ERR_OVERFLOW = 2, SX_ERR_CAPACITY = 3,
+                  SX_ERR_INPUT = 4 };
 
 // kernel exit reasons written to Ctrl::state
 enum : int { EXIT_NONE = 0, EXIT_DONE = 1, EXIT_SWITCH = 2, EXIT_ERROR = 3, EXIT_LIMIT = 4 };
@@ -96,6 +99,8 @@ struct Work {
   unsigned *alive_min;             // [2][kMaxGrid] minimum survivor degree
   float *contrib[2];               // PageRank contributions (double buffered)
   float *dang;                     // PageRank dangling partials [2][kMaxGrid][2]
+  float *bph;                      // belief propagation: prior field atanh(2p - 1)
+  float2 *bpq[2];                  // and (2 b - 1, degree) per vertex, double buffered
   Ctrl *ctrl;
 };
 
@@ -173,6 +178,15 @@ struct PrArgs {
   float *rank;                  // output
   float base_teleport;          // (1-d)/n
   float inv_n;                  // 1/n
+  int iters;
+};
+
+struct BpArgs {
+  DevGraph g;
+  Work w;
+  Params P;
+  float *belief;                // in: prior P(x_v = 1); out: belief after iters
+  float kappa;                  // coupling scale of the pairwise potentials
   int iters;
 };
 
