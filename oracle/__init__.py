@@ -52,7 +52,9 @@ def lib():
                            ("sxo_kcore_member", [ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32, vp]),
                            ("sxo_wcc", [ctypes.c_int32, vp, vp, vp]),
                            ("sxo_pagerank", [ctypes.c_int32, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp]),
-                           ("sxo_bp", [ctypes.c_int32, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp])]:
+                           ("sxo_bp", [ctypes.c_int32, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp]),
+                           ("sxo_pagerank_fixpoint", [ctypes.c_int32, vp, vp, vp, ctypes.c_double, ctypes.c_double,
+                                                      ctypes.c_int32, vp])]:
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int
@@ -207,3 +209,22 @@ def bp_g(g, prior, kappa=0.5, iters=10):
     if g.directed:
         raise ValueError("belief propagation runs on undirected graphs")
     return bp(g.n, g.offsets, g.indices, g.weights, prior, kappa, iters)
+
+
+def pagerank_fixpoint(n, offsets, in_offsets, in_indices, d=0.85, tol=1e-14, max_iters=10000):
+    """PageRank iterated to its fixed point (Section 6: until the ranks are
+    stable): the fp64 recurrence of pagerank() until one step changes the
+    vector by at most `tol` in L1.  Returns (ranks, steps)."""
+    off = _c(offsets, np.int32)
+    io = _c(in_offsets, np.int32)
+    ii = _c(in_indices, np.int32)
+    out = np.empty(max(n, 1), dtype=np.float64)
+    steps = _check(lib().sxo_pagerank_fixpoint(n, _p(off), _p(io), _p(ii), float(d), float(tol), int(max_iters),
+                                               _p(out)), "sxo_pagerank_fixpoint")
+    return out[:n], steps
+
+
+def pagerank_fixpoint_g(g, d=0.85, tol=1e-14, max_iters=10000):
+    if g.directed:
+        return pagerank_fixpoint(g.n, g.offsets, g.in_offsets, g.in_indices, d, tol, max_iters)
+    return pagerank_fixpoint(g.n, g.offsets, g.offsets, g.indices, d, tol, max_iters)

@@ -30,6 +30,9 @@
  *            synchronous iterations in fp64, x0 = 1/n,
  *            x'(v) = (1-d)/n + d * (sum_{u->v} x(u)/outdeg(u) + D/n),
  *            D = sum of x over vertices without out-arcs.
+ *            The same recurrence iterated to its fixed point (Section 6:
+ *            "till all vertices have stable rank values"): until one step
+ *            changes the vector by at most tol in L1.
  *   BP       Section 6 ("Belief propagation": sum-product message passing on
  *            a Markov random field, the vertex's probability as its state)
  *            and Section 3.2 (every vertex active, updates summed): a binary
@@ -387,6 +390,42 @@ int sxo_pagerank(int32_t n, const int32_t *off, const int32_t *in_off, const int
     memcpy(x_out, x, sizeof(double) * (size_t)n);
     free(x); free(y);
     return 0;
+}
+
+/* PageRank to its fixed point: the recurrence above, iterated until the L1
+ * norm of one step's change is at most tol (or max_iters steps).  The map is a
+ * contraction with factor d in L1, so the result lies within tol * d / (1 - d)
+ * of the fixed point.  Returns the number of steps taken (negative on bad
+ * input). */
+int sxo_pagerank_fixpoint(int32_t n, const int32_t *off, const int32_t *in_off, const int32_t *in_idx,
+                          double d, double tol, int32_t max_iters, double *x_out) {
+    if (n < 0 || max_iters < 0 || !(tol >= 0.0)) return -1;
+    if (n == 0) return 0;
+    double *x = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!x || !y) { free(x); free(y); return -2; }
+    for (int32_t v = 0; v < n; ++v) x[v] = 1.0 / (double)n;
+    int32_t t = 0;
+    for (; t < max_iters; ++t) {
+        double dangling = 0.0;
+        for (int32_t u = 0; u < n; ++u)
+            if (off[u + 1] == off[u]) dangling += x[u];
+        double change = 0.0;
+        for (int32_t v = 0; v < n; ++v) {
+            double s = 0.0;
+            for (int64_t e = in_off[v]; e < in_off[v + 1]; ++e) {
+                int32_t u = in_idx[e];
+                s += x[u] / (double)(off[u + 1] - off[u]);
+            }
+            y[v] = (1.0 - d) / (double)n + d * (s + dangling / (double)n);
+            change += fabs(y[v] - x[v]);
+        }
+        double *t2 = x; x = y; y = t2;
+        if (change <= tol) { ++t; break; }
+    }
+    memcpy(x_out, x, sizeof(double) * (size_t)n);
+    free(x); free(y);
+    return t;
 }
 
 /* ---------------------------------------------------- belief propagation --- */

@@ -321,6 +321,46 @@ def test_wcc_scipy_cross_check():
         assert np.unique(mine).size == nc
 
 
+def test_pagerank_fixpoint_solves_the_linear_system():
+    """The fixed point equals the solution of (I - d P - d/n 1 dangling^T) x =
+    (1 - d)/n 1 by numpy.linalg.solve (a library routine on the dense
+    system), and the Google matrix's principal eigenvector."""
+    for seed, dangle in ((3, True), (4, False), (5, True)):
+        g0 = gen.random_graph(14, 0.25, seed=seed, directed=True)
+        if dangle:
+            src = np.repeat(np.arange(g0.n), np.diff(g0.offsets))
+            keep = src % 5 != 0
+            g = gen.from_edges(g0.n, np.stack([src[keep], g0.indices[keep]], 1), directed=True)
+        else:
+            g = g0
+        x, steps = oracle.pagerank_fixpoint_g(g, tol=1e-15)
+        n = g.n
+        outdeg = np.diff(g.offsets)
+        P = np.zeros((n, n))
+        for v in range(n):
+            for e in range(g.in_offsets[v], g.in_offsets[v + 1]):
+                P[v, g.in_indices[e]] += 1.0 / outdeg[g.in_indices[e]]
+        D = np.outer(np.ones(n), (outdeg == 0).astype(float)) / n
+        A = np.eye(n) - 0.85 * (P + D)
+        np.testing.assert_allclose(x, np.linalg.solve(A, np.full(n, 0.15 / n)), rtol=1e-12)
+        _, G = pins.pagerank_dense(n, g.offsets, g.in_offsets, g.in_indices, 0.85, 0)
+        np.testing.assert_allclose(x, pins.pagerank_stationary(G), rtol=1e-10)
+        assert 0 < steps < 10000
+
+
+def test_pagerank_fixpoint_stopping_rule():
+    """Steps and distance: a loose tolerance stops earlier, and the result is
+    within tol * d / (1 - d) of the tight fixed point (contraction in L1); the
+    20-step vector is within 2 d^20 of it."""
+    g = gen.rmat(12, seed=4, directed=True)
+    xs, ns = oracle.pagerank_fixpoint_g(g, tol=1e-15)
+    for tol in (1e-4, 1e-7, 1e-10):
+        x, k = oracle.pagerank_fixpoint_g(g, tol=tol)
+        assert k < ns
+        assert np.abs(x - xs).sum() <= tol * 0.85 / 0.15 * 1.0001
+    assert np.abs(oracle.pagerank_g(g) - xs).sum() <= 2 * 0.85 ** 20
+
+
 # ------------------------------------------------- belief propagation ----
 
 def _bp_graphs():
