@@ -349,6 +349,20 @@ def pagerank_main(args):
                      "traffic": None, "launches": 1, "avg_launch_us": round(1e3 * dev_ms, 1),
                      "algorithmic_bytes_per_launch": nbytes},
     }
+    # run until stable (Section 6): pull while most vertices change, then the
+    # delta-accumulative push tail chosen by the decision tree
+    tail = {}
+    for tol in (1e-4, 1e-6):
+        for _ in range(max(1, args.warmup)):
+            eng.run(dg, sx.SX_PAGERANK, -1, pol, out=out, pr_tol=tol, pr_iters=0)
+        tdev = []
+        for _ in range(max(3, args.steps // 4)):
+            _, tst = eng.run(dg, sx.SX_PAGERANK, -1, pol, out=out, pr_tol=tol, pr_iters=0)
+            tdev.append(tst["device_ms"])
+        tail[f"tol_{tol:g}"] = {"device_ms": round(float(np.median(tdev)), 3), "pull_iterations": tst["pull_iters"],
+                                "push_steps": tst["iterations"] - tst["pull_iters"],
+                                "arcs_inspected": tst["edges_inspected"]}
+    log(f"[bench] pagerank until stable: {tail}")
     if not args.no_cpu:
         import oracle
         t0 = time.perf_counter()
@@ -364,6 +378,7 @@ def pagerank_main(args):
     else:
         result["cpu_baseline"] = None
     result["kcore"] = kcore
+    result["until_stable"] = tail
     dg.close()
     eng.close()
     print(json.dumps(result))

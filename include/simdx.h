@@ -164,6 +164,17 @@ typedef struct {
   uint32_t sssp_delta;   /* SSSP bucket width (0 = none)                       */
   int32_t kcore_k;       /* SX_KCORE: 0 = full decomposition (core numbers);
                             k > 0 = membership in the k-core (1 / 0)          */
+  float pr_tol;          /* SX_PAGERANK: 0 = exactly pr_iters synchronous
+                            pull iterations; > 0 = run until stable (Section
+                            6): pull iterations while most vertices still
+                            change, then the delta-accumulative push tail,
+                            switched by a fixed decision tree (converged: stop;
+                            at most n/2 vertices (the majority is stable)
+                            changing by more than
+                            pr_tol (1 - d) / (2n), or pr_iters pull
+                            iterations done (0: 1,000): push; else pull); the
+                            result lies within about pr_tol (L1) of the fixed
+                            point, up to FP32 rounding; 0 <= pr_tol < 1      */
   float bp_kappa;        /* SX_BP: coupling scale, 0 <= bp_kappa < 1 (0 leaves
                             every potential uniform; the synchronous update is
                             a contraction with factor about bp_kappa)        */

@@ -64,7 +64,7 @@ class sx_graph_desc(ctypes.Structure):
 class sx_algo_params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int), ("pr_damping", ctypes.c_float), ("pr_iters", ctypes.c_int32),
                 ("sssp_delta", ctypes.c_uint32), ("kcore_k", ctypes.c_int32),
-                ("bp_kappa", ctypes.c_float), ("bp_iters", ctypes.c_int32)]
+                ("pr_tol", ctypes.c_float), ("bp_kappa", ctypes.c_float), ("bp_iters", ctypes.c_int32)]
 
 
 class sx_policy(ctypes.Structure):
@@ -216,9 +216,9 @@ SX_DELTA_AUTO = 0xFFFFFFFF
 
 
 def sx_program_register(ctx, algo: int, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0,
-                        kcore_k: int = 0, bp_kappa: float = 0.5, bp_iters: int = 10):
+                        kcore_k: int = 0, bp_kappa: float = 0.5, bp_iters: int = 10, pr_tol: float = 0.0):
     h = ctypes.c_void_p()
-    p = sx_algo_params(algo, pr_damping, pr_iters, sssp_delta, kcore_k, bp_kappa, bp_iters)
+    p = sx_algo_params(algo, pr_damping, pr_iters, sssp_delta, kcore_k, pr_tol, bp_kappa, bp_iters)
     check(lib().sx_program_register(ctx, ctypes.byref(p), ctypes.byref(h)), "sx_program_register")
     return h
 
@@ -457,11 +457,11 @@ class Engine:
         return torch.cuda.current_stream(self.device).cuda_stream
 
     def program(self, algo: int, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0,
-                kcore_k: int = 0, bp_kappa: float = 0.5, bp_iters: int = 10):
-        key = (algo, pr_damping, pr_iters, sssp_delta, kcore_k, bp_kappa, bp_iters)
+                kcore_k: int = 0, bp_kappa: float = 0.5, bp_iters: int = 10, pr_tol: float = 0.0):
+        key = (algo, pr_damping, pr_iters, sssp_delta, kcore_k, bp_kappa, bp_iters, pr_tol)
         if key not in self.programs:
             self.programs[key] = sx_program_register(self.ctx, algo, pr_damping, pr_iters, sssp_delta, kcore_k,
-                                                     bp_kappa, bp_iters)
+                                                     bp_kappa, bp_iters, pr_tol)
         return self.programs[key]
 
     def load(self, g, validate: bool = False, reorder: bool = False) -> DeviceGraph:
@@ -471,7 +471,7 @@ class Engine:
 
     def run(self, dg: DeviceGraph, algo: int, source: int = -1, policy: Optional[Policy] = None,
             out=None, pr_damping: float = 0.85, pr_iters: int = 20, sssp_delta: int = 0, kcore_k: int = 0,
-            prior=None, bp_kappa: float = 0.5, bp_iters: int = 10):
+            prior=None, bp_kappa: float = 0.5, bp_iters: int = 10, pr_tol: float = 0.0):
         """Run and return (torch device tensor, stats dict).  sssp_delta: SSSP
         bucket width of delta-stepping (0 = none); kcore_k: membership in the
         k-core instead of the decomposition (k > 0).  SX_BP: `prior` (n
@@ -479,7 +479,7 @@ class Engine:
         which the run turns into the beliefs (or pass `out` already holding
         the priors)."""
         import torch
-        p = self.program(algo, pr_damping, pr_iters, sssp_delta, kcore_k, bp_kappa, bp_iters)
+        p = self.program(algo, pr_damping, pr_iters, sssp_delta, kcore_k, bp_kappa, bp_iters, pr_tol)
         sx_program_set_policy(p, (policy or Policy()).c())
         if algo == SX_BP and prior is not None:
             t = torch.as_tensor(np.ascontiguousarray(prior, dtype=np.float32)

@@ -352,6 +352,8 @@ static sx_status work_alloc(Alloc al, long long n, long long m, bool directed, i
     ALLOC(w.alive_min, 4 * 2 * kMaxGrid);
     ALLOC(w.deg, 4 * nn);
     ALLOC(w.dang, 4 * 4 * kMaxGrid);
+    ALLOC(w.prd, 4 * nn);
+    ALLOC(w.prp, 4 * 2 * 8 * kMaxGrid);
     ALLOC(w.bph, 4 * nn);
     for (int p = 0; p < 2; ++p) ALLOC(w.bpq[p], 8 * nn);
   }
@@ -507,7 +509,9 @@ extern "C" sx_status sx_program_register(sx_ctx *ctx, const sx_algo_params *p, s
   if (p->algo == SX_BP && (p->bp_iters < 0 || !(p->bp_kappa >= 0.f && p->bp_kappa < 1.f)))
     return fail(SX_EINVAL, "bad belief-propagation parameters (bp_iters >= 0, 0 <= bp_kappa < 1)");
   if (p->algo == SX_KCORE && p->kcore_k < 0) return fail(SX_EINVAL, "kcore_k < 0");
-  if (p->algo == SX_PAGERANK && (p->pr_iters < 0 || !(p->pr_damping >= 0.f && p->pr_damping <= 1.f)))
+  if (p->algo == SX_PAGERANK && (p->pr_iters < 0 || !(p->pr_damping >= 0.f && p->pr_damping <= 1.f) ||
+                                 !(p->pr_tol >= 0.f && p->pr_tol < 1.f) ||
+                                 (p->pr_tol > 0.f && !(p->pr_damping < 1.f))))
     return fail(SX_EINVAL, "bad PageRank parameters");
   sx_program *P = new sx_program();
   P->ctx = ctx;
@@ -1060,7 +1064,8 @@ static sx_status run_pagerank(sx_program *p, sx_graph *G, void *d_out, hipStream
     if (stats) memset(stats, 0, sizeof *stats);
     return SX_OK;
   }
-  const int grid = persistent_grid(p->ctx, pagerank_kernel(), p->pol.grid_wgs);
+  const bool conv = p->ap.pr_tol > 0.f;
+  const int grid = persistent_grid(p->ctx, pagerank_kernel(conv), p->pol.grid_wgs);
   PrArgs a;
   memset(&a, 0, sizeof a);
   a.g = G->g;
@@ -1075,8 +1080,18 @@ static sx_status run_pagerank(sx_program *p, sx_graph *G, void *d_out, hipStream
   a.base_teleport = (float)((1.0 - (double)d) / (double)n);
   a.inv_n = (float)(1.0 / (double)n);
   a.iters = p->ap.pr_iters;
+  if (conv) {
+    // run to convergence: a pending change of at most thr per vertex leaves
+    // an L1 error of at most n thr / (1 - d) = tol / 2; a pull step that
+    // changes the vector by at most tol (1 - d) / d is within tol of the
+    // fixed point (contraction with factor d in L1)
+    a.conv = 1;
+    a.max_pull = a.iters > 0 ? a.iters : 1000;
+    a.thr = (float)((double)p->ap.pr_tol * (1.0 - (double)d) / (2.0 * (double)n));
+    a.stop_change = (float)((double)p->ap.pr_tol * (1.0 - (double)d) / std::max((double)d, 1e-30));
+  }
   HIP_TRY(hipEventRecord(G->ev0, st));
-  if (a.iters == 0) {
+  if (a.iters == 0 && !conv) {
     std::vector<float> h((size_t)n, a.inv_n);
     HIP_TRY(hipMemcpyAsync(d_out, h.data(), sizeof(float) * n, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));

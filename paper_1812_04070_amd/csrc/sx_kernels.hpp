@@ -37,7 +37,8 @@ hipError_t kcore_membership(int *core, int n, hipStream_t s);
 const void *kcore_seq_kernel();
 
 hipError_t pagerank_launch(const PrArgs &a, int grid, hipStream_t s);
-const void *pagerank_kernel();
+// conv: the kernel of the run to convergence
+const void *pagerank_kernel(bool conv = false);
 
 hipError_t bp_launch(const BpArgs &a, int grid, hipStream_t s);
 const void *bp_kernel();

@@ -99,6 +99,8 @@ struct Work {
   unsigned *alive_min;             // [2][kMaxGrid] minimum survivor degree
   float *contrib[2];               // PageRank contributions (double buffered)
   float *dang;                     // PageRank dangling partials [2][kMaxGrid][2]
+  float *prd;                      // PageRank to convergence: pending change per vertex
+  float *prp;                      // and per-workgroup partials [2][kMaxGrid][8]
   float *bph;                      // belief propagation: prior field atanh(2p - 1)
   float2 *bpq[2];                  // and (2 b - 1, degree) per vertex, double buffered
   Ctrl *ctrl;
@@ -179,6 +181,11 @@ struct PrArgs {
   float base_teleport;          // (1-d)/n
   float inv_n;                  // 1/n
   int iters;
+  // run to convergence (pull, then the delta-accumulative push tail):
+  int conv;                     // 1: iterate until stable instead of `iters`
+  int max_pull;                 // pull iterations after which the tail starts anyway
+  float thr;                    // a pending change above this is pushed
+  float stop_change;            // pull converged: one step changed at most this (L1)
 };
 
 struct BpArgs {

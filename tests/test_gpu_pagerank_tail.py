@@ -1,0 +1,101 @@
+"""PageRank run until stable (pr_tol > 0): pull iterations, the decision
+tree, the delta-accumulative push tail and the final normalisation, against
+the fp64 fixed point of the oracle.
+
+Bound: L1 distance to the fixed point <= pr_tol + 3e-6.  pr_tol is the
+algorithm's own bound (a pull step changing the vector by at most
+tol (1 - d) / d, or pending changes of at most tol (1 - d) / (2n) per vertex,
+leave at most tol, resp. tol / 2, in L1); 3e-6 covers FP32 rounding: ranks
+near 1/n carry ~1e-7 relative error per stored value and per accumulated
+push (a few per vertex), plus the compensated pull sums."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1812_04070_amd as sx
+from paper_1812_04070_amd import gen
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+FP32_FLOOR = 3e-6
+
+
+@pytest.fixture(scope="module")
+def engine():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    e = sx.Engine(0)
+    yield e
+    e.close()
+
+
+def _dangling(g0):
+    src = np.repeat(np.arange(g0.n), np.diff(g0.offsets))
+    keep = src % 3 != 0
+    return gen.from_edges(g0.n, np.stack([src[keep], g0.indices[keep]], 1), directed=True)
+
+
+GRAPHS = [
+    ("er-200-directed", lambda: gen.random_graph(200, 0.03, seed=1, directed=True)),
+    ("er-300-dangling", lambda: _dangling(gen.random_graph(300, 0.02, seed=2, directed=True))),
+    ("rmat12-directed", lambda: gen.rmat(12, seed=4, directed=True)),
+    ("rmat14-directed", lambda: gen.rmat(14, seed=5, directed=True)),
+    ("rmat12-undirected", lambda: gen.rmat(12, seed=6)),
+    ("grid-40", lambda: gen.grid(40, 0.1, seed=7)),
+]
+ARMS = [("default", None, 0), ("tail-after-2-pulls", None, 2), ("tail-after-1-pull", None, 1),
+        ("tiny-online-cap", sx.Policy(online_cap=1), 2), ("tiny-bins", sx.Policy(bin_small=4, bin_large=8), 3)]
+
+
+def _check(engine, dg, g, tol, pol, max_pull):
+    out, st = engine.run(dg, sx.SX_PAGERANK, -1, pol, pr_tol=tol, pr_iters=max_pull)
+    x = engine.to_host(dg, sx.SX_PAGERANK, out).astype(np.float64)
+    ref, _ = oracle.pagerank_fixpoint_g(g, tol=1e-15)
+    err = float(np.abs(x - ref).sum())
+    assert err <= tol + FP32_FLOOR, (err, tol, st)
+    assert abs(x.sum() - 1.0) <= 1e-5
+    return st, err
+
+
+@pytest.mark.parametrize("name,make", GRAPHS, ids=[g[0] for g in GRAPHS])
+def test_pagerank_until_stable(engine, name, make):
+    g = make()
+    dg = engine.load(g)
+    for tol in (1e-4, 1e-6):
+        for arm, pol, max_pull in ARMS:
+            announce(f"pagerank tail {name} tol={tol} {arm}")
+            st, err = _check(engine, dg, g, tol, pol, max_pull)
+            if max_pull:
+                assert st["pull_iters"] <= max_pull
+    dg.close()
+
+
+def test_pagerank_tail_engages_and_reorder(engine):
+    """On R-MAT s16 (directed) the default tree hands over to the push tail;
+    the same on the degree-renumbered load."""
+    g = gen.rmat(16, seed=4, directed=True)
+    for reorder in (False, True):
+        dg = engine.load(g, reorder=reorder)
+        announce(f"pagerank tail rmat16d reorder={reorder}")
+        st, err = _check(engine, dg, g, 1e-6, None, 0)
+        assert st["iterations"] > st["pull_iters"], st      # push steps ran
+        dg.close()
+
+
+def test_pagerank_tail_rmat20(engine):
+    g = gen.rmat(20, seed=7, directed=True)
+    dg = engine.load(g, reorder=True)
+    for tol, max_pull in ((1e-5, 0), (1e-5, 4)):
+        announce(f"pagerank tail rmat20d tol={tol} max_pull={max_pull}")
+        _check(engine, dg, g, tol, None, max_pull)
+    dg.close()
+
+
+def test_pagerank_tol_rejected(engine):
+    for tol in (-1e-3, 1.0):
+        with pytest.raises(sx.SxError) as ei:
+            sx.sx_program_register(engine.ctx, sx.SX_PAGERANK, pr_tol=tol)
+        assert ei.value.status == sx.SX_EINVAL
