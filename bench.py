@@ -58,6 +58,11 @@ def parse():
     ap.add_argument("--bp", action="store_true",
                     help="instead of the step: time belief propagation (10 iterations, kappa 0.5) on "
                          "the R-MAT scale 22 graph and print its own JSON line")
+    ap.add_argument("--ablation", action="store_true",
+                    help="instead of the step: time every kernel arrangement (no fusion, the sequenced "
+                         "launches, selective fusion, all fusion) per algorithm on the R-MAT scale 22 "
+                         "graph and the 4096^2 grid, with the register use of each kernel, and print "
+                         "one JSON line")
     ap.add_argument("--delta", type=int, default=-1,
                     help="SSSP delta-stepping bucket width (0 = none; default: the workload's own)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -456,6 +461,89 @@ def bp_main(args):
     print(json.dumps(result))
 
 
+def ablation_main(args):
+    """Fusion ablation (Section 5, Table table-compile; Section 7,
+    Fig. exp-selective-fusion): device time of each algorithm under each
+    arrangement of the same phases -- none (one launch per phase, the host
+    deciding in between), sequenced (one launch per phase, decisions on the
+    device, launches queued ahead), selective fusion (one persistent kernel
+    per direction, a direction change relaunches) and all fusion (one
+    persistent kernel for both directions) -- where the engine has it, plus
+    the kernels' registers and persistent grids.  Outputs of every arm are
+    compared with the first arm's (bit for bit; PageRank and BP have one
+    arrangement)."""
+    import torch
+    import paper_1812_04070_amd as sx
+    from paper_1812_04070_amd import gen
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    eng = sx.Engine(0)
+    arms = [("none", sx.SX_UNFUSED), ("sequenced", sx.SX_SEQUENCED), ("selective", sx.SX_FUSED),
+            ("all", sx.SX_FUSED_ALL)]
+    reps = max(3, min(args.steps, 7))
+    table = {}
+    for wname, reorder in (("rmat22", True), ("grid4096", False)):
+        g = gen.workload_graph(wname)
+        src = gen.max_degree_vertex(g)
+        dg = eng.load(g, reorder=reorder)
+        algos = [("bfs", sx.SX_BFS, src), ("sssp", sx.SX_SSSP, src), ("wcc", sx.SX_WCC, -1)]
+        if wname == "rmat22":
+            algos.append(("kcore", sx.SX_KCORE, -1))
+        for aname, algo, s0 in algos:
+            ref = None
+            for arm, fused in arms:
+                if aname == "kcore" and fused in (sx.SX_UNFUSED, sx.SX_FUSED_ALL):
+                    continue       # k-core: sequenced launches or one persistent kernel
+                pol = sx.Policy(fused=fused)
+                kw = {"sssp_delta": sx.SX_DELTA_AUTO} if algo == sx.SX_SSSP else {}
+                if wname == "grid4096" and fused == sx.SX_UNFUSED:
+                    reps_here = 1  # thousands of host round trips
+                else:
+                    reps_here = reps
+                ts = []
+                for _ in range(reps_here + 1):
+                    out, st = eng.run(dg, algo, s0, pol, **kw)
+                    ts.append(st["device_ms"])
+                h = eng.to_host(dg, algo, out)
+                same = True if ref is None else bool(np.array_equal(h, ref))
+                ref = h if ref is None else ref
+                table[f"{wname}/{aname}/{arm}"] = {"ms": round(float(np.median(ts[1:])), 3),
+                                                   "launches": st["launches"], "iterations": st["iterations"],
+                                                   "barrier_wait_ms": round(st["barrier_wait_ms"], 3),
+                                                   "same_as_first_arm": same}
+                log(f"[ablation] {wname} {aname} {arm}: {table[f'{wname}/{aname}/{arm}']}")
+        if wname == "rmat22":
+            prior = gen.bp_priors(g.n, seed=22)
+            for aname, algo, kw in (("bp", sx.SX_BP, {"prior": prior}),):
+                ts = []
+                for _ in range(reps + 1):
+                    _, st = eng.run(dg, algo, -1, None, **kw)
+                    ts.append(st["device_ms"])
+                table[f"{wname}/{aname}/all"] = {"ms": round(float(np.median(ts[1:])), 3),
+                                                 "launches": st["launches"], "iterations": st["iterations"]}
+        dg.close()
+    gd = gen.workload_graph("rmat24d")
+    dgd = eng.load(gd, reorder=True)
+    ts = []
+    for _ in range(reps + 1):
+        _, st = eng.run(dgd, sx.SX_PAGERANK, -1, None)
+        ts.append(st["device_ms"])
+    table["rmat24d/pagerank/all"] = {"ms": round(float(np.median(ts[1:])), 3), "launches": st["launches"],
+                                     "iterations": st["iterations"]}
+    dgd.close()
+    regs = {}
+    for k in ("bfs_fused", "bfs_fused_pull", "bfs_fused_all", "bfs_seq", "bfs_push_step", "bfs_pull_step",
+              "sssp_fused", "sssp_fused_pull", "sssp_fused_all", "sssp_seq", "sssp_push_step",
+              "sssp_pull_step", "wcc_fused", "wcc_fused_all", "wcc_seq", "kcore_fused", "kcore_seq",
+              "pagerank_fused", "pagerank_until_stable", "bp_fused", "batch"):
+        regs[k] = eng.kernel_info(k)
+    result = {"metric": "fusion ablation: device ms per algorithm and kernel arrangement", "value": None,
+              "unit": "ms", "n_gpus": 1, "steps": reps, "warmup": 1, "higher_is_better": False,
+              "data": "synthetic", "config": {"workload": "rmat22 (renumbered), grid4096, rmat24d"},
+              "times": table, "kernels": regs}
+    eng.close()
+    print(json.dumps(result))
+
+
 def grid_main(args):
     """BFS + SSSP on the 4096 x 4096 four-neighbour grid with 10 % of its
     edges deleted (weights in [1, 1000]) from the highest-degree vertex
@@ -567,6 +655,9 @@ def main():
         return
     if args.bp:
         bp_main(args)
+        return
+    if args.ablation:
+        ablation_main(args)
         return
     import torch
     import paper_1812_04070_amd as sx

@@ -170,8 +170,8 @@ typedef struct {
                             change, then the delta-accumulative push tail,
                             switched by a fixed decision tree (converged: stop;
                             at most n/2 vertices (the majority is stable)
-                            changing by more than
-                            pr_tol (1 - d) / (2n), or pr_iters pull
+                            changing by more than pr_tol (1 - d) / (2n) and
+                            their out-arcs at most m / 16, or pr_iters pull
                             iterations done (0: 1,000): push; else pull); the
                             result lies within about pr_tol (L1) of the fixed
                             point, up to FP32 rounding; 0 <= pr_tol < 1      */
@@ -378,7 +378,7 @@ sx_status sx_batch_autotune(sx_ctx *ctx, const sx_query *queries, int32_t nq, co
  * graphs of 2^25 arcs or more, built for three workgroups per CU),
  * "bfs_push_step", "bfs_pull_step", "sssp_push_step",
  * "sssp_pull_step", "ballot_scan", "pull_scan", "kcore_fused", "kcore_seq",
- * "pagerank_fused", "batch".
+ * "pagerank_fused", "pagerank_until_stable" (pr_tol > 0), "bp_fused", "batch".
  * Errors: SX_EINVAL (unknown name), SX_EHIP. */
 typedef struct {
   int32_t vgprs, sgprs, lds_bytes, block, wgs_per_cu, grid_wgs, cus;

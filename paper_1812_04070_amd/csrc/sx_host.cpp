@@ -1746,6 +1746,8 @@ extern "C" sx_status sx_kernel_info_get(sx_ctx *ctx, const char *name, sx_kernel
       {"kcore_fused", kcore_kernel(), true},
       {"kcore_seq", kcore_seq_kernel(), false},
       {"pagerank_fused", pagerank_kernel(), true},
+      {"pagerank_until_stable", pagerank_kernel(true), true},
+      {"bp_fused", bp_kernel(), true},
       {"batch", batch_kernel(), true},
   };
   for (const Named &t : table) {

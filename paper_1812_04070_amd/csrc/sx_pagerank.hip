@@ -25,8 +25,11 @@
 // tree).  Pull iterations as above also record each vertex's change; the
 // tree after every iteration: (1) the step changed the vector by at most
 // stop_change in L1 -> done; (2) at most n/2 vertices (the majority is
-// stable) have a non-uniform change above thr, or max_pull iterations ran
-// -> push tail; (3) otherwise pull again.  The tail is the delta-accumulative form: every vertex keeps
+// stable) have a non-uniform change above thr and their out-arcs are at
+// most m / kPushArcCost (a push sends an atomic add per arc where a pull
+// gathers one value: MI355X runs the pull about ten times as many arcs per
+// second), or max_pull iterations ran -> push tail; (3) otherwise pull
+// again.  The tail is the delta-accumulative form: every vertex keeps
 // its pending change; a listed vertex takes its change (atomic exchange),
 // adds it to its rank and sends d * change / outdeg to each out-neighbour
 // (atomic add); a neighbour whose pending change crosses thr joins the next
@@ -44,6 +47,9 @@
 
 namespace sx {
 
+
+// a push step's cost per arc in units of a pull step's (decision tree)
+constexpr float kPushArcCost = 16.f;
 
 struct LdsPr {
   LdsView view;
@@ -123,6 +129,7 @@ struct Track {
   float cu;                     // uniform part of this step's change: d (D_t - D_{t-1}) / n
   float active;                 // vertices with a non-uniform change above thr
   CSum change;                  // L1 norm of x_{t+1} - x_t
+  CSum arcs;                    // their out-arcs (what a push step would send)
 };
 SX_DEV void pr_finish_tracked(const PrArgs &a, int v, CSum s, float D, float *dst, CSum &dang,
                               Track &tr) {
@@ -133,8 +140,11 @@ SX_DEV void pr_finish_tracked(const PrArgs &a, int v, CSum s, float D, float *ds
   const float pend = (r - r0) - tr.cu;
   a.w.prd[v] = pend;
   cadd(tr.change, fabsf(r - r0));
-  if (fabsf(pend) > a.thr) tr.active += 1.f;
   const int od = a.g.off[v + 1] - a.g.off[v];
+  if (fabsf(pend) > a.thr) {
+    tr.active += 1.f;
+    cadd(tr.arcs, (float)od);
+  }
   if (od > 0) dst[v] = r / (float)od;
   else cadd(dang, r);
 }
@@ -194,11 +204,14 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const ViewRef &L, const Totals 
   if constexpr (kTrack) {
     const CSum ch = wg_merge(tr.change, lds.f);
     const CSum ac = wg_merge(CSum{tr.active, 0.f}, lds.f);
+    const CSum ar = wg_merge(tr.arcs, lds.f);
     if (threadIdx.x == 0) {
       float *q = w.prp + ((size_t)(t & 1) * kMaxGrid + blockIdx.x) * 8;
       q[0] = ac.s + ac.c;
       q[1] = ch.s;
       q[2] = ch.c;
+      q[3] = ar.s;
+      q[4] = ar.c;
     }
   }
   add_stats(w.ctrl, blockIdx.x, edges, 0ull, lds.red);
@@ -381,14 +394,16 @@ __global__ void __launch_bounds__(kBlock) k_pr_conv(PrArgs a) {
     const float D = dangling_total(a.w.dang + (size_t)(t & 1) * 2 * kMaxGrid, gridDim.x, lds.f);
     cu = t == 0 ? 0.f : a.P.pr_d * (D - Dprev) * a.inv_n;
     Dprev = D;
-    Track tr{cu, 0.f, CSum{0.f, 0.f}};
+    Track tr{cu, 0.f, CSum{0.f, 0.f}, CSum{0.f, 0.f}};
     pr_iteration<true>(a, t, L, T, lds, D, tr);
     if (!bar.sync()) return;
     // the decision tree, evaluated identically by every workgroup
     const CSum ch = partial_sum(a.w.prp, t & 1, 1, 2, lds.f);
     const CSum ac = partial_sum(a.w.prp, t & 1, 0, -1, lds.f);
+    const CSum ar = partial_sum(a.w.prp, t & 1, 3, 4, lds.f);
     if (ch.s + ch.c <= a.stop_change) break;
-    if ((t >= 1 && ac.s + ac.c <= 0.5f * (float)n) || t + 1 >= a.max_pull) {
+    if ((t >= 1 && ac.s + ac.c <= 0.5f * (float)n && (ar.s + ar.c) * kPushArcCost <= (float)a.g.m) ||
+        t + 1 >= a.max_pull) {
       tail = true;
       break;
     }
@@ -440,11 +455,11 @@ __global__ void __launch_bounds__(kBlock) k_pr_conv(PrArgs a) {
   sum = wg_merge(sum, lds.f);
   if (threadIdx.x == 0) {
     float *q = a.w.prp + ((size_t)0 * kMaxGrid + vg.bid) * 8;
-    q[4] = sum.s;
-    q[5] = sum.c;
+    q[6] = sum.s;
+    q[7] = sum.c;
   }
   if (!bar.sync()) return;
-  const CSum tot = partial_sum(a.w.prp, 0, 4, 5, lds.f);
+  const CSum tot = partial_sum(a.w.prp, 0, 6, 7, lds.f);
   const float S1 = tot.s + tot.c;
   for (long long v = (long long)vg.bid * kBlock + threadIdx.x; v < n; v += (long long)vg.nb * kBlock)
     a.rank[v] = a.rank[v] / S1;
