@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--bp", action="store_true",
                     help="instead of the step: time belief propagation (10 iterations, kappa 0.5) on "
                          "the R-MAT scale 22 graph and print its own JSON line")
+    ap.add_argument("--wcc", action="store_true",
+                    help="instead of the step: time connected components (minimum-label propagation) on "
+                         "the R-MAT scale 22 graph and print its own JSON line")
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the step: time every kernel arrangement (no fusion, the sequenced "
                          "launches, selective fusion, all fusion) per algorithm on the R-MAT scale 22 "
@@ -124,7 +127,10 @@ def algo_bytes(kind: str, st: dict, n: int, reached: int) -> float:
       k-core 8 B per inspected arc (id + degree decrement, or id + stamp in a
             pull step) + 12 B per alive-list entry scanned (entry, core number,
             degree) + 16 B per vertex (core number and stamp writes, list
-            write and read)."""
+            write and read)
+      WCC   8 B per expansion + 8 B per inspected arc (id, label) + 12 B per
+            expansion (label and stamp write, list write and read) + 4n B
+            per metadata scan."""
     e, x = st["edges_inspected"], st["vertex_expansions"]
     scans = st["ballot_iters"] + st["pull_iters"]
     if kind == "bfs":
@@ -133,6 +139,8 @@ def algo_bytes(kind: str, st: dict, n: int, reached: int) -> float:
         return 8.0 * x + 12.0 * e + 12.0 * x + 4.0 * n * scans
     if kind == "kcore":
         return 8.0 * e + 12.0 * st["scan_entries"] + 16.0 * n
+    if kind == "wcc":
+        return 8.0 * x + 8.0 * e + 12.0 * x + 4.0 * n * scans
     raise KeyError(kind)
 
 
@@ -154,7 +162,7 @@ def trav_kernel_name(kind: str, fused: int, arcs: int, n: int) -> str:
     seq = fused in (0, 3)
     if kind == "kcore":
         return "k_kcore_seq" if seq else "k_kcore_fused"
-    ops = "BfsOps" if kind == "bfs" else "SsspOps"
+    ops = {"bfs": "BfsOps", "wcc": "WccOps"}.get(kind, "SsspOps")
     if not seq:
         return f"k_fused<{ops}>"
     return f"k_seq<{ops}, 6>" if arcs >= (1 << 25) and arcs >= 8 * n else f"k_seq<{ops}>"
@@ -461,6 +469,66 @@ def bp_main(args):
     print(json.dumps(result))
 
 
+def wcc_main(args):
+    """Connected components (minimum-label propagation, every vertex active
+    at the start) on the undirected R-MAT scale-22 graph, renumbered;
+    value = GTEPS over all undirected edges.  Labels are checked against the
+    oracle's union-find after the timed region."""
+    import torch
+    import paper_1812_04070_amd as sx
+    from paper_1812_04070_amd import gen
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    g = gen.workload_graph("rmat22")
+    eng = sx.Engine(0)
+    dg = eng.load(g, reorder=True)
+    out = torch.empty(g.n, dtype=torch.int32, device=eng.device)
+    pol = sx.Policy(fused=args.fused)
+    for _ in range(args.warmup):
+        eng.run(dg, sx.SX_WCC, -1, pol, out=out)
+    torch.cuda.synchronize()
+    dev = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = eng.run(dg, sx.SX_WCC, -1, pol, out=out)
+        dev.append(st["device_ms"])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    dev_ms = float(np.median(dev))
+    launches = max(1, int(st["launches"]) - 1)
+    nbytes = algo_bytes("wcc", st, g.n, g.n)
+    avg_us = 1e3 * dev_ms / launches
+    achieved = nbytes / launches / (avg_us / 1e6) / 1e9
+    lab = eng.to_host(dg, sx.SX_WCC, out)
+    result = {
+        "metric": "connected components (minimum labels), R-MAT s22", "value": round((g.m // 2) / (dev_ms / 1e3) / 1e9, 3),
+        "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "rmat22-wcc", "n": g.n, "arcs": g.m, "reorder": True},
+        "device_ms": {"median": round(dev_ms, 4), "mean": round(float(np.mean(dev)), 4),
+                      "min": round(float(np.min(dev)), 4)},
+        "iterations": st["iterations"], "pull_iters": st["pull_iters"], "edges_inspected": st["edges_inspected"],
+        "roofline": {"bound": "hbm", "kernel": trav_kernel_name("wcc", args.fused, g.m, g.n),
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "launches": launches,
+                     "avg_launch_us": round(avg_us, 3), "algorithmic_bytes_per_launch": round(nbytes / launches, 1)},
+    }
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.wcc_g(g)
+        cpu_s = time.perf_counter() - t0
+        result["bit_exact"] = bool(np.array_equal(lab, ref))
+        result["cpu_baseline"] = {"value": round((g.m // 2) / cpu_s / 1e9, 4), "unit": "GTEPS", "cores": 1,
+                                  "kind": "oracle", "sample": "union-find over the same graph, serial C"}
+    else:
+        result["cpu_baseline"] = None
+    dg.close()
+    eng.close()
+    print(json.dumps(result))
+    if result.get("bit_exact") is False:
+        sys.exit(1)
+
+
 def ablation_main(args):
     """Fusion ablation (Section 5, Table table-compile; Section 7,
     Fig. exp-selective-fusion): device time of each algorithm under each
@@ -658,6 +726,9 @@ def main():
         return
     if args.ablation:
         ablation_main(args)
+        return
+    if args.wcc:
+        wcc_main(args)
         return
     import torch
     import paper_1812_04070_amd as sx
