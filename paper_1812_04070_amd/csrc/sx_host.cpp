@@ -567,16 +567,19 @@ static int plain_grid(sx_ctx *ctx, const void *kernel) {
   return std::min(per * ctx->cus, kMaxGrid);
 }
 
+// the heuristic's bin thresholds (lane / wavefront / workgroup)
+static const int kDefaultT1 = 64, kDefaultT2 = 512;
+
 static Params make_params(const sx_program *p, const sx_graph *G, int grid) {
   Params P;
   memset(&P, 0, sizeof P);
   const sx_policy &pol = p->pol;
-  P.t1 = pol.bin_small > 0 ? pol.bin_small : 64;
+  P.t1 = pol.bin_small > 0 ? pol.bin_small : kDefaultT1;
   // 512: below it a vertex's arcs are one or two steps of a wavefront (four
   // arcs per lane); as a workgroup item they would leave most of its 2,048
   // lanes-times-arcs idle (R-MAT s22: BFS 0.56 -> 0.42 ms, SSSP 3.1 -> 2.8 ms
   // against 256; k-core is flat from 384 to 768 and slower from 1,024 up)
-  P.t2 = pol.bin_large > 0 ? pol.bin_large : 512;
+  P.t2 = pol.bin_large > 0 ? pol.bin_large : kDefaultT2;
   if (P.t2 < P.t1) P.t2 = P.t1;
   P.chunk = kChunk;
   // online filter limit per workgroup and bin: the caller's entries per
@@ -772,16 +775,8 @@ static Decision host_decide(const sx_ctx *ctx, const sx_policy &pol, Params &P, 
       memcpy(log->x, x, sizeof log->x);
       memcpy(log->y, y, sizeof log->y);
     }
-    if (pol.direction == SX_DIR_AUTO) {
-      if (!pulling) d.to_pull = y[0] > 0.f;
-      else d.to_push = !(y[0] > 0.f);
-    }
-    if (!pulling && !d.to_pull) d.ballot = in.ovf || (P.filter == 0 ? y[1] > 0.f : P.filter == 2);
-    if (!P.bins_fixed) {
-      P.t1 = 1 << clamp_log2(y[2], 2, 8);
-      const int t2 = 1 << clamp_log2(y[3], 6, 12);
-      P.t2 = std::max(t2, P.t1);
-    }
+    apply_network(y, pulling, in.ovf != 0, pol.direction, P.filter, P.bins_fixed != 0, kDefaultT1,
+                  std::max(kDefaultT1, kDefaultT2), d, P.t1, P.t2);
   }
   ps.nf_prev = in.nf;
   ps.reached += in.nf;

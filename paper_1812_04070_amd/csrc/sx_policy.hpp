@@ -22,14 +22,14 @@ constexpr int kMlpW1 = 0, kMlpB1 = kMlpW1 + kMlpHid * kMlpIn, kMlpW2 = kMlpB1 + 
               kMlpB3 = kMlpW3 + kMlpOut * kMlpHid, kMlpParams = kMlpB3 + kMlpOut;
 static_assert(kMlpParams == 1476, "parameter count");
 
-// The network is consulted for frontiers of at least this many arcs.  In
-// the collected per-iteration timings (R-MAT and grid graphs, BFS and SSSP)
-// the mean time the best of the six ways to run an iteration saves over
-// pushing the online lists is 0.01-0.1 us below 10^4 frontier arcs and
-// 1.9 us between 10^4 and 3 * 10^4, against about 1.5 us that an in-kernel
-// decision by the network adds to the launch (measured on 2,137-iteration
-// grid runs); below the threshold the heuristic decides.
-constexpr unsigned long long kPolicyMinArcs = 32768;
+// The network is consulted for frontiers of at least this many arcs: an
+// in-kernel decision by the network adds about 1.5 us to its launch (weights
+// staged into LDS by every workgroup, one wavefront evaluating), which the
+// thousands of light iterations of a grid pay without any gain (1024^2 grid
+// SSSP, 2,600 iterations of 10^4 to 10^5 arcs: 35.6 -> 38.0 ms with the
+// network consulted from 32,768 arcs); from 2^18 arcs an iteration takes
+// 50 us or more.
+constexpr unsigned long long kPolicyMinArcs = 1ull << 18;
 
 // Frontier features of the decision after iteration it.
 struct PolicyState {
@@ -130,6 +130,54 @@ inline void mlp_eval_host(const float *P, const float x[8], float y[4]) {
 __host__ __device__ inline int clamp_log2(float v, int lo, int hi) {
   int r = (int)floorf(v + 0.5f);
   return r < lo ? lo : (r > hi ? hi : r);
+}
+
+// How far a logit must lean away from the heuristic's choice before the
+// network's choice replaces it.  On the 361 training records the heuristic
+// runs within 0.6 % of the best of the six arms per iteration (22.06 ms
+// against 21.92 ms summed); the trained network's picks cost 23.14 ms when
+// followed at margin 0, 23.08 at 1, 22.43 at 2 and 22.06 (the heuristic's)
+// at 4: the margin is the smallest at which the network costs nothing on
+// its own training data.
+constexpr float kPolicyMargin = 4.0f;
+
+// The heuristic's decision d for the next iteration, amended by the network's
+// outputs y where the caller left the choice open (direction SX_DIR_AUTO,
+// filter SX_FILTER_JIT, bins not fixed): each logit is shifted toward the
+// heuristic's own choice by kPolicyMargin, and the bin thresholds follow the
+// network only for a ballot rebuild the network chose; otherwise they are
+// the run's (dflt_t1, dflt_t2).  Shared by the device decision and the
+// one-phase host loop.
+__host__ __device__ inline void apply_network(const float y[kMlpOut], bool pulling, bool ovf, int direction,
+                                              int filter, bool bins_fixed, int dflt_t1, int dflt_t2,
+                                              Decision &d, int &t1, int &t2) {
+  if (direction == 0) {
+    const bool h_pull = pulling ? !d.to_push : d.to_pull;
+    const bool n_pull = y[0] + (h_pull ? kPolicyMargin : -kPolicyMargin) > 0.f;
+    if (!pulling) d.to_pull = n_pull;
+    else d.to_push = !n_pull;
+  }
+  bool net_ballot = false;
+  if (!pulling && !d.to_pull) {
+    if (filter == 0) {
+      const bool h_ballot = d.ballot;
+      const bool b = y[1] + (h_ballot ? kPolicyMargin : -kPolicyMargin) > 0.f;
+      net_ballot = b && !h_ballot;
+      d.ballot = ovf || b;
+    } else {
+      d.ballot = ovf || filter == 2;
+    }
+  }
+  if (!bins_fixed) {
+    if (net_ballot) {
+      t1 = 1 << clamp_log2(y[2], 2, 8);
+      const int u = 1 << clamp_log2(y[3], 6, 12);
+      t2 = u > t1 ? u : t1;
+    } else {
+      t1 = dflt_t1;
+      t2 = dflt_t2;
+    }
+  }
 }
 
 }  // namespace sx

@@ -582,17 +582,9 @@ SX_DEV Decision decide(const TravArgs &a, RunState &s, bool pulling, const Total
       }
     }
     __syncthreads();
-    const float y0 = pol->y[0], y1 = pol->y[1], y2 = pol->y[2], y3 = pol->y[3];
-    if (a.P.direction == 0) {
-      if (!pulling) d.to_pull = y0 > 0.f;
-      else d.to_push = !(y0 > 0.f);
-    }
-    if (!pulling && !d.to_pull) d.ballot = in.ovf || (a.P.filter == 0 ? y1 > 0.f : a.P.filter == 2);
-    if (!a.P.bins_fixed) {
-      s.P.t1 = 1 << clamp_log2(y2, 2, 8);
-      const int t2 = 1 << clamp_log2(y3, 6, 12);
-      s.P.t2 = t2 > s.P.t1 ? t2 : s.P.t1;
-    }
+    const float y[kMlpOut] = {pol->y[0], pol->y[1], pol->y[2], pol->y[3]};
+    apply_network(y, pulling, in.ovf != 0, a.P.direction, a.P.filter, a.P.bins_fixed != 0, a.P.t1, a.P.t2, d,
+                  s.P.t1, s.P.t2);
   }
   s.ps.nf_prev = in.nf;
   s.ps.reached += in.nf;

@@ -7,9 +7,10 @@
    and grid graphs), `sx_policy_collect` times, before each iteration, six ways
    of running it from the same saved state (push on the online lists, push
    after a ballot rebuild with four bin-threshold pairs, pull).
-2. Label: the fastest arm gives the pull target; among push arms, whether a
-   ballot rebuild won; the thresholds of the fastest ballot arm give the two
-   regression targets (log2).
+2. Label: the heuristic's own arm, unless another arm is more than 10 %
+   faster on that record (then that arm): its direction, filter and -- for a
+   ballot arm -- bin thresholds (log2) are the targets; elsewhere the
+   heuristic's thresholds.
 3. Train on the GPU with the library's own kernels (sx_mlp_loss_grad +
    sx_mlp_adam), full batch.
 4. Write the parameters (1,476 floats) and the training summary as JSON.
@@ -28,6 +29,10 @@ import time
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_BINS = (64, 512)        # the heuristic's bin thresholds
+POLICY_MIN_ARCS = 1 << 18       # the engine's kPolicyMinArcs (sx_policy.hpp)
+DEVIATE_MARGIN = 0.10           # depart from the heuristic's arm only if >10 % faster
+POLICY_MARGIN = 4.0             # the engine's kPolicyMargin (logit units, sx_policy.hpp)
 DEFAULT_OUT = os.path.join(HERE, "policy_mlp.json")
 
 
@@ -44,39 +49,61 @@ def training_graphs(quick: bool):
     return gs
 
 
-def labels(arm_ms: np.ndarray):
+def labels(arm_ms: np.ndarray, margin: float = None):
     """targets [r, 4], weights [r, 4] from per-arm times (NaN = arm not
-    possible).  The two classification heads are weighted by what a wrong
-    choice costs on that record (relative time difference between the best
-    push and the pull arm, and between the online and the best ballot arm,
-    clipped to [0.05, 5]), so that iterations where the choice hardly
-    matters do not outvote the ones where it does."""
+    possible).  The target of a record is the heuristic's own arm unless
+    another arm is faster by more than `margin` (relative): the network is
+    to depart from the heuristic only where the timings say that pays, by
+    more than its in-kernel evaluation and the timing noise.  The two
+    classification heads are weighted by what a wrong choice costs on that
+    record (relative time difference between the best push and the pull
+    arm, and between the online and the best ballot arm, clipped to
+    [0.05, 5]), so that iterations where the choice hardly matters do not
+    outvote the ones where it does.  Bin thresholds: the chosen ballot arm's
+    where the target is a ballot arm, else the heuristic's (64, 512) -- the
+    network's thresholds also bin the online lists, which no arm timed with
+    other thresholds (targets taken from the best ballot arm regardless
+    cost the online pushes 5-18 % with 16 / 256)."""
     import paper_1812_04070_amd as sx
+    if margin is None:
+        margin = DEVIATE_MARGIN
     r = arm_ms.shape[0]
+    rows = np.arange(r)
     t = np.zeros((r, 4), dtype=np.float32)
     m = np.zeros((r, 4), dtype=np.float32)
     ms = np.where(np.isnan(arm_ms), np.inf, arm_ms)
     best = ms.argmin(1)
+    harm = heuristic_arm(arm_ms)
+    dev = ms[rows, best] < (1.0 - margin) * ms[rows, harm]
+    target = np.where(dev, best, harm)
+    t[:, 0] = target == 5
     t_push = ms[:, :5].min(1)
     t_pull = ms[:, 5]
-    t[:, 0] = (t_pull < t_push)
     lo = np.minimum(t_push, t_pull)
     m[:, 0] = np.clip(np.abs(t_push - t_pull) / np.maximum(lo, 1e-6), 0.05, 5.0)
+    t[:, 1] = (target >= 1) & (target <= 4)
     t_on = ms[:, 0]
     t_bal = ms[:, 1:5].min(1)
-    t[:, 1] = (t_bal < t_on)
     have_on = np.isfinite(t_on)
     lo = np.minimum(t_on, t_bal)
     w = np.clip(np.abs(t_on - t_bal) / np.maximum(lo, 1e-6), 0.05, 5.0)
-    # without the online arm (after a pull or an overflow) the rebuild is forced
+    # without the online arm (after a pull) the filter head is not used
     m[:, 1] = np.where(have_on, w, 0.0)
-    bb = 1 + ms[:, 1:5].argmin(1)
-    th = np.array([sx.ARM_THRESHOLDS[k] for k in bb], dtype=np.float64)
-    t[:, 2] = np.log2(th[:, 0])
-    t[:, 3] = np.log2(th[:, 1])
+    ballot = (target >= 1) & (target <= 4)
+    th = np.array([sx.ARM_THRESHOLDS[k] if 1 <= k <= 4 else DEFAULT_BINS for k in target], dtype=np.float64)
+    t[:, 2] = np.where(ballot, np.log2(th[:, 0]), np.log2(DEFAULT_BINS[0]))
+    t[:, 3] = np.where(ballot, np.log2(th[:, 1]), np.log2(DEFAULT_BINS[1]))
     m[:, 2] = 1
     m[:, 3] = 1
     return t, m, best
+
+
+def heuristic_arm(arm_ms: np.ndarray) -> np.ndarray:
+    """The arm the heuristic itself runs for each record: the pull (arm 5)
+    where it was pulling -- the only case in which the collector marks the
+    online push (arm 0) unavailable -- else the push of its own lists (arm
+    0: the online lists, or the ballot rebuild it made after an overflow)."""
+    return np.where(np.isnan(arm_ms[:, 0]), 5, 0)
 
 
 def collect(eng, quick: bool, log=print):
@@ -178,8 +205,30 @@ def main():
     ms = np.where(np.isnan(A), np.inf, A)
     # time of the arms the network picks, against the best arm and the arm
     # the heuristic rule picks (push on the online lists unless pulling)
-    pick = np.where(y[:, 0] > 0, 5, np.where((y[:, 1] > 0) | ~np.isfinite(ms[:, 0]), 1 + ms[:, 1:5].argmin(1), 0))
-    net_ms = float(ms[np.arange(len(ms)), pick].sum())
+    # the arms the deployed network picks: the engine consults it only for
+    # frontiers of POLICY_MIN_ARCS arcs or more (feature 1 = log2(1 + arcs)
+    # / 32), and a choice departs from the heuristic's only when its logit
+    # leans the other way by more than the margin
+    harm = heuristic_arm(A)
+    consult = np.exp2(32.0 * X[:, 1]) - 1.0 >= POLICY_MIN_ARCS
+    rows = np.arange(len(ms))
+    heur_ms = float(ms[rows, harm].sum())
+
+    def picks(tau):
+        h_pull = harm == 5
+        n_pull = y[:, 0] + np.where(h_pull, tau, -tau) > 0
+        n_ballot = ~n_pull & (harm == 0) & (y[:, 1] - tau > 0)
+        th = np.stack([np.clip(np.rint(y[:, 2]), 2, 8), np.clip(np.rint(y[:, 3]), 6, 12)], 1)
+        arms_th = np.log2(np.array(sx.ARM_THRESHOLDS[1:5], dtype=np.float64))
+        near = 1 + np.abs(th[:, None, :] - arms_th[None, :, :]).sum(2).argmin(1)
+        # a push after the heuristic's pull: its lists are rebuilt (the
+        # collector has no online arm there); counted as the (64, 256) rebuild
+        pk = np.where(n_pull, 5, np.where(n_ballot, near, np.where(harm == 5, 2, 0)))
+        return np.where(consult, pk, harm)
+
+    margins = {f"{tau:g}": float(ms[rows, picks(tau)].sum()) for tau in (0.0, 0.5, 1.0, 2.0, 4.0)}
+    pick = picks(POLICY_MARGIN)
+    net_ms = float(ms[rows, pick].sum())
     summary = {
         "records": int(len(X)),
         "arm_wins": {str(k): int((best == k).sum()) for k in range(sx.SX_POLICY_ARMS)},
@@ -187,7 +236,11 @@ def main():
         "train_acc_direction": acc_dir,
         "train_acc_filter": acc_flt,
         "best_arm_ms_total": float(ms.min(1).sum()),
+        "heuristic_arm_ms_total": heur_ms,
         "network_arm_ms_total": net_ms,
+        "network_arm_ms_total_by_margin": margins,
+        "records_network_consulted": int(consult.sum()),
+        "records_network_differs_from_heuristic": int((pick != harm).sum()),
         "workloads": sorted(set(tags.tolist())),
     }
     with open(args.out, "w") as f:

@@ -104,7 +104,9 @@ def test_learned_policy_keeps_results_exact(engine, seed):
     pull drops them)."""
     p = (ref.init_params(seed) * 3.0).astype(np.float32)
     sx.sx_policy_load_mlp(engine.ctx, p)
-    for name, g in [("rmat13", gen.rmat(13, seed=seed + 3, weights=(1, 64))),
+    # R-MAT s16 has frontiers above the engine's consultation threshold (2^18
+    # arcs), the grid none: both paths of the decision
+    for name, g in [("rmat16", gen.rmat(16, seed=seed + 3, weights=(1, 64))),
                     ("grid64", gen.grid(64, 0.1, seed=seed, weights=(1, 1000)))]:
         src = gen.max_degree_vertex(g)
         dg = engine.load(g)
@@ -114,6 +116,8 @@ def test_learned_policy_keeps_results_exact(engine, seed):
             announce(f"learned {name} seed={seed} fused={fused}")
             d, st = run(engine, g, sx.SX_BFS, src, pol, dg=dg)
             np.testing.assert_array_equal(d, ref_d)
+            if name == "rmat16":
+                assert st["policy_evals"] >= 1, st
             x, st = run(engine, g, sx.SX_SSSP, src, pol, dg=dg)
             np.testing.assert_array_equal(x, ref_x)
             for delta in (40, 2000):
@@ -132,7 +136,7 @@ def test_learned_decisions_match_oracle_network(engine, fused):
     host inference in the one-phase arrangement)."""
     p = (ref.init_params(11) * 2.0).astype(np.float32)
     sx.sx_policy_load_mlp(engine.ctx, p)
-    g = gen.rmat(15, seed=13, weights=(1, 64))
+    g = gen.rmat(16, seed=13, weights=(1, 64))
     src = gen.max_degree_vertex(g)
     dg = engine.load(g)
     for algo in (sx.SX_BFS, sx.SX_SSSP):
@@ -165,7 +169,7 @@ def test_policy_collect(engine):
 
 
 def _batch_graphs():
-    return [gen.rmat(10, seed=21, weights=(1, 64)), gen.rmat(13, seed=22, weights=(1, 64)),
+    return [gen.rmat(10, seed=21, weights=(1, 64)), gen.rmat(16, seed=22, weights=(1, 64)),
             gen.grid(48, 0.1, seed=23, weights=(1, 64)), gen.grid(100, 0.1, seed=24, weights=(1, 64)),
             gen.random_graph(300, 0.02, seed=25, weights=(1, 64))]
 
@@ -236,8 +240,11 @@ def test_trained_policy_gain(engine):
     """What the trained network gains over the heuristic it replaces: BFS and
     SSSP device time on graphs of the training families (R-MAT and a grid
     with deleted edges, fresh seeds), heuristic vs learned policy, outputs
-    identical.  The network may lose on some runs; over the set its regret
-    stays bounded (learned total within 1.25x of the heuristic total)."""
+    identical.  On these workloads the heuristic runs within 0.6 % of the
+    best arm per iteration (training records), so the network departs from
+    it only with a confident logit and only on heavy iterations: the bound is
+    no measurable loss (learned total within 3 % of the heuristic's, the
+    run-to-run spread of these timings), not a gain."""
     sx.sx_policy_load_mlp(engine.ctx, _trained_params())
     heur, learned = sx.Policy(), sx.Policy(policy=sx.SX_POLICY_LEARNED)
     rows, tot_h, tot_l = [], 0.0, 0.0
@@ -267,4 +274,4 @@ def test_trained_policy_gain(engine):
               f"gain {r[2] / r[3]:.3f}x", flush=True)
     print(f"[policy-gain] total heuristic {tot_h:.3f} ms learned {tot_l:.3f} ms gain {tot_h / tot_l:.3f}x",
           flush=True)
-    assert tot_l <= 1.25 * tot_h
+    assert tot_l <= 1.03 * tot_h
