@@ -602,7 +602,7 @@ def ablation_main(args):
     for k in ("bfs_fused", "bfs_fused_pull", "bfs_fused_all", "bfs_seq", "bfs_push_step", "bfs_pull_step",
               "sssp_fused", "sssp_fused_pull", "sssp_fused_all", "sssp_seq", "sssp_push_step",
               "sssp_pull_step", "wcc_fused", "wcc_fused_all", "wcc_seq", "kcore_fused", "kcore_seq",
-              "pagerank_fused", "pagerank_until_stable", "bp_fused", "batch"):
+              "pagerank_fused", "pagerank_until_stable", "pagerank_push_tail", "bp_fused", "batch"):
         regs[k] = eng.kernel_info(k)
     result = {"metric": "fusion ablation: device ms per algorithm and kernel arrangement", "value": None,
               "unit": "ms", "n_gpus": 1, "steps": reps, "warmup": 1, "higher_is_better": False,

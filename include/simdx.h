@@ -378,7 +378,8 @@ sx_status sx_batch_autotune(sx_ctx *ctx, const sx_query *queries, int32_t nq, co
  * graphs of 2^25 arcs or more, built for three workgroups per CU),
  * "bfs_push_step", "bfs_pull_step", "sssp_push_step",
  * "sssp_pull_step", "ballot_scan", "pull_scan", "kcore_fused", "kcore_seq",
- * "pagerank_fused", "pagerank_until_stable" (pr_tol > 0), "bp_fused", "batch".
+ * "pagerank_fused", "pagerank_until_stable" (pr_tol > 0: its pull kernel),
+ * "pagerank_push_tail" (its push kernel), "bp_fused", "batch".
  * Errors: SX_EINVAL (unknown name), SX_EHIP. */
 typedef struct {
   int32_t vgprs, sgprs, lds_bytes, block, wgs_per_cu, grid_wgs, cus;

@@ -1093,15 +1093,30 @@ static sx_status run_pagerank(sx_program *p, sx_graph *G, void *d_out, hipStream
   } else {
     HIP_TRY(pagerank_launch(a, grid, st));
   }
+  int launches = 2;
+  if (conv) {
+    // the pull kernel ends the run or hands it to the push kernel
+    sx_status s0 = read_ctrl(G, st);
+    if (s0 != SX_OK) return s0;
+    s0 = ctrl_error(G->h_ctrl);
+    if (s0 != SX_OK) return s0;
+    if (G->h_ctrl->state.v[0] == EXIT_SWITCH) {
+      const int pgrid = persistent_grid(p->ctx, pagerank_push_kernel(), p->pol.grid_wgs);
+      HIP_TRY(pagerank_push_launch(a, pgrid, st));
+      ++launches;
+    }
+  }
   HIP_TRY(hipEventRecord(G->ev1, st));
   sx_status s = read_ctrl(G, st);
   if (s != SX_OK) return s;
   s = ctrl_error(G->h_ctrl);
   if (s != SX_OK) return s;
+  if (conv && G->h_ctrl->state.v[0] != EXIT_DONE)
+    return fail(SX_EHIP, "PageRank run ended in state %u", G->h_ctrl->state.v[0]);
   HIP_TRY(hipEventSynchronize(G->ev1));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, G->ev0, G->ev1));
-  fill_stats(G->h_ctrl, 2, ms, grid, p->ctx->wall_khz, stats);
+  fill_stats(G->h_ctrl, launches, ms, grid, p->ctx->wall_khz, stats);
   return SX_OK;
 }
 
@@ -1742,6 +1757,7 @@ extern "C" sx_status sx_kernel_info_get(sx_ctx *ctx, const char *name, sx_kernel
       {"kcore_seq", kcore_seq_kernel(), false},
       {"pagerank_fused", pagerank_kernel(), true},
       {"pagerank_until_stable", pagerank_kernel(true), true},
+      {"pagerank_push_tail", pagerank_push_kernel(), true},
       {"bp_fused", bp_kernel(), true},
       {"batch", batch_kernel(), true},
   };

@@ -37,8 +37,11 @@ hipError_t kcore_membership(int *core, int n, hipStream_t s);
 const void *kcore_seq_kernel();
 
 hipError_t pagerank_launch(const PrArgs &a, int grid, hipStream_t s);
-// conv: the kernel of the run to convergence
+// conv: the pull kernel of the run to convergence (launched after k_pr_init
+// by pagerank_launch); its push tail is a kernel of its own
 const void *pagerank_kernel(bool conv = false);
+hipError_t pagerank_push_launch(const PrArgs &a, int grid, hipStream_t s);
+const void *pagerank_push_kernel();
 
 hipError_t bp_launch(const BpArgs &a, int grid, hipStream_t s);
 const void *bp_kernel();
