@@ -104,6 +104,7 @@ struct sx_graph {
   bool reordered = false;
   int *d_inv = nullptr;
   std::vector<int> h_inv;
+  unsigned *d_xdist = nullptr;  // SSSP / WCC expansion record (TravArgs::xdist)
   void *state = nullptr;
   long long weight_sum = -1;  // sum of the arc weights, once SX_DELTA_AUTO needed it
   // where the lists of the next iteration sit after sx_run_iterations:
@@ -476,6 +477,7 @@ extern "C" sx_status sx_graph_load(sx_ctx *ctx, const sx_graph_desc *d, void *hi
   Work &w = G->w;
   TRY(work_alloc([&](void **p, size_t bytes) { return dalloc(G, p, bytes); }, n, m, !undirected,
                  kMaxGrid, true, w));
+  TRY(dalloc(G, (void **)&G->d_xdist, sizeof(unsigned) * (size_t)(n > 0 ? n : 1)));
   HTRY(hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), st));
   HTRY(hipHostMalloc((void **)&G->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
   HTRY(hipHostMalloc((void **)&G->h_ctrl2, sizeof(Ctrl), hipHostMallocDefault));
@@ -864,6 +866,7 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   a.src = src;
   a.mlp = ctx->d_mlp;
   a.wcc_inv = wcc && G->reordered ? G->d_inv : nullptr;
+  a.xdist = G->d_xdist;
   if (a.P.learned && !ctx->d_mlp) return fail(SX_ESTATE, "learned policy without loaded MLP");
   if (algo == ALG_SSSP && a.P.delta == SX_DELTA_AUTO) {
     sx_status s = auto_delta(G, st, &a.P.delta);
@@ -1208,6 +1211,8 @@ extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_
   snap.items.push_back({w.rec, sizeof(RecSlot) * NSLOTS});
   snap.items.push_back({d_out, sizeof(int) * (size_t)n});
   snap.items.push_back({w.stamp, sizeof(int) * (size_t)n});
+  // the expansion record: an arm's expansions must not make the replay skip
+  snap.items.push_back({G->d_xdist, sizeof(unsigned) * (size_t)n});
   snap.items.push_back({w.ctrl, sizeof(Ctrl)});
   for (auto &it : snap.items) {
     void *c = nullptr;
@@ -1630,6 +1635,8 @@ extern "C" sx_status sx_run_static(sx_program *p, const sx_graph_desc *d, int32_
     return SX_OK;
   };
   sx_status s = work_alloc(carve, d->n, d->m, !undirected, grid, false, G.w);
+  if (s != SX_OK) return s;
+  s = carve((void **)&G.d_xdist, sizeof(unsigned) * (size_t)std::max(d->n, 1));
   if (s != SX_OK) return s;
   if (used > kStaticScratchBytes)
     return fail(SX_EINVAL,

@@ -190,7 +190,9 @@ SX_DEV void raise_error(Ctrl *C, unsigned e) { store_relaxed(&C->error.v[0], e);
 // the carrying pass and as near by its visitor is both carried and expanded
 // (redundant, never lost).  The smallest distance set or carried in the
 // step goes to Ctrl::aux[(it+1) % 3], from which the next decision moves B.
-template <class Ops>
+constexpr unsigned kDedupMinList = 1u << 16;
+
+template <class Ops, bool kDedup = true>
 SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, const Ops &ops, int it,
                          const ViewRef &cur, const Totals &T, LdsTrav &lds,
                          unsigned B = 0xFFFFFFFFu) {
@@ -210,6 +212,33 @@ SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
       return v;
     } else {
       return buckets && (unsigned)v < (unsigned)g.n && ops.dist[v] >= B ? -1 : v;
+    }
+  };
+  // A listed vertex whose value equals the one its last expansion started
+  // from is skipped (reads as -1): that expansion recorded the value before
+  // relaxing any arc and read the source value of each arc afterwards, and
+  // values only fall, so every arc was relaxed with exactly this value.  A
+  // vertex improved while listed, before its own expansion, is expanded
+  // with the new value and listed again for the next step, where it is
+  // skipped (R-MAT s22 SSSP: a third of the expansions).  Only the small and
+  // medium visitors (one expander per vertex) record and skip; `writer` is
+  // the lane whose result the visitor uses.  Only steps with long lists do
+  // (kDedupMinList): the test puts a dependent load before each row's, which
+  // the thousands of short steps of a high-diameter graph would each pay
+  // (a record left stale by such a step only holds a value above the
+  // vertex's current one, so it never matches).  The batched kernel
+  // compiles it out (kDedup false): its spilling register budget would pay
+  // for it in every step.
+  const bool dedup = kDedup && !Ops::kVote && a.xdist && T.nf >= kDedupMinList;
+  auto fresh = [&](int v, bool writer) -> int {
+    if constexpr (Ops::kVote) {
+      return v;
+    } else {
+      if (!dedup || !writer || (unsigned)v >= (unsigned)g.n) return v;
+      const unsigned d = ops.dist[v];
+      if (a.xdist[v] == d) return -1;
+      a.xdist[v] = d;
+      return v;
     }
   };
   if constexpr (!Ops::kVote) {
@@ -269,11 +298,13 @@ SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   visit_med(g.n,
             [&](unsigned i) {
               const int v = cur.med(i);
-              return buckets ? __shfl(near(v), 0) : v;
+              if constexpr (Ops::kVote) return v;
+              if (!buckets && !dedup) return v;
+              return __shfl(fresh(near(v), lane_id() == 0), 0);
             },
             T.cnt[BIN_MED], g.off, g.idx, op, gw, nw);
-  visit_small(g.n, [&](unsigned i) { return near(cur.small(i)); }, T.cnt[BIN_SMALL], g.off, g.idx, op,
-              gw, nw, lds.small[wave_in_wg()]);
+  visit_small(g.n, [&](unsigned i) { return fresh(near(cur.small(i)), true); }, T.cnt[BIN_SMALL], g.off,
+              g.idx, op, gw, nw, lds.small[wave_in_wg()]);
   bins_end(lds.bins, st, a.w.rec + ((it + 1) % 3), vg.bid);   // ends with a barrier
   if (record) {
     const unsigned m = wave_min_u(lowest);
@@ -651,7 +682,7 @@ SX_DEV bool entry_done(Ctrl *C) {
 // (EXIT_SWITCH) so that the host launches the other kernel; kDir 2: both
 // directions, switching in place (all fusion and the batched kernel).
 // Returns the exit reason.
-template <class Ops, int kDir>
+template <class Ops, int kDir, bool kDedup = true>
 SX_DEV int run_loop(const VGrid &vg, const TravArgs &a, GridBarrier &bar, LdsTrav &lds,
                     LdsPolicy &pol, RunState &s, bool &pulling, bool &rebuilt) {
   constexpr bool both = kDir == 2;
@@ -685,7 +716,7 @@ SX_DEV int run_loop(const VGrid &vg, const TravArgs &a, GridBarrier &bar, LdsTra
       } else {
         if (vg.bid == 0 && threadIdx.x == 0) atomic_add_u32(&C->stats.v[6], 1u);
         Ops ops = make_ops<Ops>(a, s.it);
-        push_phase(vg, a, s.P, ops, s.it, ref, T, lds);
+        push_phase<Ops, kDedup>(vg, a, s.P, ops, s.it, ref, T, lds);
         if (!bar.sync()) return EXIT_ERROR;
         T = make_view(vg, a, (s.it + 1) % 3, (s.it + 1) & 1, lds, ref);
         Decision d = decide<Ops>(a, s, false, T, &pol, vg.bid == 0);
@@ -992,9 +1023,11 @@ SX_DEV void init_state(const VGrid &vg, const TravArgs &a, bool sssp, bool wcc =
       const int at = a.wcc_inv ? a.wcc_inv[v] : (int)v;
       a.state_i[at] = (int)v;
       a.w.stamp[at] = 0;
+      if (a.xdist) a.xdist[v] = 0xFFFFFFFFu;
     } else if (sssp) {
       ((unsigned *)a.state_i)[v] = v == a.src ? 0u : 0xFFFFFFFFu;
       a.w.stamp[v] = v == a.src ? 0 : -1;
+      if (a.xdist) a.xdist[v] = 0xFFFFFFFFu;
     } else {
       a.state_i[v] = v == a.src ? 0 : -1;
     }
@@ -1070,7 +1103,7 @@ SX_DEV bool batch_query(const VGrid &vg, const TravArgs &a, GridBarrier &bar, Ld
   s.ps.reached = 0;
   s.P = a.P;
   bool pulling = a.P.direction == 2, rebuilt = false;
-  const int r = run_loop<Ops, 2>(vg, a, bar, lds, pol, s, pulling, rebuilt);
+  const int r = run_loop<Ops, 2, false>(vg, a, bar, lds, pol, s, pulling, rebuilt);
   finish(vg, a.w.ctrl, r, s, false);
   if (r == EXIT_ERROR) return false;
   return bar.sync();
@@ -1092,6 +1125,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   a.P = b.P;
   a.mlp = b.mlp;
   a.wcc_inv = nullptr;
+  a.xdist = nullptr;   // no expansion record in batches
   load_policy(a, pol);
   for (;;) {
     if (vg.bid == 0 && threadIdx.x == 0)

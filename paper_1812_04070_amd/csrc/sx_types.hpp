@@ -140,6 +140,9 @@ struct TravArgs {
   // label v (its id in the caller's numbering), so that the minimum label of
   // a component is its smallest original id.  NULL: label = own id.
   const int *wcc_inv;
+  // SSSP / WCC: the value each vertex's last expansion started from (~0u:
+  // none; see push_phase).  NULL: no record, every listed vertex expands.
+  unsigned *xdist;
 };
 
 // Batched queries (see k_batch).

@@ -199,3 +199,37 @@ def test_kcore_directed_pull(engine):
         announce(f"kcore rmat16d {name}")
         c, _ = run(engine, g, sx.SX_KCORE, -1, pol)
         np.testing.assert_array_equal(c, ref)
+
+
+def test_expansion_record_long_lists(engine):
+    """Steps whose lists hold 2^16 vertices or more skip a listed vertex whose
+    distance (label) equals the one its last expansion started from.  R-MAT
+    s18 reaches such lists: SSSP in every arrangement and from two sources
+    in a row on one loaded graph (the second run must not meet the first
+    run's record), a directed SSSP, and WCC; all identical to the oracle."""
+    g = gen.rmat(18, seed=21, weights=(1, 64))
+    dg = engine.load(g)
+    deg = np.diff(g.offsets)
+    srcs = [gen.max_degree_vertex(g), int(np.nonzero(deg == 1)[0][0])]
+    pols = [("auto", sx.Policy()), ("push-only", sx.Policy(direction=sx.SX_DIR_PUSH)),
+            ("ballot", sx.Policy(direction=sx.SX_DIR_PUSH, filter=sx.SX_FILTER_BALLOT)),
+            ("fused", sx.Policy(fused=sx.SX_FUSED)), ("fused-all", sx.Policy(fused=sx.SX_FUSED_ALL)),
+            ("unfused", sx.Policy(fused=sx.SX_UNFUSED))]
+    long_list = False
+    for src in srcs:
+        ref = oracle.sssp_g(g, src)
+        for name, pol in pols:
+            announce(f"expansion record sssp src={src} {name}")
+            x, st = run(engine, g, sx.SX_SSSP, src, pol, dg=dg)
+            np.testing.assert_array_equal(x, ref)
+            long_list = long_list or st["vertex_expansions"] >= (1 << 16)
+    assert long_list
+    ref_w = oracle.wcc_g(g)
+    for name, pol in pols:
+        announce(f"expansion record wcc {name}")
+        np.testing.assert_array_equal(run(engine, g, sx.SX_WCC, -1, pol, dg=dg)[0], ref_w)
+    dg.close()
+    gd = gen.rmat(18, seed=22, weights=(1, 64), directed=True)
+    src = gen.max_degree_vertex(gd)
+    announce("expansion record directed sssp")
+    np.testing.assert_array_equal(run(engine, gd, sx.SX_SSSP, src)[0], oracle.sssp_g(gd, src))
