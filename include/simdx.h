@@ -280,7 +280,7 @@ sx_status sx_run(sx_program *p, const sx_graph *g, int32_t source, void *d_out,
  * same graph loaded with SX_DEVICE_PTRS.  The call allocates nothing: the
  * context's pinned control-block mirrors and events come from
  * sx_ctx_create.
- * Size limit: the workspace takes about 57 n + 32 KiB G + 16 (G + 1)
+ * Size limit: the workspace takes about 61 n + 32 KiB G + 16 (G + 1)
  * (m / 2048 + 1) + 300 KiB bytes for a grid of G workgroups (the
  * program's grid, at most policy grid_wgs when that is set; 512 by default
  * on MI355X); a graph that needs more than 256 MiB fails with SX_EINVAL and

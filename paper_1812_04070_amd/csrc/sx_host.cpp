@@ -286,7 +286,6 @@ static void free_graph(sx_graph *G) {
   delete G;
 }
 
-static const int kChunk = 4 * kBlock;  // arcs per large-bin item
 
 // Worklist storage for grids of up to `gmax` workgroups (regions: workgroup b
 // of G owns 1/G of every bin array).  The sizes make every list a ballot scan
@@ -317,6 +316,12 @@ static Sizing work_sizing(long long n, long long m, bool directed, int gmax) {
 
 // Allocate a workspace through `al(void **, bytes)`; `full` adds the k-core
 // and PageRank arrays.
+// Entries of the expansion record (TravArgs::xdist): per vertex, then per
+// large-bin chunk.
+static size_t xrec_entries(long long n, long long m) {
+  return 2 * (size_t)std::max<long long>(n, 0) + (size_t)(std::max<long long>(m, 0) / kChunk) + 2;
+}
+
 template <class Alloc>
 static sx_status work_alloc(Alloc al, long long n, long long m, bool directed, int gmax, bool full,
                             Work &w) {
@@ -477,7 +482,7 @@ extern "C" sx_status sx_graph_load(sx_ctx *ctx, const sx_graph_desc *d, void *hi
   Work &w = G->w;
   TRY(work_alloc([&](void **p, size_t bytes) { return dalloc(G, p, bytes); }, n, m, !undirected,
                  kMaxGrid, true, w));
-  TRY(dalloc(G, (void **)&G->d_xdist, sizeof(unsigned) * (size_t)(n > 0 ? n : 1)));
+  TRY(dalloc(G, (void **)&G->d_xdist, sizeof(unsigned) * xrec_entries(n, m)));
   HTRY(hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), st));
   HTRY(hipHostMalloc((void **)&G->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
   HTRY(hipHostMalloc((void **)&G->h_ctrl2, sizeof(Ctrl), hipHostMallocDefault));
@@ -1212,7 +1217,7 @@ extern "C" sx_status sx_policy_collect(sx_program *p, const sx_graph *gc, int32_
   snap.items.push_back({d_out, sizeof(int) * (size_t)n});
   snap.items.push_back({w.stamp, sizeof(int) * (size_t)n});
   // the expansion record: an arm's expansions must not make the replay skip
-  snap.items.push_back({G->d_xdist, sizeof(unsigned) * (size_t)n});
+  snap.items.push_back({G->d_xdist, sizeof(unsigned) * xrec_entries(n, G->g.m)});
   snap.items.push_back({w.ctrl, sizeof(Ctrl)});
   for (auto &it : snap.items) {
     void *c = nullptr;
@@ -1636,7 +1641,7 @@ extern "C" sx_status sx_run_static(sx_program *p, const sx_graph_desc *d, int32_
   };
   sx_status s = work_alloc(carve, d->n, d->m, !undirected, grid, false, G.w);
   if (s != SX_OK) return s;
-  s = carve((void **)&G.d_xdist, sizeof(unsigned) * (size_t)std::max(d->n, 1));
+  s = carve((void **)&G.d_xdist, sizeof(unsigned) * xrec_entries(d->n, d->m));
   if (s != SX_OK) return s;
   if (used > kStaticScratchBytes)
     return fail(SX_EINVAL,

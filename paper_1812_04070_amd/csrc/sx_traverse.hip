@@ -174,6 +174,7 @@ struct LdsTrav {
   long long red[kWaves];
   unsigned cnt[kWaves];
   unsigned sq[33];                 // the run-state line and the error word
+  unsigned skip;                   // push step: the current large item is skipped
 };
 
 SX_DEV void raise_error(Ctrl *C, unsigned e) { store_relaxed(&C->error.v[0], e); }
@@ -287,12 +288,38 @@ SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   const unsigned nw = vg.nb * kWaves;
   // (the medium and large visitors call their accessor with every lane of a
   // wavefront on one entry: lane 0's reading decides for the wavefront)
+  // The large bin records per chunk (each chunk has one expanding workgroup
+  // per step): thread 0 takes the decision for the whole workgroup between
+  // two barriers, so that the record is written before any wavefront reads
+  // the source value and every wavefront follows it.  Not with buckets
+  // (whose near / far test each wavefront takes for itself).
+  const bool cdedup = dedup && !buckets && P.chunk == kChunk;
   visit_large(vg, g.n,
               [&](unsigned i) {
-                const unsigned long long x = cur.large(i);
-                if (!buckets) return x;
-                const int far = __shfl(near((int)(x & 0xffffffffu)) < 0 ? 1 : 0, 0);
-                return far ? (x | 0xffffffffull) : x;
+                unsigned long long x = cur.large(i);
+                if (buckets) {
+                  const int far = __shfl(near((int)(x & 0xffffffffu)) < 0 ? 1 : 0, 0);
+                  if (far) x |= 0xffffffffull;
+                }
+                if constexpr (!Ops::kVote) {
+                  if (cdedup) {
+                    __syncthreads();   // every wavefront has read the last item's decision
+                    if (threadIdx.x == 0) {
+                      unsigned sk = 0;
+                      const int v = (int)(x & 0xffffffffu);
+                      if ((unsigned)v < (unsigned)g.n) {
+                        const unsigned d = ops.dist[v];
+                        unsigned *rec = a.xdist + g.n + (size_t)(g.off[v] / kChunk) + (size_t)(x >> 32) + (size_t)v;
+                        if (*rec == d) sk = 1;
+                        else *rec = d;
+                      }
+                      lds.skip = sk;
+                    }
+                    __syncthreads();
+                    if (lds.skip) x |= 0xffffffffull;
+                  }
+                }
+                return x;
               },
               T.cnt[BIN_LARGE], g.off, g.idx, P.chunk, op);
   visit_med(g.n,
@@ -1018,16 +1045,18 @@ __global__ void k_seq_start(Ctrl *C, unsigned pull_first, unsigned all_active) {
 SX_DEV void init_state(const VGrid &vg, const TravArgs &a, bool sssp, bool wcc = false) {
   const int n = a.g.n;
   const long long tid = (long long)vg.bid * kBlock + threadIdx.x, nt = (long long)vg.nb * kBlock;
+  if (a.xdist && (sssp || wcc)) {
+    const long long nx = 2ll * n + a.g.m / kChunk + 2;
+    for (long long i = tid; i < nx; i += nt) a.xdist[i] = 0xFFFFFFFFu;
+  }
   for (long long v = tid; v < n; v += nt) {
     if (wcc) {
       const int at = a.wcc_inv ? a.wcc_inv[v] : (int)v;
       a.state_i[at] = (int)v;
       a.w.stamp[at] = 0;
-      if (a.xdist) a.xdist[v] = 0xFFFFFFFFu;
     } else if (sssp) {
       ((unsigned *)a.state_i)[v] = v == a.src ? 0u : 0xFFFFFFFFu;
       a.w.stamp[v] = v == a.src ? 0 : -1;
-      if (a.xdist) a.xdist[v] = 0xFFFFFFFFu;
     } else {
       a.state_i[v] = v == a.src ? 0 : -1;
     }

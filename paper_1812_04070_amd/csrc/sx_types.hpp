@@ -8,6 +8,7 @@
 namespace sx {
 
 constexpr int kBlock = 512;              // threads per workgroup (8 wavefronts)
+constexpr int kChunk = 4 * kBlock;       // arcs per large-bin item (traversals)
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxGrid = 1024;           // upper bound on workgroups per grid
 // watchdog of the software global barrier: how long one wait may last, in
@@ -140,8 +141,11 @@ struct TravArgs {
   // label v (its id in the caller's numbering), so that the minimum label of
   // a component is its smallest original id.  NULL: label = own id.
   const int *wcc_inv;
-  // SSSP / WCC: the value each vertex's last expansion started from (~0u:
-  // none; see push_phase).  NULL: no record, every listed vertex expands.
+  // SSSP / WCC expansion record (see push_phase): [0, n) the value each
+  // vertex's last small- or medium-bin expansion started from, then per
+  // large-bin chunk the same, chunk c of vertex v at n + off[v] / kChunk +
+  // c + v (unique; n + m / kChunk + 2 entries); ~0u: none.  NULL: no
+  // record, every listed vertex expands.
   unsigned *xdist;
 };
 
