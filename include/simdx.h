@@ -228,6 +228,16 @@ typedef struct {
   int32_t watchdog_us;   /* how long one wait at the software global barrier
                             may last before the run fails with SX_EDEADLOCK,
                             in microseconds of wall-clock time; 0 = 2 s      */
+  int32_t kcore_tail;    /* k-core decomposition (sequenced arrangement): once
+                            a level ends with at most this many vertices
+                            left, the rest of the decomposition runs in one
+                            workgroup whose LDS holds their degrees (the
+                            alive subgraph compacted first); at most 36,864
+                            (the most that fits).  0 = 16,384 vertices whose
+                            rows, arcs to deleted vertices included, hold
+                            at most 2^22 arcs (one CU's LDS atomics are
+                            slower than the grid on more work); negative =
+                            never.  Results are identical either way.        */
 } sx_policy;
 
 sx_status sx_program_set_policy(sx_program *p, const sx_policy *pol);
@@ -378,6 +388,7 @@ sx_status sx_batch_autotune(sx_ctx *ctx, const sx_query *queries, int32_t nq, co
  * graphs of 2^25 arcs or more, built for three workgroups per CU),
  * "bfs_push_step", "bfs_pull_step", "sssp_push_step",
  * "sssp_pull_step", "ballot_scan", "pull_scan", "kcore_fused", "kcore_seq",
+ * "kcore_tail" (the peel of the one-workgroup tail: block 1024, grid 1),
  * "pagerank_fused", "pagerank_until_stable" (pr_tol > 0: its pull kernel),
  * "pagerank_push_tail" (its push kernel), "bp_fused", "batch".
  * Errors: SX_EINVAL (unknown name), SX_EHIP. */

@@ -72,7 +72,7 @@ class sx_policy(ctypes.Structure):
                 ("bin_small", ctypes.c_int32), ("bin_large", ctypes.c_int32),
                 ("online_cap", ctypes.c_int32), ("fused", ctypes.c_int32),
                 ("policy", ctypes.c_int32), ("grid_wgs", ctypes.c_int32),
-                ("watchdog_us", ctypes.c_int32)]
+                ("watchdog_us", ctypes.c_int32), ("kcore_tail", ctypes.c_int32)]
 
 
 class sx_run_stats(ctypes.Structure):
@@ -368,10 +368,12 @@ class Policy:
     policy: int = SX_POLICY_HEURISTIC
     grid_wgs: int = 0
     watchdog_us: int = 0
+    kcore_tail: int = 0
 
     def c(self) -> sx_policy:
         return sx_policy(self.direction, self.filter, self.bin_small, self.bin_large,
-                         self.online_cap, self.fused, self.policy, self.grid_wgs, self.watchdog_us)
+                         self.online_cap, self.fused, self.policy, self.grid_wgs, self.watchdog_us,
+                         self.kcore_tail)
 
 
 OUT_DTYPES = {SX_BFS: "int32", SX_SSSP: "uint32", SX_KCORE: "int32", SX_PAGERANK: "float32",

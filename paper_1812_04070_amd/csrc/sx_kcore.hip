@@ -464,6 +464,7 @@ struct KState {
   int k, s, j;
   bool from_scan;
   unsigned long long alive_arcs;
+  unsigned alive_n = 0;           // vertices of the alive list of the last scan
 };
 
 // What follows a scan: 1 peel, 0 scan again at a higher level (k updated),
@@ -471,6 +472,7 @@ struct KState {
 SX_DEV int after_scan(const VGrid &vg, const KArgs &a, KState &q, const Totals &T,
                       const Totals &TA, LdsK &lds) {
   q.alive_arcs = TA.mf;
+  q.alive_n = TA.nf;
   // no survivors: the frontier's core numbers are set (by the scan), and
   // nobody is left to receive its decrements
   if (TA.nf == 0) return -1;
@@ -588,8 +590,9 @@ __global__ void __launch_bounds__(kBlock) k_kcore_fused(KArgs a) {
 // decision taken at the start of the launch after it; launch L reads
 // Ctrl::seq[L & 1] and writes seq[(L+1) & 1]: [0] phase [1] k [2] scans [3]
 // peel steps [4] decision due (1 after a scan, 2 after a peel) [5] the list
-// of the next peel comes from a scan [6,7] alive arcs [30] L + 1 when
-// launch L (a peel) appended to the next list.
+// of the next peel comes from a scan [6,7] alive arcs [8] alive vertices
+// (both of the last scan) [30] L + 1 when launch L (a peel) appended to the
+// next list.
 enum : unsigned { KP_SCAN = 0, KP_PEEL = 1, KP_DONE = 6, KP_ERROR = 7, KP_LIMIT = 8 };
 
 // Returns whether the launch ran a phase of an active run.
@@ -606,6 +609,7 @@ SX_DEV bool kcore_seq_body(const KArgs &a, unsigned L, LdsK &lds) {
   unsigned due = lds.sq[4];
   q.from_scan = lds.sq[5] != 0;
   q.alive_arcs = (unsigned long long)lds.sq[6] | ((unsigned long long)lds.sq[7] << 32);
+  q.alive_n = lds.sq[8];
   const bool lead = vg.bid == 0 && threadIdx.x == 0;
   auto save = [&](unsigned ph) {
     if (lead) {
@@ -616,6 +620,7 @@ SX_DEV bool kcore_seq_body(const KArgs &a, unsigned L, LdsK &lds) {
       store_relaxed(&out.v[4], due);
       store_relaxed(&out.v[5], q.from_scan ? 1u : 0u);
       store_relaxed((unsigned long long *)&out.v[6], q.alive_arcs);
+      store_relaxed(&out.v[8], q.alive_n);
     }
   };
   if (phase >= KP_DONE) { save(phase); return false; }
@@ -625,6 +630,9 @@ SX_DEV bool kcore_seq_body(const KArgs &a, unsigned L, LdsK &lds) {
   ViewRef ref;
   Totals V;
   bool have = false, pull = false;
+  // the scan this launch may run starts a level with nothing pending (the
+  // run's first scan, or the previous level exhausted): the tail may take over
+  bool boundary = due == 0 && phase == KP_SCAN;
   if (due == 1) {
     V = kview(vg, a.w, SLOT_SCAN, regions(a.w, q.j & 1, vg.nb), lds, ref);
     have = true;
@@ -638,7 +646,7 @@ SX_DEV bool kcore_seq_body(const KArgs &a, unsigned L, LdsK &lds) {
     const int r = after_scan(vg, a, q, V, TA, lds);
     due = 0;
     if (r < 0) { save(KP_DONE); return true; }
-    if (r == 0) phase = KP_SCAN;
+    if (r == 0) { phase = KP_SCAN; boundary = true; }
     else { phase = KP_PEEL; q.from_scan = true; pull = pull_step(q, V, a.P); }
   } else if (due == 2 && lds.sq[30] != L) {
     // the peel appended nothing (no workgroup stamped the line): next level
@@ -648,15 +656,32 @@ SX_DEV bool kcore_seq_body(const KArgs &a, unsigned L, LdsK &lds) {
     if (a.P.kfix) { save(KP_DONE); return true; }
     ++q.k;
     phase = KP_SCAN;
+    boundary = true;
   } else if (due == 2) {
     V = kview(vg, a.w, q.j % 3, regions(a.w, q.j & 1, vg.nb), lds, ref);
     have = true;
     q.from_scan = false;
     due = 0;
     if (V.nf == 0 && a.P.kfix) { save(KP_DONE); return true; }
-    if (V.nf == 0) { ++q.k; phase = KP_SCAN; }
+    if (V.nf == 0) { ++q.k; phase = KP_SCAN; boundary = true; }
     else if (V.ovf || a.P.filter == 2) phase = KP_SCAN;
     else { phase = KP_PEEL; pull = pull_step(q, V, a.P); }
+  }
+  if (phase == KP_SCAN && boundary && a.P.ktail > 0) {
+    // few vertices and arcs left (the last scan's survivors bound them; the
+    // whole graph before the first scan) and their arcs fit the tail's
+    // rows: hand the rest to the one-workgroup tail
+    const bool first = q.s == 0;
+    const unsigned long long an = first ? (unsigned long long)a.g.n : q.alive_n;
+    const unsigned long long aa = first ? (unsigned long long)a.g.m * (a.g.directed ? 2 : 1) : q.alive_arcs;
+    if (an <= (unsigned long long)a.P.ktail && aa <= a.P.ktail_arcs && aa + 8ull * an <= 4ull * a.w.tot_l) {
+      if (lead) {
+        store_relaxed(&C->aux.v[KT_K], (unsigned)q.k);
+        store_relaxed(&C->aux.v[KT_N], 0u);
+      }
+      save(KP_TAIL);
+      return true;
+    }
   }
   if (phase == KP_SCAN) {
     kscan_phase(vg, a, q, lds);

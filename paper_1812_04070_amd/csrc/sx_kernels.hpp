@@ -35,6 +35,12 @@ hipError_t kcore_seq_launch(const KArgs &a, unsigned L, int grid, hipStream_t s,
 // core[v] = 1 where v survived (core[v] == -1, fixed-k membership), else 0
 hipError_t kcore_membership(int *core, int n, hipStream_t s);
 const void *kcore_seq_kernel();
+// the one-workgroup tail of a decomposition the sequenced loop handed over
+// (state KP_TAIL; Ctrl::aux[KT_K] the level to go on with, aux[KT_N] zero)
+enum : unsigned { KP_TAIL = 9 };
+enum { KT_K = 24, KT_N = 25 };
+hipError_t kcore_tail_launch(const KArgs &a, int grid, hipStream_t s);
+const void *kcore_tail_kernel();
 
 hipError_t pagerank_launch(const PrArgs &a, int grid, hipStream_t s);
 // conv: the pull kernel of the run to convergence (launched after k_pr_init

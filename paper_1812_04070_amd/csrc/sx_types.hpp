@@ -9,6 +9,12 @@ namespace sx {
 
 constexpr int kBlock = 512;              // threads per workgroup (8 wavefronts)
 constexpr int kChunk = 4 * kBlock;       // arcs per large-bin item (traversals)
+constexpr int kTailMax = 36864;          // k-core tail: vertices whose degrees
+                                         // one workgroup's LDS holds
+constexpr int kTailThreads = 1024;       // and the workgroup's threads
+constexpr int kTailDefault = 16384;      // the tail's default hand-over: this
+constexpr unsigned long long kTailDefaultArcs = 1ull << 22;  // many vertices
+                                         // and arcs at most
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxGrid = 1024;           // upper bound on workgroups per grid
 // watchdog of the software global barrier: how long one wait may last, in
@@ -127,6 +133,11 @@ struct Params {
   int delta_after;              // iterations run before the buckets engage
   int kfix;                     // k-core: 0 full decomposition, k > 0
                                 // membership in the k-core only
+  int ktail;                    // k-core: hand the rest of the decomposition
+                                // to the one-workgroup tail once a level ends
+                                // with at most this many vertices (0: never)
+  unsigned long long ktail_arcs;  // and with their rows (arcs to deleted
+                                  // vertices included) at most this long
   unsigned long long watchdog;  // barrier wait budget (wall-clock ticks)
 };
 

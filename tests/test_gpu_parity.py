@@ -7,6 +7,8 @@ integer output: the method's choices change the schedule, never the result.
 """
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -65,11 +67,15 @@ def test_bfs_sssp_small(engine, name, make, arm):
 
 @pytest.mark.parametrize("name,make", SMALL_GRAPHS, ids=[s[0] for s in SMALL_GRAPHS])
 def test_kcore_small(engine, name, make):
+    """Graphs this small go to the one-workgroup tail at once (kcore_tail
+    default); with kcore_tail = -1 every arm peels on the grid."""
     g = make()
+    ref = oracle.kcore_g(g)
     for arm in ARMS:
-        announce(f"kcore {name} {arm[0]}")
-        c, _ = run(engine, g, sx.SX_KCORE, -1, arm[1])
-        np.testing.assert_array_equal(c, oracle.kcore_g(g))
+        for tail in (0, -1):
+            announce(f"kcore {name} {arm[0]} tail={tail}")
+            c, _ = run(engine, g, sx.SX_KCORE, -1, dataclasses.replace(arm[1], kcore_tail=tail))
+            np.testing.assert_array_equal(c, ref)
 
 
 def test_sources_and_isolated(engine):
@@ -179,10 +185,12 @@ def test_kcore_pull_steps(engine, scale):
     g = gen.rmat(scale, seed=2)
     ref = oracle.kcore_g(g)
     dg = engine.load(g)
-    for name, pol in [("auto", sx.Policy()), ("auto-fused", sx.Policy(fused=sx.SX_FUSED)),
-                      ("pull", sx.Policy(direction=sx.SX_DIR_PULL)),
+    # the grid peels every level (no one-workgroup tail), where the pull
+    # steps of the dense last levels are
+    for name, pol in [("auto", sx.Policy(kcore_tail=-1)), ("auto-fused", sx.Policy(fused=sx.SX_FUSED)),
+                      ("pull", sx.Policy(direction=sx.SX_DIR_PULL, kcore_tail=-1)),
                       ("push-fused", sx.Policy(fused=sx.SX_FUSED, direction=sx.SX_DIR_PUSH)),
-                      ("ballot", sx.Policy(filter=sx.SX_FILTER_BALLOT))]:
+                      ("ballot", sx.Policy(filter=sx.SX_FILTER_BALLOT, kcore_tail=-1))]:
         announce(f"kcore rmat{scale} {name}")
         c, st = run(engine, g, sx.SX_KCORE, -1, pol, dg=dg)
         np.testing.assert_array_equal(c, ref)
@@ -194,7 +202,8 @@ def test_kcore_pull_steps(engine, scale):
 def test_kcore_directed_pull(engine):
     g = gen.rmat(16, seed=4, directed=True)
     ref = oracle.kcore_g(g)
-    for name, pol in [("auto", sx.Policy()), ("pull", sx.Policy(direction=sx.SX_DIR_PULL)),
+    for name, pol in [("auto", sx.Policy()), ("auto-grid", sx.Policy(kcore_tail=-1)),
+                      ("pull", sx.Policy(direction=sx.SX_DIR_PULL, kcore_tail=-1)),
                       ("fused", sx.Policy(fused=sx.SX_FUSED))]:
         announce(f"kcore rmat16d {name}")
         c, _ = run(engine, g, sx.SX_KCORE, -1, pol)
@@ -233,3 +242,23 @@ def test_expansion_record_long_lists(engine):
     src = gen.max_degree_vertex(gd)
     announce("expansion record directed sssp")
     np.testing.assert_array_equal(run(engine, gd, sx.SX_SSSP, src)[0], oracle.sssp_g(gd, src))
+
+
+@pytest.mark.parametrize("case", ["rmat16", "rmat18", "rmat16d", "grid-150", "er-20000"])
+def test_kcore_tail(engine, case):
+    """The one-workgroup tail of the decomposition: taken over at several
+    sizes (from the first level on for the default on small graphs, at a
+    few hundred or thousand vertices, never), on undirected and directed
+    R-MAT, a grid and a sparse random graph; every result equal to the
+    oracle's."""
+    g = {"rmat16": lambda: gen.rmat(16, seed=31), "rmat18": lambda: gen.rmat(18, seed=32),
+         "rmat16d": lambda: gen.rmat(16, seed=33, directed=True),
+         "grid-150": lambda: gen.grid(150, 0.1, seed=34),
+         "er-20000": lambda: gen.random_graph(20000, 0.0008, seed=35)}[case]()
+    ref = oracle.kcore_g(g)
+    dg = engine.load(g)
+    for tail in (0, 4096, 300, 1, -1):
+        announce(f"kcore tail {case} kcore_tail={tail}")
+        c, st = run(engine, g, sx.SX_KCORE, -1, sx.Policy(kcore_tail=tail), dg=dg)
+        np.testing.assert_array_equal(c, ref)
+    dg.close()
