@@ -652,6 +652,8 @@ static sx_status ctrl_error(const Ctrl *c) {
   if (c->error.v[0] == SX_ERR_OVERFLOW) return fail(SX_EOVERFLOW, "distance reached 0xFFFFFFFF");
   if (c->error.v[0] == SX_ERR_CAPACITY)
     return fail(SX_EHIP, "a scanned worklist exceeded its regions (engine bug)");
+  if (c->error.v[0] == SX_ERR_TAIL)
+    return fail(SX_EHIP, "the k-core tail's compacted rows disagree with the degrees (engine bug)");
   if (c->error.v[0] == SX_ERR_INPUT)
     return fail(SX_EINVAL, "an input value is outside its domain (belief-propagation prior not in (0, 1))");
   if (c->error.v[0]) return fail(SX_EHIP, "device error %u", c->error.v[0]);

@@ -26,7 +26,7 @@
 // alive neighbour arcs (every deleted neighbour lowered it once, the peel
 // steps' skipped decrements only concern vertices deleted in that level),
 // so the rows hold deg[v] entries; the fill checks this and raises
-// SX_ERR_CAPACITY rather than write past a row.  The buffers are the
+// SX_ERR_TAIL rather than write past a row.  The buffers are the
 // frontier regions and the PageRank contributions, idle in a k-core run
 // from the hand-over on.
 #include "sx_frontier.hpp"
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kTailThreads) k_ktail_offsets(KArgs a) {
   Ctrl *C = a.w.ctrl;
   const unsigned N = load_relaxed(&C->aux.v[KT_N]);
   if (N > (unsigned)kTailMax) {
-    if (threadIdx.x == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
+    if (threadIdx.x == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_TAIL);
     return;
   }
   // thread t takes the contiguous ids [t * per, (t + 1) * per)
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kTailThreads) k_ktail_offsets(KArgs a) {
   unsigned long long ra = tail_scan(sa, sh, ta);
   unsigned long long rw = tail_scan(sw, sh, tw);
   if (ta > b.cap || ta >= 0xFFFFFFF0ull || tw >= 0xFFFFFFF0ull) {
-    if (threadIdx.x == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
+    if (threadIdx.x == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_TAIL);
     return;
   }
   for (unsigned i = i0; i < i1; ++i) {
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(kBlock) k_ktail_fill(KArgs a) {
     const unsigned d = (unsigned)a.w.deg[v];
     if (base + cnt > d) {
       // more alive neighbours than the degree says: the rows would overlap
-      if (lane == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
+      if (lane == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_TAIL);
       continue;
     }
     unsigned pos = base;
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(kTailThreads) k_ktail_peel(KArgs a) {
   for (unsigned i = threadIdx.x; i < N; i += kTailThreads) {
     const unsigned d = (unsigned)a.w.deg[b.gid[i]];
     dg[i] = d;
-    if (b.fill[i] != d) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
+    if (b.fill[i] != d) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_TAIL);
   }
   __syncthreads();
   if (load_relaxed(&C->error.v[0])) return;
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(kTailThreads) k_ktail_peel(KArgs a) {
   const uint4 *arcs4 = (const uint4 *)b.arcs;
   while (left > 0) {
     if (rounds > 4u * N + 64u) {   // every round deletes a vertex or raises k past a degree
-      if (threadIdx.x == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_CAPACITY);
+      if (threadIdx.x == 0) store_relaxed(&C->error.v[0], (unsigned)SX_ERR_TAIL);
       return;
     }
     ++rounds;

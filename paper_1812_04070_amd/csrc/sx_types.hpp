@@ -26,8 +26,9 @@ constexpr int kStatLines = 64;           // statistics spread over 64 lines
 // (the host sizes them so that this cannot happen)
 // SX_ERR_INPUT: an input value outside its domain (a belief-propagation
 // prior not in (0, 1))
+// SX_ERR_TAIL: the k-core tail's compacted rows disagree with the degrees
 enum : unsigned { SX_ERR_NONE = 0, SX_ERR_DEADLOCK = 1, SX_ERR_OVERFLOW = 2, SX_ERR_CAPACITY = 3,
-                  SX_ERR_INPUT = 4 };
+                  SX_ERR_INPUT = 4, SX_ERR_TAIL = 5 };
 
 // kernel exit reasons written to Ctrl::state
 enum : int { EXIT_NONE = 0, EXIT_DONE = 1, EXIT_SWITCH = 2, EXIT_ERROR = 3, EXIT_LIMIT = 4 };

@@ -262,3 +262,23 @@ def test_kcore_tail(engine, case):
         c, st = run(engine, g, sx.SX_KCORE, -1, sx.Policy(kcore_tail=tail), dg=dg)
         np.testing.assert_array_equal(c, ref)
     dg.close()
+
+
+def test_kcore_multigraph(engine):
+    """Parallel arcs count once each in a degree (the oracle's definition
+    too): every arc of R-MAT s12 doubled.  The one-workgroup tail sizes its
+    rows by the current degree, parallel arcs included, and must agree with
+    the grid and the oracle."""
+    import dataclasses as dc
+    g = gen.rmat(12, seed=41)
+    deg = np.diff(g.offsets)
+    off2 = (2 * g.offsets).astype(np.int32)
+    idx2 = np.repeat(g.indices, 2).astype(np.int32)
+    mg = dc.replace(g, offsets=off2, indices=idx2, name="rmat12-doubled")
+    assert mg.m == 2 * g.m and np.array_equal(np.diff(mg.offsets), 2 * deg)
+    ref = oracle.kcore_g(mg)
+    assert np.array_equal(ref, 2 * oracle.kcore_g(g))   # doubling every arc doubles every core
+    for tail in (0, 2000, -1):
+        announce(f"kcore multigraph kcore_tail={tail}")
+        c, _ = run(engine, mg, sx.SX_KCORE, -1, sx.Policy(kcore_tail=tail))
+        np.testing.assert_array_equal(c, ref)
