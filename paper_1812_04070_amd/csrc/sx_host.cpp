@@ -614,11 +614,6 @@ static Params make_params(const sx_program *p, const sx_graph *G, int grid) {
   P.learned = pol.policy == SX_POLICY_LEARNED ? 1 : 0;
   P.bins_fixed = (pol.bin_small > 0 || pol.bin_large > 0) ? 1 : 0;
   P.kfix = p->ap.algo == SX_KCORE ? p->ap.kcore_k : 0;
-  // the expansion record pays where a listed vertex is often improved
-  // again within its own step before its expansion (R-MAT s22: a third of
-  // the expansions skipped); on sparse graphs (4096^2 grid, unbucketed
-  // SSSP: no expansion skipped, 15 % slower) it only adds a dependent load
-  P.xrec = G && G->g.m >= 8ll * G->g.n ? 1 : 0;
   // the one-workgroup tail pays only once little work is left: one CU's LDS
   // atomics take the decrements the grid spreads over all CUs (R-MAT s22
   // from 35,827 vertices / 36 M arcs on: 6.8 ms against 5.7 on the grid;
@@ -889,7 +884,12 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   a.src = src;
   a.mlp = ctx->d_mlp;
   a.wcc_inv = wcc && G->reordered ? G->d_inv : nullptr;
-  a.xdist = G->d_xdist;
+  // the expansion record pays where a listed vertex is often improved
+  // again within its own step before its expansion (R-MAT s22: a third of
+  // the expansions skipped); on sparse graphs (4096^2 grid, unbucketed
+  // SSSP: no expansion skipped, 15 % slower) it only adds a dependent load,
+  // so graphs of fewer than 8 arcs per vertex run without it
+  a.xdist = G->g.m >= 8ll * G->g.n ? G->d_xdist : nullptr;
   if (a.P.learned && !ctx->d_mlp) return fail(SX_ESTATE, "learned policy without loaded MLP");
   if (algo == ALG_SSSP && a.P.delta == SX_DELTA_AUTO) {
     sx_status s = auto_delta(G, st, &a.P.delta);

@@ -224,7 +224,8 @@ SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   // skipped (R-MAT s22 SSSP: a third of the expansions).  Only the small and
   // medium visitors (one expander per vertex) record and skip; `writer` is
   // the lane whose result the visitor uses.  Only steps with long lists do
-  // (kDedupMinList), on graphs of 8+ arcs per vertex (Params::xrec): the
+  // (kDedupMinList), on graphs of 8+ arcs per vertex (the host passes no
+  // record otherwise): the
   // test puts a dependent load before each row's, which the thousands of
   // short steps of a high-diameter graph would each pay, and sparse graphs
   // re-improve their vertices with new values, not the same one (a record
@@ -232,7 +233,7 @@ SX_PHASE void push_phase(const VGrid &vg, const TravArgs &a, const Params &P, co
   // current one, so it never matches).  The batched kernel
   // compiles it out (kDedup false): its spilling register budget would pay
   // for it in every step.
-  const bool dedup = kDedup && !Ops::kVote && a.xdist && P.xrec && T.nf >= kDedupMinList;
+  const bool dedup = kDedup && !Ops::kVote && a.xdist && T.nf >= kDedupMinList;
   auto fresh = [&](int v, bool writer) -> int {
     if constexpr (Ops::kVote) {
       return v;

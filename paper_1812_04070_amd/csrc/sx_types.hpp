@@ -139,8 +139,6 @@ struct Params {
                                 // with at most this many vertices (0: never)
   unsigned long long ktail_arcs;  // and with their rows (arcs to deleted
                                   // vertices included) at most this long
-  int xrec;                     // SSSP / WCC: consult the expansion record
-                                // (graphs of 8+ arcs per vertex)
   unsigned long long watchdog;  // barrier wait budget (wall-clock ticks)
 };
 
