@@ -98,12 +98,28 @@ SX_DEV void pr_finish_vertex(const PrArgs &a, int v, CSum s, float D, bool last,
   if (od == 0) cadd(dang, r);
 }
 
-// s += src[ii[e]] for e = e0, e0 + stride, ... < end, in that order.  The
-// indices and contributions of kIlp consecutive terms are loaded before any
-// of them is added, so a lane has kIlp gathers in flight instead of one; the
-// additions keep their order, so the sum is the same bits.
+// The contributions of the first kHotPr vertices, copied into LDS by every
+// workgroup at the start of each pull iteration.  After the degree-ordered
+// renumbering they are the highest-degree sources (the first 8,192 of
+// directed R-MAT s24 send 21 % of its arcs), and a gather served by LDS is
+// one request fewer at the L2, whose request rate bounds the pull more than
+// its misses do (s24: 36.3 -> 34.4 ms for 20 iterations, the same bits;
+// 16,384 entries cost a workgroup per CU and gained nothing).
+constexpr int kHotPr = 8192;
+
+// Stage src[0, nhot) into hot (every thread of the workgroup).
+SX_DEV void stage_hot(float *hot, const float *src, int nhot) {
+  for (int i = threadIdx.x; i < nhot; i += kBlock) hot[i] = src[i];
+  __syncthreads();
+}
+
+// s += src[ii[e]] for e = e0, e0 + stride, ... < end, in that order (an
+// index below nhot reads the LDS copy hot instead).  The indices and
+// contributions of kIlp consecutive terms are loaded before any of them is
+// added, so a lane has kIlp gathers in flight instead of one; the additions
+// keep their order, so the sum is the same bits.
 SX_DEV void gather(CSum &s, const float *src, const int *ii, int e0, int end, int stride,
-                   long long &edges) {
+                   long long &edges, const float *hot, int nhot) {
   int e = e0;
   for (; e + (kIlp - 1) * stride < end; e += kIlp * stride) {
     int u[kIlp];
@@ -111,13 +127,14 @@ SX_DEV void gather(CSum &s, const float *src, const int *ii, int e0, int end, in
 #pragma unroll
     for (int r = 0; r < kIlp; ++r) u[r] = ii[e + r * stride];
 #pragma unroll
-    for (int r = 0; r < kIlp; ++r) x[r] = src[u[r]];
+    for (int r = 0; r < kIlp; ++r) x[r] = u[r] < nhot ? hot[u[r]] : src[u[r]];
 #pragma unroll
     for (int r = 0; r < kIlp; ++r) cadd(s, x[r]);
     edges += kIlp;
   }
   for (; e < end; e += stride) {
-    cadd(s, src[ii[e]]);
+    const int u = ii[e];
+    cadd(s, u < nhot ? hot[u] : src[u]);
     ++edges;
   }
 }
@@ -151,9 +168,11 @@ SX_DEV void pr_finish_tracked(const PrArgs &a, int v, CSum s, float D, float *ds
 
 template <bool kTrack>
 SX_DEV void pr_iteration(const PrArgs &a, int t, const ViewRef &L, const Totals &T, LdsPr &lds,
-                         float D, Track &tr) {
+                         float D, Track &tr, float *hot) {
   const Work &w = a.w;
   const float *src = w.contrib[t & 1];
+  const int nhot = a.g.n < kHotPr ? a.g.n : kHotPr;
+  stage_hot(hot, src, nhot);
   float *dst = w.contrib[(t + 1) & 1];
   const bool last = !kTrack && t == a.iters - 1;
   auto finish = [&](int v, CSum s, CSum &dang) {
@@ -170,7 +189,7 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const ViewRef &L, const Totals 
     if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
-    gather(s, src, ii, beg + (int)threadIdx.x, end, kBlock, edges);
+    gather(s, src, ii, beg + (int)threadIdx.x, end, kBlock, edges, hot, nhot);
     s = wg_merge(s, lds.f);
     if (threadIdx.x == 0) finish(v, s, dang);
   }
@@ -182,7 +201,7 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const ViewRef &L, const Totals 
     if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
-    gather(s, src, ii, beg + lane, end, 64, edges);
+    gather(s, src, ii, beg + lane, end, 64, edges, hot, nhot);
     s = wave_merge(s);
     if (lane == 0) finish(v, s, dang);
   }
@@ -192,7 +211,7 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const ViewRef &L, const Totals 
     if ((unsigned)v >= (unsigned)a.g.n) continue;
     const int beg = io[v], end = io[v + 1];
     CSum s{0.f, 0.f};
-    gather(s, src, ii, beg, end, 1, edges);
+    gather(s, src, ii, beg, end, 1, edges, hot, nhot);
     finish(v, s, dang);
   }
   dang = wg_merge(dang, lds.f);
@@ -219,6 +238,7 @@ SX_DEV void pr_iteration(const PrArgs &a, int t, const ViewRef &L, const Totals 
 
 __global__ void __launch_bounds__(kBlock) k_pr_fused(PrArgs a) {
   __shared__ LdsPr lds;
+  __shared__ float hot[kHotPr];
   Ctrl *C = a.w.ctrl;
   const VGrid vg = hw_grid();
   GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]), a.P.watchdog);
@@ -236,7 +256,7 @@ __global__ void __launch_bounds__(kBlock) k_pr_fused(PrArgs a) {
   for (int t = 0; t < a.iters; ++t) {
     const float D = dangling_total(a.w.dang + (size_t)(t & 1) * 2 * kMaxGrid, gridDim.x, lds.f);
     Track none{0.f, 0.f, CSum{0.f, 0.f}};
-    pr_iteration<false>(a, t, L, T, lds, D, none);
+    pr_iteration<false>(a, t, L, T, lds, D, none, hot);
     if (!bar.sync()) return;
   }
   if (vg.bid == 0 && threadIdx.x == 0) {
@@ -411,6 +431,7 @@ enum { PRX_CU = 0, PRX_PULLS = 1, PRX_ENTRIES = 2 };
 // CU: 2.5 against 1.8 ms per iteration at s24).
 __global__ void __launch_bounds__(kBlock) k_pr_conv_pull(PrArgs a) {
   __shared__ LdsPr lds;
+  __shared__ float hot[kHotPr];
   Ctrl *C = a.w.ctrl;
   const VGrid vg = hw_grid();
   GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]), a.P.watchdog);
@@ -434,7 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_pr_conv_pull(PrArgs a) {
     cu = t == 0 ? 0.f : a.P.pr_d * (D - Dprev) * a.inv_n;
     Dprev = D;
     Track tr{cu, 0.f, CSum{0.f, 0.f}, CSum{0.f, 0.f}};
-    pr_iteration<true>(a, t, L, T, lds, D, tr);
+    pr_iteration<true>(a, t, L, T, lds, D, tr, hot);
     if (!bar.sync()) return;
     // the decision tree, evaluated identically by every workgroup
     const CSum ch = partial_sum(a.w.prp, t & 1, 1, 2, lds.f);
