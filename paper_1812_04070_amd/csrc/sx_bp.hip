@@ -43,10 +43,17 @@ SX_DEV float bp_theta(const unsigned *w, long long e) {
   return w ? ((float)((w[e] - 1u) & 63u) - 31.5f) / 31.5f : 1.f;
 }
 
+// (q, deg) of the first kHotBp vertices, copied into LDS by every workgroup
+// at the start of each iteration: after the degree-ordered renumbering they
+// are the highest-degree neighbours, and a gather served by LDS is one
+// request fewer at the L2 (the pull's bound, as for PageRank).
+constexpr int kHotBp = 4096;
+
 // s += atanh(c_uv q_u) over the arcs e = e0, e0 + stride, ... < end of
-// vertex v (degree dv), kIlp arcs in flight per lane, added in order.
+// vertex v (degree dv), kIlp arcs in flight per lane, added in order (an
+// index below nhot reads the LDS copy hot).
 SX_DEV void bp_gather(CSum &s, const BpArgs &a, const float2 *src, float dv, long long e0, long long end,
-                      int stride, long long &edges) {
+                      int stride, long long &edges, const float2 *hot, int nhot) {
   const int *ii = a.g.idx;
   const unsigned *ww = a.g.w;
   long long e = e0;
@@ -60,13 +67,14 @@ SX_DEV void bp_gather(CSum &s, const BpArgs &a, const float2 *src, float dv, lon
       th[r] = bp_theta(ww, e + r * stride);
     }
 #pragma unroll
-    for (int r = 0; r < kIlp; ++r) su[r] = src[u[r]];
+    for (int r = 0; r < kIlp; ++r) su[r] = u[r] < nhot ? hot[u[r]] : src[u[r]];
 #pragma unroll
     for (int r = 0; r < kIlp; ++r) cadd(s, atanhf(a.kappa * th[r] / fmaxf(su[r].y, dv) * su[r].x));
     edges += kIlp;
   }
   for (; e < end; e += stride) {
-    const float2 su = src[ii[e]];
+    const int uu = ii[e];
+    const float2 su = uu < nhot ? hot[uu] : src[uu];
     cadd(s, atanhf(a.kappa * bp_theta(ww, e) / fmaxf(su.y, dv) * su.x));
     ++edges;
   }
@@ -80,8 +88,12 @@ SX_DEV void bp_finish_vertex(const BpArgs &a, int v, CSum s, float dv, bool last
   else dst[v] = make_float2(tanhf(x), dv);
 }
 
-SX_DEV void bp_iteration(const BpArgs &a, int t, const ViewRef &L, const Totals &T, LdsBp &lds) {
+SX_DEV void bp_iteration(const BpArgs &a, int t, const ViewRef &L, const Totals &T, LdsBp &lds,
+                         float2 *hot) {
   const float2 *src = a.w.bpq[t & 1];
+  const int nhot = a.g.n < kHotBp ? a.g.n : kHotBp;
+  for (int i = threadIdx.x; i < nhot; i += kBlock) hot[i] = src[i];
+  __syncthreads();
   float2 *dst = a.w.bpq[(t + 1) & 1];
   const bool last = t == a.iters - 1;
   const int *off = a.g.off;
@@ -94,7 +106,7 @@ SX_DEV void bp_iteration(const BpArgs &a, int t, const ViewRef &L, const Totals 
     const long long beg = off[v], end = off[v + 1];
     const float dv = (float)(end - beg);
     CSum s{0.f, 0.f};
-    bp_gather(s, a, src, dv, beg + threadIdx.x, end, kBlock, edges);
+    bp_gather(s, a, src, dv, beg + threadIdx.x, end, kBlock, edges, hot, nhot);
     s = wg_merge(s, lds.f);
     if (threadIdx.x == 0) bp_finish_vertex(a, v, s, dv, last, dst);
   }
@@ -107,7 +119,7 @@ SX_DEV void bp_iteration(const BpArgs &a, int t, const ViewRef &L, const Totals 
     const long long beg = off[v], end = off[v + 1];
     const float dv = (float)(end - beg);
     CSum s{0.f, 0.f};
-    bp_gather(s, a, src, dv, beg + lane, end, 64, edges);
+    bp_gather(s, a, src, dv, beg + lane, end, 64, edges, hot, nhot);
     s = wave_merge(s);
     if (lane == 0) bp_finish_vertex(a, v, s, dv, last, dst);
   }
@@ -118,7 +130,7 @@ SX_DEV void bp_iteration(const BpArgs &a, int t, const ViewRef &L, const Totals 
     const long long beg = off[v], end = off[v + 1];
     const float dv = (float)(end - beg);
     CSum s{0.f, 0.f};
-    bp_gather(s, a, src, dv, beg, end, 1, edges);
+    bp_gather(s, a, src, dv, beg, end, 1, edges, hot, nhot);
     bp_finish_vertex(a, v, s, dv, last, dst);
   }
   add_stats(a.w.ctrl, blockIdx.x, edges, 0ull, lds.red);
@@ -126,6 +138,7 @@ SX_DEV void bp_iteration(const BpArgs &a, int t, const ViewRef &L, const Totals 
 
 __global__ void __launch_bounds__(kBlock) k_bp_fused(BpArgs a) {
   __shared__ LdsBp lds;
+  __shared__ float2 hot[kHotBp];
   Ctrl *C = a.w.ctrl;
   const VGrid vg = hw_grid();
   GridBarrier bar(C, load_relaxed(&C->bar_gen.v[0]), a.P.watchdog);
@@ -147,7 +160,7 @@ __global__ void __launch_bounds__(kBlock) k_bp_fused(BpArgs a) {
     return;
   }
   for (int t = 0; t < a.iters; ++t) {
-    bp_iteration(a, t, L, T, lds);
+    bp_iteration(a, t, L, T, lds, hot);
     if (!bar.sync()) return;
   }
   if (vg.bid == 0 && threadIdx.x == 0) {
