@@ -282,3 +282,56 @@ def test_kcore_multigraph(engine):
         announce(f"kcore multigraph kcore_tail={tail}")
         c, _ = run(engine, mg, sx.SX_KCORE, -1, sx.Policy(kcore_tail=tail))
         np.testing.assert_array_equal(c, ref)
+
+
+@pytest.mark.skip(reason="level scans that peel their own finds were removed: the build that carried "
+                         "them gave wrong core numbers (one level low) on the plain ballot arm of R-MAT "
+                         "s20, which does not take that path, and one run did not end; the cause was not "
+                         "found, and the policy field kcore_scan_peel this test sets no longer exists")
+@pytest.mark.parametrize("case", ["rmat16", "rmat18", "rmat16d", "grid-150", "er-20000", "star-3000",
+                                  "rmat12-doubled"])
+def test_kcore_scan_peel(engine, case):
+    """Level scans that delete their own finds in the same launch (the
+    default) against scans that only list them: the grid peels every level
+    (no tail), with the default bins, push only, a one-entry online list (the
+    next step's list overflows and a plain scan recovers it), eight
+    workgroups (finds overflow a workgroup's queue and arc budget), and the
+    fixed-k membership; every result equal to the oracle's."""
+    import dataclasses as dc
+    if case == "rmat12-doubled":
+        g0 = gen.rmat(12, seed=41)
+        g = dc.replace(g0, offsets=(2 * g0.offsets).astype(np.int32),
+                       indices=np.repeat(g0.indices, 2).astype(np.int32), name=case)
+    else:
+        g = {"rmat16": lambda: gen.rmat(16, seed=51), "rmat18": lambda: gen.rmat(18, seed=52),
+             "rmat16d": lambda: gen.rmat(16, seed=53, directed=True),
+             "grid-150": lambda: gen.grid(150, 0.1, seed=54),
+             "er-20000": lambda: gen.random_graph(20000, 0.0008, seed=55),
+             "star-3000": lambda: gen.from_edges(3001, [(0, i) for i in range(1, 3001)])}[case]()
+    ref = oracle.kcore_g(g)
+    dg = engine.load(g)
+    try:
+        _scan_peel_arms(engine, g, dg, ref, case)
+    finally:
+        dg.close()
+
+
+def _scan_peel_arms(engine, g, dg, ref, case):
+    import dataclasses as dc
+    launches = {}
+    for sp in (0, -1):
+        for name, pol in [("auto", sx.Policy()), ("push", sx.Policy(direction=sx.SX_DIR_PUSH)),
+                          ("tiny-online", sx.Policy(bin_small=4, bin_large=8, online_cap=1)),
+                          ("grid-8", sx.Policy(grid_wgs=8))]:
+            pol = dc.replace(pol, kcore_tail=-1, kcore_scan_peel=sp)
+            announce(f"kcore scan-peel {case} {name} scan_peel={sp}")
+            c, st = run(engine, g, sx.SX_KCORE, -1, pol, dg=dg)
+            np.testing.assert_array_equal(c, ref)
+            launches[(name, sp)] = st["launches"]
+        for k in (2, int(ref.max())):
+            announce(f"kcore scan-peel {case} member k={k} scan_peel={sp}")
+            out, _ = engine.run(dg, sx.SX_KCORE, -1, sx.Policy(kcore_scan_peel=sp), kcore_k=k)
+            np.testing.assert_array_equal(engine.to_host(dg, sx.SX_KCORE, out), oracle.kcore_member_g(g, k))
+    print(f"[scan-peel] {case} launches (on, off): "
+          + ", ".join(f"{n} {launches[(n, 0)]}/{launches[(n, -1)]}" for n in ("auto", "push", "tiny-online", "grid-8")),
+          flush=True)
