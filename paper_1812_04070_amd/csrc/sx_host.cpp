@@ -44,6 +44,11 @@ static sx_status fail(sx_status s, const char *fmt, ...) {
                   __LINE__);                                                                \
   } while (0)
 
+// Launches enqueued beyond the last run's count in the first batch of a
+// sequenced traversal (the count can differ by one or two between runs:
+// the order of atomic updates changes SSSP's intermediate lists)
+static constexpr int kSeqHintMargin = 2;
+
 // Workspace of sx_run_static, for callers that cannot allocate device
 // memory: one array per device, held until the process ends.  Host code
 // never passes the array's name to a kernel (it is a host-side stand-in):
@@ -110,6 +115,10 @@ struct sx_graph {
   // where the lists of the next iteration sit after sx_run_iterations:
   // record slot, region parity, run grid (-1: no such run yet)
   int next_slot = -1, next_parity = 0, next_grid = 0;
+  // launches the last sequenced BFS / SSSP / WCC run on this graph needed
+  // (0: none yet): the next run enqueues that many plus kSeqHintMargin in its
+  // first batch instead of 16, so few launches run after the end
+  int seq_hint[3] = {0, 0, 0};
 };
 
 struct sx_program {
@@ -911,10 +920,17 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   HostPolicyLog plog;
   if (sequenced) {
     HIP_TRY(seq_start(G->w.ctrl, pull_first, wcc, st));
+    // a launch after the run's end returns at once but still costs ~5 us (768
+    // workgroups of the wide kernel): size the first batch by the last run of
+    // this algorithm on this graph (another source: a different count; too
+    // few launches only cost one host round trip before the next batch)
+    int &hint = G->seq_hint[algo];
+    const int first = hint > 0 ? std::min(hint + kSeqHintMargin, 64) : 16;
     sx_status s = seq_drive(
-        G, st, 16, 64, (unsigned)(8 * (long long)G->g.n + 1024),
+        G, st, first, 64, (unsigned)(8 * (long long)G->g.n + 1024),
         [&](unsigned L) { return trav_launch(seq_kind, algo, a, (int)L, 0, grid, st); }, launches, &fin);
     if (s != SX_OK) return s;
+    hint = (int)fin->stats.v[12];
     HIP_TRY(hipEventRecord(G->ev1, st));
   } else if (fused) {
     if (wcc && !pull_first) {

@@ -947,7 +947,12 @@ SX_DEV bool seq_body(const TravArgs &a, unsigned L, LdsTrav &lds, LdsPolicy &pol
     Decision d = decide<Ops>(a, s, pulling != 0, T, &pol, vg.bid == 0, true);
     if (d.done) {
       ++s.it;
-      if (lead) seq_store(out, s.it >= a.P.max_iters ? SEQ_LIMIT : SEQ_DONE, s, pulling, 0, 0);
+      if (lead) {
+        seq_store(out, s.it >= a.P.max_iters ? SEQ_LIMIT : SEQ_DONE, s, pulling, 0, 0);
+        // the run needed launches 0..L: the host sizes the next run's first
+        // batch of launches on this graph by it
+        store_relaxed(&C->stats.v[12], L + 1u);
+      }
       return true;
     }
     // delta-stepping: once no listed vertex lies below the bound, move it to
