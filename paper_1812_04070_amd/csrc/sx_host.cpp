@@ -930,6 +930,7 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
         G, st, first, 64, (unsigned)(8 * (long long)G->g.n + 1024),
         [&](unsigned L) { return trav_launch(seq_kind, algo, a, (int)L, 0, grid, st); }, launches, &fin);
     if (s != SX_OK) return s;
+    // Ctrl::stats word 12: the index + 1 of the launch that ended the run
     hint = (int)fin->stats.v[12];
     HIP_TRY(hipEventRecord(G->ev1, st));
   } else if (fused) {

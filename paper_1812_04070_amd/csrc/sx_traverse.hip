@@ -950,7 +950,8 @@ SX_DEV bool seq_body(const TravArgs &a, unsigned L, LdsTrav &lds, LdsPolicy &pol
       if (lead) {
         seq_store(out, s.it >= a.P.max_iters ? SEQ_LIMIT : SEQ_DONE, s, pulling, 0, 0);
         // the run needed launches 0..L: the host sizes the next run's first
-        // batch of launches on this graph by it
+        // batch of launches on this graph by it (Ctrl::stats word 12, unused
+        // by the other programs; k_trav_init clears it)
         store_relaxed(&C->stats.v[12], L + 1u);
       }
       return true;

@@ -62,8 +62,7 @@ struct Ctrl {
   Line error;                   // SX_ERR_*
   Line state;                   // run state of the fused kernels
   Line stats;                   // u32 [4] ballot scans, [5] pull iterations,
-                                // [6] iterations, [12] launches a sequenced
-                                // traversal used; u64 [8] k-core scan entries
+                                // [6] iterations; u64 [8] k-core scan entries
   Line aux;                     // algorithm scratch
   Line pol;                     // learned policy: [0] network evaluations,
                                 // [1..8] features and [9..12] outputs of the
