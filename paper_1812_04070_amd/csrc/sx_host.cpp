@@ -914,12 +914,13 @@ static sx_status run_traversal(sx_program *p, sx_graph *G, int src, void *d_out,
   int launches = 0;
   HIP_TRY(hipEventRecord(G->ev0, st));
   // unexplored arcs (BFS direction rule) are computed on the device
-  HIP_TRY(trav_init(a, algo, 0ull, grid, st, pull_first));
+  // (with the first state of a sequenced run: one launch less, and the host
+  // enqueues the first phases while the set-up runs)
+  HIP_TRY(trav_init(a, algo, 0ull, grid, st, pull_first, sequenced));
   ++launches;
   const Ctrl *fin = G->h_ctrl;
   HostPolicyLog plog;
   if (sequenced) {
-    HIP_TRY(seq_start(G->w.ctrl, pull_first, wcc, st));
     // a launch after the run's end returns at once but still costs ~5 us (768
     // workgroups of the wide kernel): size the first batch by the last run of
     // this algorithm on this graph (another source: a different count; too

@@ -19,11 +19,11 @@ enum TravAlgo { ALG_BFS = 0, ALG_SSSP = 1, ALG_WCC = 2 };
 const void *trav_kernel(int kind, int algo);
 hipError_t trav_launch(int kind, int algo, const TravArgs &a, int it, int arg, int grid,
                        hipStream_t s);
-// pull_first: the run's first iteration pulls (read by the persistent kernels)
+// pull_first: the run's first iteration pulls (read by the persistent
+// kernels); sequenced: also write the first state of a sequenced run
 hipError_t trav_init(const TravArgs &a, int algo, unsigned long long mu0, int run_grid,
-                     hipStream_t s, bool pull_first = false);
+                     hipStream_t s, bool pull_first = false, bool sequenced = false);
 hipError_t batch_launch(const BatchArgs &b, int grid, hipStream_t s);
-hipError_t seq_start(Ctrl *c, bool pull_first, bool all_active, hipStream_t s);
 hipError_t weight_sum(const unsigned *w, long long m, unsigned long long *out, hipStream_t s);
 // phases of the sequenced mode (Ctrl::seq[..].v[0])
 enum : unsigned { SEQ_DONE = 6, SEQ_ERROR = 7, SEQ_LIMIT = 8 };

@@ -1031,20 +1031,20 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMi
   if (seq_body<Ops>(a, L, lds, pol)) seq_stall_leave(a.w.ctrl, blockIdx.x);
 }
 
-// first state of a sequenced run (after k_trav_init).  all_active: every
-// vertex is active in iteration 0 (WCC), so a push start first builds the
-// lists of iteration 0 by a ballot scan (iteration -1's next lists).
-__global__ void k_seq_start(Ctrl *C, unsigned pull_first, unsigned all_active) {
-  if (threadIdx.x == 0) {
-    Line &l = C->seq[0];
-    for (int i = 0; i < 32; ++i) l.v[i] = 0u;
-    l.v[0] = pull_first ? PH_PULL_SCAN : (all_active ? PH_BALLOT : PH_PUSH);
-    if (!pull_first && all_active) l.v[1] = 0xFFFFFFFFu;
-    l.v[10] = pull_first;
-    *(unsigned long long *)&l.v[2] = *(unsigned long long *)&C->state.v[6];
-    // delta-stepping: smallest distance set by each step (three rotating words)
-    for (int i = 0; i < 3; ++i) C->aux.v[i] = 0xFFFFFFFFu;
-  }
+// First state of a sequenced run, written by k_trav_init's first thread
+// after the run state (one thread; nothing reads it before the first k_seq).
+// all_active: every vertex is active in iteration 0 (WCC), so a push start
+// first builds the lists of iteration 0 by a ballot scan (iteration -1's next
+// lists).
+SX_DEV void seq_first_state(Ctrl *C, unsigned pull_first, unsigned all_active) {
+  Line &l = C->seq[0];
+  for (int i = 0; i < 32; ++i) l.v[i] = 0u;
+  l.v[0] = pull_first ? PH_PULL_SCAN : (all_active ? PH_BALLOT : PH_PUSH);
+  if (!pull_first && all_active) l.v[1] = 0xFFFFFFFFu;
+  l.v[10] = pull_first;
+  *(unsigned long long *)&l.v[2] = *(unsigned long long *)&C->state.v[6];
+  // delta-stepping: smallest distance set by each step (three rotating words)
+  for (int i = 0; i < 3; ++i) C->aux.v[i] = 0xFFFFFFFFu;
 }
 
 // ------------------------------------------------------------ set-up ---
@@ -1101,7 +1101,7 @@ SX_DEV void init_source(const TravArgs &a, unsigned G) {
 // persistent and one-phase arrangements are told so by state word 2).
 // Launched with any grid of at least 2 workgroups; G = the run's grid.
 __global__ void k_trav_init(TravArgs a, int algo, unsigned long long mu0, unsigned G,
-                            unsigned pull_first) {
+                            unsigned pull_first, unsigned sequenced) {
   const bool wcc = algo == ALG_WCC;
   init_state(hw_grid(), a, algo == ALG_SSSP, wcc);
   Ctrl *C = a.w.ctrl;
@@ -1115,6 +1115,7 @@ __global__ void k_trav_init(TravArgs a, int algo, unsigned long long mu0, unsign
           wcc ? 0ull : (mu0 ? mu0 : (unsigned long long)(a.g.m - degree_of(a.g.off, a.src)));
       if (wcc) C->state.v[2] = 1u;
       C->state.v[3] = pull_first;
+      if (sequenced) seq_first_state(C, pull_first, wcc ? 1u : 0u);
     }
     if (!wcc) init_source(a, G);
   }
@@ -1286,12 +1287,12 @@ hipError_t trav_launch(int kind, int algo, const TravArgs &a, int it, int arg, i
 }
 
 hipError_t trav_init(const TravArgs &a, int algo, unsigned long long mu0, int run_grid,
-                     hipStream_t s, bool pull_first) {
+                     hipStream_t s, bool pull_first, bool sequenced) {
   int grid = (a.g.n + kBlock - 1) / kBlock;
   if (grid < 2) grid = 2;
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(k_trav_init, dim3(grid), dim3(kBlock), 0, s, a, algo, mu0, (unsigned)run_grid,
-                     pull_first ? 1u : 0u);
+                     pull_first ? 1u : 0u, sequenced ? 1u : 0u);
   return hipGetLastError();
 }
 
@@ -1314,12 +1315,6 @@ hipError_t weight_sum(const unsigned *w, long long m, unsigned long long *out, h
   long long grid = (m + 255) / 256;
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(k_weight_sum, dim3((unsigned)grid), dim3(256), 0, s, w, m, out);
-  return hipGetLastError();
-}
-
-hipError_t seq_start(Ctrl *c, bool pull_first, bool all_active, hipStream_t s) {
-  hipLaunchKernelGGL(k_seq_start, dim3(1), dim3(64), 0, s, c, pull_first ? 1u : 0u,
-                     all_active ? 1u : 0u);
   return hipGetLastError();
 }
 
