@@ -207,8 +207,10 @@ void sx_program_destroy(sx_program *p);
  *             the host deciding between launches) | SX_SEQUENCED (one launch
  *             per phase, decisions taken on the device at the start of the
  *             next launch, launches enqueued ahead: the kernel boundary is
- *             the global barrier) | 0 = auto (sequenced for BFS, SSSP and
- *             k-core, fused for PageRank)
+ *             the global barrier; a BFS / SSSP / WCC run enqueues first as
+ *             many launches as the previous run of that algorithm on the
+ *             same sx_graph needed, plus two, else 16) | 0 = auto
+ *             (sequenced for BFS, SSSP and k-core, fused for PageRank)
  *  policy     SX_POLICY_HEURISTIC | SX_POLICY_LEARNED (MLP; needs
  *             sx_policy_load_mlp first)                                       */
 enum { SX_DIR_AUTO = 0, SX_DIR_PUSH = 1, SX_DIR_PULL = 2 };
@@ -245,7 +247,9 @@ sx_status sx_program_set_policy(sx_program *p, const sx_policy *pol);
 /* ---------------------------------------------------------------- run --- */
 typedef struct {
   int32_t iterations;        /* BSP iterations (levels / rounds / sweeps)     */
-  int32_t launches;          /* kernel launches issued for the run            */
+  int32_t launches;          /* kernel launches issued for the run (sequenced:
+                                also those enqueued ahead that found the run
+                                over and returned at once)                    */
   int32_t pull_iters;        /* iterations processed in pull direction        */
   int32_t ballot_iters;      /* iterations whose worklist came from the ballot
                                 filter                                         */
